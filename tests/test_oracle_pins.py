@@ -1,0 +1,500 @@
+"""Pins for the CPU oracle: checks against things other than the oracle itself.
+
+The paper prints no worked numerical example, so the oracle (section 3.1,
+Fig. FW-Alg) is pinned by what mathematics fixes:
+
+* brute-force enumeration of all simple paths on tiny graphs (distances,
+  k-restricted distances d^(k) of section 3.1, canonical predecessors);
+* closed forms (empty, complete, directed cycle, path, bidirectional grid);
+* library routines (scipy's Floyd-Warshall, Dijkstra and Johnson);
+* invariants (zero diagonal, d <= w, triangle inequality, idempotence,
+  Johnson's potential identity, path reconstruction);
+* a hand-derived fixture under tests/golden/;
+* mutants of the Floyd-Warshall loop (planted on the CPU, in a Python copy)
+  that each of the pins above must reject.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1001_4108_amd import gen
+
+I32_INF = gen.I32_INF
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# brute force
+# ---------------------------------------------------------------------------
+
+def _edges(W):
+    n = W.shape[0]
+    inf = np.inf if W.dtype == np.float32 else I32_INF
+    return {(p, q): int(W[p, q]) for p in range(n) for q in range(n)
+            if p != q and W[p, q] != inf}
+
+
+def brute_force(W, allowed_mid=None):
+    """Exact shortest simple-path lengths and canonical last hops by enumeration.
+
+    Returns (dist, last) with dist[i][j] = None when unreachable, and
+    last[i][j] = smallest last hop over all shortest i->j paths (-1 for i == j
+    or unreachable).  ``allowed_mid`` restricts intermediate vertices.
+    """
+    n = W.shape[0]
+    E = _edges(W)
+    adj = {p: [q for q in range(n) if (p, q) in E] for p in range(n)}
+    dist = [[None] * n for _ in range(n)]
+    last = [[-1] * n for _ in range(n)]
+    for i in range(n):
+        dist[i][i] = 0
+
+        def dfs(u, total, visited, prev):
+            if u != i:
+                if dist[i][u] is None or total < dist[i][u]:
+                    dist[i][u] = total
+                    last[i][u] = prev
+                elif total == dist[i][u] and prev < last[i][u]:
+                    last[i][u] = prev
+                if allowed_mid is not None and u not in allowed_mid:
+                    return  # u may end a path but not be passed through
+            for v in adj[u]:
+                if v not in visited:
+                    visited.add(v)
+                    dfs(v, total + E[(u, v)], visited, u)
+                    visited.discard(v)
+
+        dfs(i, 0, {i}, -1)
+    return dist, last
+
+
+def random_tiny(n, p, lo, hi, rng, dtype=np.float32, neg=False):
+    seed = int(rng.integers(0, 2**31))
+    if neg:
+        return gen.reweighted_graph(n, p, lo, hi, -5, 5, seed).w
+    return gen.dense_graph(n, p, lo, hi, seed, dtype=dtype)
+
+
+def check_against_brute(D, W):
+    dist, _ = brute_force(W)
+    n = W.shape[0]
+    for i in range(n):
+        for j in range(n):
+            if dist[i][j] is None:
+                if W.dtype == np.float32:
+                    assert np.isinf(D[i, j]) and D[i, j] > 0, (i, j)
+                else:
+                    assert D[i, j] > I32_INF // 2, (i, j)
+            else:
+                assert D[i, j] == dist[i][j], (i, j, D[i, j], dist[i][j])
+
+
+# ---------------------------------------------------------------------------
+# distances
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(40))
+def test_fw_f32_matches_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 8))
+    W = random_tiny(n, float(rng.uniform(0.1, 0.9)), 1, 9, rng)
+    check_against_brute(oracle.fw(W, nthreads=1), W)
+    check_against_brute(oracle.fw(W), W)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_fw_i32_negative_edges_matches_brute_force(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(2, 8))
+    W = random_tiny(n, float(rng.uniform(0.2, 0.9)), 1, 9, rng, neg=True)
+    check_against_brute(oracle.fw(W), W)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_fw_k_prefix_is_restricted_distance(seed):
+    """After iterations k < K the matrix holds d^(K): shortest paths whose
+    intermediate vertices all lie in {0..K-1} (section 3.1)."""
+    rng = np.random.default_rng(2000 + seed)
+    n = int(rng.integers(3, 8))
+    W = random_tiny(n, 0.5, 1, 9, rng)
+    K = int(rng.integers(0, n + 1))
+    D = oracle.fw(W, k_end=K)
+    dist, _ = brute_force(W, allowed_mid=set(range(K)))
+    for i in range(n):
+        for j in range(n):
+            ref = dist[i][j]
+            if ref is None:
+                assert np.isinf(D[i, j])
+            else:
+                assert D[i, j] == ref
+
+
+def test_fw_closed_forms():
+    n = 37
+    # empty graph: +INF off the diagonal, 0 on it
+    W = np.full((n, n), np.inf, np.float32)
+    np.fill_diagonal(W, 0)
+    assert np.array_equal(oracle.fw(W), W)
+    # complete graph with weight c: d_ij = c
+    c = 7.0
+    W = np.full((n, n), c, np.float32)
+    np.fill_diagonal(W, 0)
+    assert np.array_equal(oracle.fw(W), W)
+    # directed n-cycle i -> i+1 of weight c: d_ij = ((j - i) mod n) * c
+    W = np.full((n, n), np.inf, np.float32)
+    np.fill_diagonal(W, 0)
+    for i in range(n):
+        W[i, (i + 1) % n] = c
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    assert np.array_equal(oracle.fw(W), (((j - i) % n) * c).astype(np.float32))
+    # path 0 -> 1 -> ... -> n-1 with weights 1..n-1: prefix sums forward, INF back
+    wts = np.arange(1, n, dtype=np.int64)
+    W = np.full((n, n), np.inf, np.float32)
+    np.fill_diagonal(W, 0)
+    W[np.arange(n - 1), np.arange(1, n)] = wts
+    pref = np.concatenate([[0], np.cumsum(wts)])
+    ref = np.where(j >= i, (pref[j] - pref[i]).astype(np.float32), np.float32(np.inf))
+    assert np.array_equal(oracle.fw(W), ref)
+    # bidirectional unit grid r x c: Manhattan distance
+    R, C = 5, 7
+    n = R * C
+    W = np.full((n, n), np.inf, np.float32)
+    np.fill_diagonal(W, 0)
+    for r in range(R):
+        for q in range(C):
+            u = r * C + q
+            if q + 1 < C:
+                W[u, u + 1] = W[u + 1, u] = 1
+            if r + 1 < R:
+                W[u, u + C] = W[u + C, u] = 1
+    rr, qq = np.divmod(np.arange(n), C)
+    ref = (np.abs(rr[:, None] - rr[None, :]) + np.abs(qq[:, None] - qq[None, :])).astype(np.float32)
+    assert np.array_equal(oracle.fw(W), ref)
+
+
+def test_fw_int32_closed_forms_and_sentinel():
+    n = 33
+    W = np.full((n, n), I32_INF, np.int32)
+    np.fill_diagonal(W, 0)
+    assert np.array_equal(oracle.fw(W), W)  # M + M never beats M
+    for i in range(n):
+        W[i, (i + 1) % n] = 3
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    assert np.array_equal(oracle.fw(W), ((j - i) % n * 3).astype(np.int32))
+
+
+def _scipy_input(W):
+    """csgraph dense input: 0 = no edge, so only valid when no weight is 0."""
+    inf = np.inf if W.dtype == np.float32 else I32_INF
+    X = np.where(W == inf, 0, W).astype(np.float64)
+    np.fill_diagonal(X, 0)
+    return X
+
+
+@pytest.mark.parametrize("n,p", [(1, 0.5), (2, 0.5), (50, 0.05), (131, 0.2), (257, 0.5)])
+def test_fw_matches_scipy(n, p):
+    from scipy.sparse import csgraph
+    W = gen.dense_graph(n, p, 1, 1000, seed=n)
+    D = oracle.fw(W)
+    ref = csgraph.floyd_warshall(_scipy_input(W), directed=True)
+    assert np.array_equal(D.astype(np.float64), ref)
+    ref2 = csgraph.dijkstra(_scipy_input(W), directed=True)
+    assert np.array_equal(D.astype(np.float64), ref2)
+
+
+@pytest.mark.parametrize("n", [5, 64, 200])
+def test_fw_i32_negative_matches_scipy_johnson(n):
+    from scipy.sparse import csgraph
+    g = gen.reweighted_graph(n, 0.3, 1, 1000, -500, 500, seed=7 * n)
+    X = np.where(g.w == I32_INF, 0, g.w).astype(np.float64)
+    np.fill_diagonal(X, 0)
+    # csgraph treats explicit zeros as absent; a reweighted edge can be 0, so
+    # feed it a sparse matrix that keeps explicit zero-weight edges.
+    from scipy.sparse import csr_matrix
+    rows, cols = np.nonzero((g.w != I32_INF) & ~np.eye(n, dtype=bool))
+    S = csr_matrix((g.w[rows, cols].astype(np.float64), (rows, cols)), shape=(n, n))
+    ref = csgraph.johnson(S, directed=True)
+    D = oracle.fw(g.w)
+    reach = np.isfinite(ref)
+    assert np.array_equal(D[reach].astype(np.float64), ref[reach])
+    assert (D[~reach] > I32_INF // 2).all()
+
+
+def test_johnson_identity_on_reweighted_graph():
+    """d'(u,v) = d(u,v) + pot(u) - pot(v) for the reweighted graph."""
+    g = gen.reweighted_graph(150, 0.2, 1, 1000, -500, 500, seed=11)
+    D = oracle.fw(g.w).astype(np.int64)
+    Db = oracle.fw(g.base).astype(np.int64)
+    reach = Db < I32_INF
+    ident = Db + g.pot[:, None] - g.pot[None, :]
+    assert np.array_equal(D[reach], ident[reach])
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.int32])
+def test_fw_invariants(dtype):
+    n = 180
+    W = gen.dense_graph(n, 0.1, 1, 50, seed=3, dtype=dtype)
+    D = oracle.fw(W)
+    assert (np.diag(D) == 0).all()
+    assert (D <= W).all()
+    # triangle inequality for every (i, k, j), in the matrix's own arithmetic
+    for k in range(n):
+        s = D[:, k:k + 1] + D[k:k + 1, :]  # int32: no overflow (values <= M)
+        assert (D <= s).all()
+    # idempotence: a second sweep changes no bit
+    assert np.array_equal(oracle.fw(D), D)
+
+
+def test_fw_threads_do_not_change_result():
+    W = gen.dense_graph(300, 0.05, 1, 100, seed=9)
+    assert np.array_equal(oracle.fw(W, nthreads=1), oracle.fw(W, nthreads=0))
+
+
+def test_fw_respects_leading_dimension():
+    n, ld = 40, 53
+    W = gen.dense_graph(n, 0.3, 1, 20, seed=5)
+    buf = np.full((n, ld), -123.0, np.float32)
+    buf[:, :n] = W
+    oracle.fw_inplace(buf[:, :n])
+    assert np.array_equal(buf[:, :n], oracle.fw(W))
+    assert (buf[:, n:] == -123.0).all()
+
+
+def test_fw_negative_cycle_runs_serial_loop():
+    """With a negative cycle the routine is the literal serial triple loop."""
+    W = np.array([[0, 1, np.inf], [np.inf, 0, -3], [1, np.inf, 0]], np.float32)
+    ref = W.copy()
+    n = 3
+    for k in range(n):
+        for i in range(n):
+            for j in range(n):
+                s = np.float32(ref[i, k] + ref[k, j])
+                if s < ref[i, j]:
+                    ref[i, j] = s
+    assert np.array_equal(oracle.fw(W), ref)
+    assert (np.diag(ref) < 0).any()
+
+
+# ---------------------------------------------------------------------------
+# predecessors
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(40))
+def test_canonical_pred_matches_brute_force(seed):
+    rng = np.random.default_rng(3000 + seed)
+    n = int(rng.integers(1, 8))
+    neg = bool(seed % 2)
+    if neg and n >= 2:
+        W = random_tiny(n, float(rng.uniform(0.2, 0.9)), 1, 3, rng, neg=True)
+    else:
+        W = random_tiny(n, float(rng.uniform(0.2, 0.9)), 1, 3, rng)  # dense ties
+    D = oracle.fw(W)
+    P = oracle.canonical_pred(D, W)
+    _, last = brute_force(W)
+    assert P.tolist() == last
+
+
+def test_canonical_pred_closed_forms():
+    n = 23
+    W = np.full((n, n), np.inf, np.float32)
+    np.fill_diagonal(W, 0)
+    for i in range(n):
+        W[i, (i + 1) % n] = 2
+    P = oracle.canonical_pred(oracle.fw(W), W)
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ref = np.where(i == j, -1, (j - 1) % n)
+    assert np.array_equal(P, ref)
+    # complete graph with equal weights: the direct edge is the only shortest path
+    W = np.full((n, n), 5, np.int32)
+    np.fill_diagonal(W, 0)
+    P = oracle.canonical_pred(oracle.fw(W), W)
+    assert np.array_equal(P, np.where(i == j, -1, i))
+
+
+def _walk(P, i, j):
+    path = [j]
+    while path[-1] != i:
+        path.append(int(P[i, path[-1]]))
+        assert len(path) <= P.shape[0]
+    return path[::-1]
+
+
+@pytest.mark.parametrize("dtype,neg", [(np.float32, False), (np.int32, True)])
+def test_pred_reconstructs_shortest_paths(dtype, neg):
+    n = 90
+    if neg:
+        W = gen.reweighted_graph(n, 0.1, 1, 100, -50, 50, seed=21).w
+    else:
+        W = gen.dense_graph(n, 0.05, 1, 10, seed=21)
+    D = oracle.fw(W)
+    P = oracle.canonical_pred(D, W)
+    for i in range(n):
+        reach = oracle.reach_row(W, i)
+        for j in range(n):
+            if i == j or not reach[j]:
+                assert P[i, j] == -1
+                continue
+            path = _walk(P, i, j)
+            total = sum(int(W[a, b]) for a, b in zip(path, path[1:]))
+            assert total == int(D[i, j])
+
+
+def test_canonical_pred_rows_subset_matches_full():
+    W = gen.reweighted_graph(120, 0.15, 1, 100, -50, 50, seed=5).w
+    D = oracle.fw(W)
+    P = oracle.canonical_pred(D, W)
+    rows = np.array([0, 7, 119, 64])
+    assert np.array_equal(oracle.canonical_pred(D[rows], W, rows=rows), P[rows])
+
+
+# ---------------------------------------------------------------------------
+# Dijkstra and reachability
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(20))
+def test_dijkstra_matches_brute_force(seed):
+    rng = np.random.default_rng(4000 + seed)
+    n = int(rng.integers(1, 8))
+    W = random_tiny(n, 0.5, 1, 9, rng)
+    dist, _ = brute_force(W)
+    out = oracle.dijkstra_rows(W, np.arange(n))
+    for i in range(n):
+        for j in range(n):
+            ref = np.inf if dist[i][j] is None else dist[i][j]
+            assert out[i, j] == ref
+
+
+def test_dijkstra_matches_scipy_and_rejects_negative():
+    from scipy.sparse import csgraph
+    W = gen.dense_graph(400, 0.02, 1, 1000, seed=17)
+    srcs = np.array([0, 3, 399, 200])
+    ref = csgraph.dijkstra(_scipy_input(W), directed=True, indices=srcs)
+    assert np.array_equal(oracle.dijkstra_rows(W, srcs), ref)
+    neg = gen.reweighted_graph(20, 0.5, 1, 10, -5, 5, seed=1).w
+    with pytest.raises(ValueError):
+        oracle.dijkstra_rows(neg, [0])
+
+
+def test_reach_row_matches_scipy():
+    from scipy.sparse import csgraph
+    W = gen.dense_graph(300, 0.004, 1, 10, seed=23)
+    ref = np.isfinite(csgraph.dijkstra(_scipy_input(W), directed=True, indices=[5]))[0]
+    assert np.array_equal(oracle.reach_row(W, 5), ref)
+
+
+# ---------------------------------------------------------------------------
+# hand-derived fixture
+# ---------------------------------------------------------------------------
+
+def _read_blocks(path):
+    blocks, cur, name = {}, [], None
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if not line:
+            continue
+        if line.startswith("[") and line.endswith("]"):
+            if name:
+                blocks[name] = cur
+            name, cur = line[1:-1], []
+        else:
+            cur.append(line.split())
+    blocks[name] = cur
+    return blocks
+
+
+def test_golden_hand_derived_example():
+    b = _read_blocks(os.path.join(GOLDEN, "tiny6_hand.txt"))
+    W = np.array([[np.inf if x == "inf" else float(x) for x in r] for r in b["weights"]],
+                 np.float32)
+    Dref = np.array([[np.inf if x == "inf" else float(x) for x in r] for r in b["distances"]],
+                    np.float32)
+    Pref = np.array([[int(x) for x in r] for r in b["predecessors"]], np.int32)
+    D = oracle.fw(W)
+    assert np.array_equal(D, Dref)
+    assert np.array_equal(oracle.canonical_pred(D, W), Pref)
+    Wi = np.full(W.shape, I32_INF, np.int32)
+    Wi[np.isfinite(W)] = W[np.isfinite(W)].astype(np.int32)
+    Di = oracle.fw(Wi)
+    assert np.array_equal(np.where(Di >= I32_INF, np.inf, Di).astype(np.float32), Dref)
+
+
+# ---------------------------------------------------------------------------
+# planted mistakes: each must be rejected by the pins above
+# ---------------------------------------------------------------------------
+
+def _fw_variant(W, kind):
+    D = W.astype(np.float64).copy()
+    n = D.shape[0]
+    rng = range(n)
+    if kind == "k_innermost":
+        for i in rng:
+            for j in rng:
+                for k in rng:
+                    D[i, j] = min(D[i, j], D[i, k] + D[k, j])
+        return D
+    ks = range(n - 1) if kind == "k_short" else rng
+    for k in ks:
+        for i in rng:
+            for j in rng:
+                if kind == "transposed":
+                    s = D[k, i] + D[j, k]
+                elif kind == "no_min":
+                    s = D[i, k] + D[k, j]
+                    D[i, j] = s if np.isfinite(s) else D[i, j]
+                    continue
+                elif kind == "wrong_index":
+                    s = D[i, k] + D[i, j]
+                else:
+                    s = D[i, k] + D[k, j]
+                D[i, j] = min(D[i, j], s)
+    return D
+
+
+@pytest.mark.parametrize("kind", ["k_innermost", "k_short", "transposed", "no_min",
+                                  "wrong_index"])
+def test_pins_reject_planted_mistakes(kind):
+    caught = False
+    for seed in range(30):
+        rng = np.random.default_rng(5000 + seed)
+        n = int(rng.integers(3, 8))
+        W = random_tiny(n, 0.5, 1, 9, rng)
+        D = _fw_variant(W, kind).astype(np.float32)
+        try:
+            check_against_brute(D, W)
+        except AssertionError:
+            caught = True
+            break
+    assert caught, kind
+    # and the unmutated loop passes the same checks
+    for seed in range(5):
+        rng = np.random.default_rng(5000 + seed)
+        n = int(rng.integers(3, 8))
+        W = random_tiny(n, 0.5, 1, 9, rng)
+        check_against_brute(_fw_variant(W, "plain").astype(np.float32), W)
+
+
+def test_pins_reject_wrong_predecessor_rules():
+    """Largest-index and first-hop readings fail the brute-force pin."""
+    bad_largest = bad_first = False
+    for seed in range(40):
+        rng = np.random.default_rng(6000 + seed)
+        n = int(rng.integers(3, 8))
+        W = random_tiny(n, 0.7, 1, 2, rng)
+        D = oracle.fw(W)
+        _, last = brute_force(W)
+        for i, j in itertools.product(range(n), range(n)):
+            if i == j or np.isinf(D[i, j]):
+                continue
+            cands = [p for p in range(n) if p != j and np.isfinite(W[p, j]) and
+                     D[i, p] + W[p, j] == D[i, j]]
+            if max(cands) != last[i][j]:
+                bad_largest = True
+            # first hop of a shortest path differs from the last hop somewhere
+            firsts = [q for q in range(n) if q != i and np.isfinite(W[i, q]) and
+                      W[i, q] + D[q, j] == D[i, j]]
+            if firsts and min(firsts) != last[i][j]:
+                bad_first = True
+    assert bad_largest and bad_first
