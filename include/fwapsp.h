@@ -1,0 +1,203 @@
+/*
+ * fwapsp.h -- C ABI of the MI355X (gfx950) blocked Floyd-Warshall APSP library
+ * (libfwapsp.so).
+ *
+ * Paper: B. Lund, J. W. Smith, "A Multi-Stage CUDA Kernel for Floyd-Warshall"
+ * (arXiv 1001.4108).  The operation is the problem of section 3.1: given a
+ * weighted directed graph as a dense matrix W with w_ii = 0 and "infinity" on
+ * absent edges and no negative cycle, overwrite W with the shortest-path
+ * lengths d_ij (Fig. FW-Alg).  The library computes it by the blocked
+ * schedule of section 3.2 / Fig. BFW-Alg (per k-block: the diagonal tile, the
+ * row and column panels, then all remaining tiles).
+ *
+ * Common conventions
+ *   - Matrices are row-major: entry (i, j) lives at d[i * ld + j], 0 <= i, j < n,
+ *     ld >= n.  Columns n .. ld-1 of every row are never read or written.
+ *   - Every matrix and output pointer is DEVICE memory owned by the caller; the
+ *     library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     compute calls are stream-ordered and asynchronous: they return after
+ *     enqueueing work; results are valid once the stream has been
+ *     synchronised.  Faults of enqueued kernels surface from later HIP calls,
+ *     as with any stream API.
+ *   - Argument errors are detected before anything is enqueued and return
+ *     FW_ERR_INVALID with no side effect.  HIP launch/allocation failures
+ *     return FW_ERR_HIP / FW_ERR_NOMEM.
+ *   - fp32: "infinity" is IEEE +INF.  Inputs must not contain NaN or -INF.
+ *     Where both signs of zero meet, either zero may be returned.
+ *   - int32: "infinity" is FW_I32_INF and sums are plain 32-bit adds (no
+ *     saturation): the library solves APSP on the complete graph whose missing
+ *     edges weigh FW_I32_INF.  Precondition: every simple-path weight sum of
+ *     the real edges lies in (-2^29, 2^29) and every entry lies in
+ *     [-2^29, FW_I32_INF]; then no add overflows, reachable distances are
+ *     exact and unreachable pairs end at values above FW_I32_INF / 2.
+ *   - Exactness: blocked Floyd-Warshall evaluates path sums in a different
+ *     association than the plain triple loop.  Results are bit-identical to the
+ *     triple loop whenever the arithmetic is exact (int32 under the
+ *     precondition; fp32 with integer-valued weights whose true distances are
+ *     below 2^24).  Otherwise fp32 results are valid shortest-path values that
+ *     may differ from the triple loop's in the last bits.
+ *   - Negative cycles violate the problem statement (section 3.1); the
+ *     distances are then unspecified.  fw_negative_cycle detects them.
+ */
+#ifndef FWAPSP_H
+#define FWAPSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FW_I32_INF 1073741823 /* INT32_MAX / 2: "no edge" for int32 matrices */
+
+typedef enum { FW_F32 = 0, FW_I32 = 1 } fw_dtype;
+
+typedef enum {
+    FW_OK = 0,
+    FW_ERR_INVALID = 1,     /* bad argument; nothing was enqueued            */
+    FW_ERR_HIP = 2,         /* a HIP call failed                             */
+    FW_ERR_NOMEM = 3,       /* device or host allocation failed              */
+    FW_ERR_UNSUPPORTED = 4, /* valid request this build cannot serve         */
+    FW_ERR_BUSY = 5,        /* server: admission refused (budget or queue)   */
+    FW_ERR_NOT_FOUND = 6    /* server: unknown request id                    */
+} fw_status;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *fw_status_string(int status);
+
+/* Library version string (static). */
+const char *fw_version(void);
+
+/*
+ * fw_apsp -- all-pairs shortest paths in place, fp32 (section 3.1, solved by
+ * the blocked schedule of section 3.2).
+ *   d      device, n x n fp32 matrix with leading dimension ld (in elements);
+ *          on entry the edge weights (0 diagonal, +INF absent), on completion
+ *          the shortest-path lengths.
+ *   n      number of vertices, 0 <= n < 2^31.  n = 0 or 1 returns FW_OK and
+ *          enqueues nothing.
+ *   ld     leading dimension, ld >= n.
+ * Errors: FW_ERR_INVALID for d == NULL with n > 0, n < 0, ld < n, or n*ld
+ * overflowing int64.
+ */
+int fw_apsp(float *d, int64_t n, int64_t ld, void *stream);
+
+/* fw_apsp for int32 weights (FW_I32_INF = absent edge); same contract. */
+int fw_apsp_i32(int32_t *d, int64_t n, int64_t ld, void *stream);
+
+/*
+ * fw_apsp_pred -- distances plus the optional predecessor matrix.
+ *   d, n, ld   as fw_apsp; `dtype` (fw_dtype) says whether d is fp32 or int32.
+ *   pred       device int32 n x n matrix (leading dimension ld_pred >= n), or
+ *              NULL for distances only.  It need not be initialised.  On
+ *              completion pred[i*ld_pred+j] is -1 when i == j or j is not
+ *              reachable from i (fp32: d_ij == +INF; int32: d_ij > FW_I32_INF/2),
+ *              and otherwise the canonical predecessor: the smallest vertex p
+ *              that is the last hop of some shortest i -> j path.  (The paper
+ *              computes distances only; this reading is unique, so it is the
+ *              same for every tile size and batch composition.)  It is computed
+ *              during the sweep by a lexicographic minimum over (distance, last
+ *              hop) and requires, besides the distance preconditions, that the
+ *              graph has no zero-weight cycle.
+ * Errors: as fw_apsp, plus FW_ERR_INVALID for a bad dtype or, with pred
+ * non-NULL, ld_pred < n or n*ld_pred overflowing int64.
+ */
+int fw_apsp_pred(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred,
+                 int64_t ld_pred, void *stream);
+
+/*
+ * fw_apsp_plan -- fw_apsp_pred with an explicit tile size (the k-block depth
+ * s of section 3.2) instead of the library's choice.  tile must be one of
+ * fw_plan_tiles(); results are identical for every tile (the exactness rule
+ * above).  Used to test every plan and by the autotuner.
+ */
+int fw_apsp_plan(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred,
+                 int64_t ld_pred, int tile, void *stream);
+
+/*
+ * Tile sizes fw_apsp_plan accepts: writes up to `cap` of them to `tiles`
+ * (host memory) and returns how many exist.
+ */
+int fw_plan_tiles(int *tiles, int cap);
+
+/*
+ * Tile size the library picks for (dtype, n), from its tuned plan table.
+ * Returns the tile, or 0 for n <= 1, or -1 for a bad dtype / n < 0.
+ */
+int fw_plan_tile(int dtype, int64_t n);
+
+/*
+ * fw_plan_set -- replace the plan table entry for a size bucket: graphs of
+ * dtype `dtype` with n_lo <= n <= n_hi use `tile`.  Used by the autotuner to
+ * install measured choices.  Returns FW_OK or FW_ERR_INVALID.
+ */
+int fw_plan_set(int dtype, int64_t n_lo, int64_t n_hi, int tile);
+
+/* Restore the built-in plan table. */
+void fw_plan_reset(void);
+
+/*
+ * fw_apsp_batched -- many independent graphs in one call, solved together by
+ * one persistent kernel launch (graphs small enough for one workgroup's LDS
+ * are solved whole in LDS; larger ones tile by tile inside one workgroup).
+ *   d        HOST array of `count` device pointers, one n[g] x n[g] matrix
+ *            each (leading dimension ld[g] >= n[g]); graphs must not alias.
+ *   n, ld    HOST arrays of `count` sizes and leading dimensions.
+ *   dtype    fw_dtype of every matrix.
+ *   pred     NULL, or a HOST array of `count` device pointers (entries may be
+ *            NULL) to int32 predecessor matrices with leading dimensions
+ *            ld_pred[g] (ld_pred may be NULL only if pred is NULL).
+ *   count    number of graphs (0 = no-op).
+ * A graph's result is bit-identical to fw_apsp_pred on the same graph alone.
+ * Errors: FW_ERR_INVALID if any graph's arguments are invalid (nothing is
+ * enqueued), FW_ERR_UNSUPPORTED if a graph exceeds fw_batched_max_n().
+ * The call copies its descriptor table to the device asynchronously on
+ * `stream` from library-owned pinned memory and may be called again at once.
+ */
+int fw_apsp_batched(void *const *d, const int64_t *n, const int64_t *ld,
+                    int64_t count, int dtype, int32_t *const *pred,
+                    const int64_t *ld_pred, void *stream);
+
+/* Largest n fw_apsp_batched accepts for a dtype (with or without pred). */
+int64_t fw_batched_max_n(int dtype, int with_pred);
+
+/*
+ * fw_negative_cycle -- after a solve, write 1 to *flag_dev (device int32) if
+ * some d_ii < 0 (a negative cycle through i, section 3.1's excluded case),
+ * else 0.  Stream-ordered.
+ */
+int fw_negative_cycle(const void *d, int dtype, int64_t n, int64_t ld,
+                      int32_t *flag_dev, void *stream);
+
+/*
+ * fw_path -- reconstruct one shortest path from a predecessor matrix that was
+ * copied to HOST memory.  Writes the vertices i = v_0, v_1, ..., v_m = j to
+ * `path` (host, capacity `cap`) and returns m + 1, or 0 when j is unreachable
+ * from i, or -1 for invalid arguments / a predecessor chain that does not
+ * lead back to i within n steps / insufficient capacity.
+ */
+int64_t fw_path(const int32_t *pred_host, int64_t n, int64_t ld_pred, int64_t i,
+                int64_t j, int64_t *path, int64_t cap);
+
+/*
+ * Phase timing.  While enabled, every phase launch of the calls above is
+ * bracketed by HIP events on its stream (launches run eagerly, not from a
+ * captured graph).  fw_profile_read synchronises those events and writes, per
+ * phase kind, the summed kernel time in ms and the launch count
+ * (kinds: 0 = diagonal tile, 1 = panels, 2 = bulk tiles, 3 = predecessor
+ * init/fix-up, 4 = batched persistent kernel); it returns the number of kinds
+ * written and clears the accumulators.
+ */
+int fw_profile_enable(int on);
+int fw_profile_read(double *ms, int64_t *launches, int cap);
+
+/* Work counters of the last fw_profile_read window: algorithmic cell updates
+ * per kind (the n^3 tasks of section 1 split by phase). */
+int fw_profile_updates(double *updates, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FWAPSP_H */

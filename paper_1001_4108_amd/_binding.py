@@ -1,0 +1,265 @@
+"""ctypes binding of libfwapsp.so (the C ABI in include/fwapsp.h).
+
+Argument marshalling only: every step of a solve runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current stream.  The library
+is loaded on first use and its absence is an error (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch  # imported first so the process uses torch's HIP runtime
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfwapsp.so")
+
+I32_INF = 1073741823
+FW_F32, FW_I32 = 0, 1
+STATUS = {0: "FW_OK", 1: "FW_ERR_INVALID", 2: "FW_ERR_HIP", 3: "FW_ERR_NOMEM",
+          4: "FW_ERR_UNSUPPORTED", 5: "FW_ERR_BUSY", 6: "FW_ERR_NOT_FOUND"}
+
+_lib = None
+_lock = threading.Lock()
+
+
+class FwError(RuntimeError):
+    """A non-OK status returned by the library."""
+
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {lib().fw_status_string(status).decode()}")
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python paper_1001_4108_amd/build.py` "
+                "(or __graft_entry__.build()); there is no non-HIP fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+def _declare(L):
+    vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "fw_status_string": ([ci], ctypes.c_char_p),
+        "fw_version": ([], ctypes.c_char_p),
+        "fw_apsp": ([vp, i64, i64, vp], ci),
+        "fw_apsp_i32": ([vp, i64, i64, vp], ci),
+        "fw_apsp_pred": ([vp, ci, i64, i64, vp, i64, vp], ci),
+        "fw_apsp_plan": ([vp, ci, i64, i64, vp, i64, ci, vp], ci),
+        "fw_plan_tiles": ([ctypes.POINTER(ci), ci], ci),
+        "fw_plan_tile": ([ci, i64], ci),
+        "fw_plan_set": ([ci, i64, i64, ci], ci),
+        "fw_plan_reset": ([], None),
+        "fw_apsp_batched": ([ctypes.POINTER(vp), P64, P64, i64, ci, ctypes.POINTER(vp), P64, vp],
+                            ci),
+        "fw_batched_max_n": ([ci, ci], i64),
+        "fw_negative_cycle": ([vp, ci, i64, i64, vp, vp], ci),
+        "fw_path": ([vp, i64, i64, i64, i64, P64, i64], i64),
+        "fw_profile_enable": ([ci], ci),
+        "fw_profile_read": ([ctypes.POINTER(ctypes.c_double), P64, ci], ci),
+        "fw_profile_updates": ([ctypes.POINTER(ctypes.c_double), ci], ci),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise FwError(status, where)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return FW_F32
+    if t.dtype == torch.int32:
+        return FW_I32
+    raise TypeError(f"distance matrices are float32 or int32, got {t.dtype}")
+
+
+def _matrix(t: torch.Tensor, name: str):
+    """(pointer, n, ld) of a square row-major device matrix view."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dim() != 2 or t.shape[0] != t.shape[1]:
+        raise ValueError(f"{name} must be square, got {tuple(t.shape)}")
+    n = t.shape[0]
+    if n > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name} needs unit column stride (row-major)")
+    ld = t.stride(0) if n > 0 else 0
+    if n > 0 and ld < n:
+        raise ValueError(f"{name} rows overlap (stride {ld} < n {n})")
+    return t.data_ptr(), n, max(ld, n)
+
+
+def _stream(t: torch.Tensor, stream):
+    if stream is None:
+        stream = torch.cuda.current_stream(t.device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def fw_apsp(d: torch.Tensor, stream=None) -> torch.Tensor:
+    """All-pairs shortest paths in place on a float32 device matrix view."""
+    if d.dtype != torch.float32:
+        raise TypeError("fw_apsp takes float32; use fw_apsp_i32 for int32")
+    p, n, ld = _matrix(d, "d")
+    with torch.cuda.device(d.device):
+        _check(lib().fw_apsp(p, n, ld, _stream(d, stream)), "fw_apsp")
+    return d
+
+
+def fw_apsp_i32(d: torch.Tensor, stream=None) -> torch.Tensor:
+    """All-pairs shortest paths in place on an int32 device matrix view."""
+    if d.dtype != torch.int32:
+        raise TypeError("fw_apsp_i32 takes int32")
+    p, n, ld = _matrix(d, "d")
+    with torch.cuda.device(d.device):
+        _check(lib().fw_apsp_i32(p, n, ld, _stream(d, stream)), "fw_apsp_i32")
+    return d
+
+
+def _pred_args(d, pred):
+    if pred is None:
+        return None, 0
+    if pred.dtype != torch.int32 or pred.device != d.device:
+        raise ValueError("pred must be an int32 tensor on d's device")
+    pp, pn, pld = _matrix(pred, "pred")
+    if pn != d.shape[0]:
+        raise ValueError("pred must have d's shape")
+    return pp, pld
+
+
+def fw_apsp_pred(d: torch.Tensor, pred: torch.Tensor | None = None, stream=None):
+    """Distances in place plus, when ``pred`` is given, the canonical predecessors."""
+    code = _dtype_code(d)
+    p, n, ld = _matrix(d, "d")
+    pp, pld = _pred_args(d, pred)
+    with torch.cuda.device(d.device):
+        _check(lib().fw_apsp_pred(p, code, n, ld, pp, pld, _stream(d, stream)), "fw_apsp_pred")
+    return d, pred
+
+
+def fw_apsp_plan(d: torch.Tensor, tile: int, pred: torch.Tensor | None = None, stream=None):
+    """fw_apsp_pred with an explicit tile size (one of :func:`plan_tiles`)."""
+    code = _dtype_code(d)
+    p, n, ld = _matrix(d, "d")
+    pp, pld = _pred_args(d, pred)
+    with torch.cuda.device(d.device):
+        _check(lib().fw_apsp_plan(p, code, n, ld, pp, pld, int(tile), _stream(d, stream)),
+               "fw_apsp_plan")
+    return d, pred
+
+
+def plan_tiles() -> list[int]:
+    buf = (ctypes.c_int * 16)()
+    k = lib().fw_plan_tiles(buf, 16)
+    return [buf[i] for i in range(k)]
+
+
+def plan_tile(dtype, n: int) -> int:
+    code = FW_F32 if dtype in (torch.float32, "f32", FW_F32) else FW_I32
+    return int(lib().fw_plan_tile(code, int(n)))
+
+
+def plan_set(dtype, n_lo: int, n_hi: int, tile: int) -> None:
+    code = FW_F32 if dtype in (torch.float32, "f32", FW_F32) else FW_I32
+    _check(lib().fw_plan_set(code, int(n_lo), int(n_hi), int(tile)), "fw_plan_set")
+
+
+def plan_reset() -> None:
+    lib().fw_plan_reset()
+
+
+def fw_apsp_batched(mats, preds=None, stream=None) -> None:
+    """Solve a list of independent square device matrices (one dtype) together."""
+    count = len(mats)
+    if count == 0:
+        return
+    code = _dtype_code(mats[0])
+    dev = mats[0].device
+    ptrs = (ctypes.c_void_p * count)()
+    ns = (ctypes.c_int64 * count)()
+    lds = (ctypes.c_int64 * count)()
+    for g, m in enumerate(mats):
+        if m.dtype != mats[0].dtype or m.device != dev:
+            raise ValueError("batched matrices must share dtype and device")
+        p, n, ld = _matrix(m, f"mats[{g}]")
+        ptrs[g], ns[g], lds[g] = p, n, ld
+    pptr = pld = None
+    if preds is not None:
+        if len(preds) != count:
+            raise ValueError("preds must match mats")
+        pptr = (ctypes.c_void_p * count)()
+        pld = (ctypes.c_int64 * count)()
+        for g, (m, q) in enumerate(zip(mats, preds)):
+            if q is None:
+                pptr[g], pld[g] = None, 0
+            else:
+                pptr[g], pld[g] = _pred_args(m, q)
+    with torch.cuda.device(dev):
+        _check(lib().fw_apsp_batched(ptrs, ns, lds, count, code, pptr, pld,
+                                     _stream(mats[0], stream)), "fw_apsp_batched")
+
+
+def batched_max_n(dtype, with_pred: bool = False) -> int:
+    code = FW_F32 if dtype in (torch.float32, "f32", FW_F32) else FW_I32
+    return int(lib().fw_batched_max_n(code, int(bool(with_pred))))
+
+
+def fw_negative_cycle(d: torch.Tensor, stream=None) -> bool:
+    """True when some d_ii < 0 after a solve (a negative cycle).  Synchronises."""
+    code = _dtype_code(d)
+    p, n, ld = _matrix(d, "d")
+    flag = torch.zeros(1, dtype=torch.int32, device=d.device)
+    with torch.cuda.device(d.device):
+        s = _stream(d, stream)
+        _check(lib().fw_negative_cycle(p, code, n, ld, flag.data_ptr(), s), "fw_negative_cycle")
+    if stream is not None:
+        stream.synchronize()
+    return bool(flag.item())
+
+
+def fw_path(pred_host, i: int, j: int) -> list[int]:
+    """Shortest path i -> j from a host predecessor matrix ([] if unreachable)."""
+    import numpy as np
+    P = np.ascontiguousarray(pred_host, dtype=np.int32)
+    n = P.shape[0]
+    buf = (ctypes.c_int64 * max(n, 1))()
+    k = lib().fw_path(P.ctypes.data, n, P.strides[0] // 4, int(i), int(j), buf, max(n, 1))
+    if k < 0:
+        raise FwError(1, "fw_path")
+    return [buf[t] for t in range(k)]
+
+
+def profile_enable(on: bool = True) -> None:
+    lib().fw_profile_enable(1 if on else 0)
+
+
+KINDS = ("diag", "panel", "bulk", "pred", "batched")
+
+
+def profile_read():
+    """{kind: (ms, launches, updates)} accumulated since the last read."""
+    ms = (ctypes.c_double * 8)()
+    cnt = (ctypes.c_int64 * 8)()
+    k = lib().fw_profile_read(ms, cnt, 8)
+    if k < 0:
+        raise FwError(-k, "fw_profile_read")
+    upd = (ctypes.c_double * 8)()
+    lib().fw_profile_updates(upd, 8)
+    return {KINDS[i]: (ms[i], cnt[i], upd[i]) for i in range(k)}

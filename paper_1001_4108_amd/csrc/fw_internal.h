@@ -1,0 +1,37 @@
+// Internal declarations shared by the host driver and the kernel files of
+// libfwapsp.  Not part of the public ABI (see include/fwapsp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fw {
+
+constexpr int32_t kI32Inf = 1073741823;   // "no edge" for int32
+constexpr int32_t kPredNone = 0x7fffffff; // in-sweep "no last hop yet"
+
+enum PhaseKind { kDiag = 0, kPanel = 1, kBulk = 2, kPredFix = 3, kBatched = 4, kNumKinds = 5 };
+
+// One stage-phase launch of the blocked schedule.  `d`/`p` are the matrix
+// and the (optional) predecessor matrix; `b` is the k-block index, `nb` the
+// number of tile rows.  Returns hipSuccess or the launch error.
+hipError_t launch_diag(int dtype, int tile, void *d, int32_t *p, int n, int64_t ld,
+                       int64_t ldp, int b, hipStream_t st);
+hipError_t launch_panels(int dtype, int tile, void *d, int32_t *p, int n, int64_t ld,
+                         int64_t ldp, int b, int nb, hipStream_t st);
+hipError_t launch_bulk(int dtype, int tile, void *d, int32_t *p, int n, int64_t ld,
+                       int64_t ldp, int b, int nb, hipStream_t st);
+hipError_t launch_pred_init(int dtype, const void *d, int32_t *p, int n, int64_t ld,
+                            int64_t ldp, hipStream_t st);
+hipError_t launch_pred_fix(int dtype, const void *d, int32_t *p, int n, int64_t ld,
+                           int64_t ldp, hipStream_t st);
+hipError_t launch_negcycle(int dtype, const void *d, int n, int64_t ld, int32_t *flag,
+                           hipStream_t st);
+
+// True when the vectorised (16-byte) load/store path may be used for a
+// matrix: 16-byte aligned base and a leading dimension divisible by 4.
+inline bool vec_ok(const void *ptr, int64_t ld) {
+    return ((uintptr_t)ptr % 16 == 0) && (ld % 4 == 0);
+}
+
+}  // namespace fw

@@ -1,0 +1,88 @@
+"""The C-ABI library loads, exports every declared symbol, and validates
+arguments on the host (no GPU needed: every call here returns before any HIP
+call is made)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1001_4108_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fwapsp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fw_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    L = B.lib()
+    for code, name in B.STATUS.items():
+        assert L.fw_status_string(code).decode().startswith(name)
+    assert L.fw_status_string(999).decode() == "FW_ERR_UNKNOWN"
+    assert b"gfx950" in L.fw_version()
+
+
+def test_argument_validation_without_gpu():
+    L = B.lib()
+    null = None
+    assert L.fw_apsp(null, 5, 5, null) == 1           # NULL matrix
+    assert L.fw_apsp(ctypes.c_void_p(16), -1, 5, null) == 1
+    assert L.fw_apsp(ctypes.c_void_p(16), 6, 5, null) == 1   # ld < n
+    assert L.fw_apsp(ctypes.c_void_p(16), 2**40, 2**40, null) == 1  # n too large
+    assert L.fw_apsp_i32(null, 3, 3, null) == 1
+    assert L.fw_apsp(null, 0, 0, null) == 0            # empty graph: no-op
+    assert L.fw_apsp(ctypes.c_void_p(16), 1, 1, null) == 0   # one vertex: no-op
+    assert L.fw_apsp_pred(ctypes.c_void_p(16), 7, 4, 4, null, 0, null) == 1  # dtype
+    assert L.fw_apsp_pred(ctypes.c_void_p(16), 0, 4, 4, ctypes.c_void_p(32), 3, null) == 1
+    assert L.fw_apsp_plan(ctypes.c_void_p(16), 0, 64, 64, null, 0, 48, null) == 1  # tile
+    assert L.fw_negative_cycle(ctypes.c_void_p(16), 0, 4, 4, null, null) == 1
+    assert L.fw_apsp_batched(None, None, None, 0, 0, None, None, null) == 0
+
+
+def test_plan_table():
+    tiles = B.plan_tiles()
+    assert tiles == sorted(tiles) and set(tiles) <= {32, 64, 128, 256}
+    B.plan_reset()
+    assert B.plan_tile("f32", 0) == 0 and B.plan_tile("f32", 1) == 0
+    for n in (2, 100, 512, 5000, 16384):
+        assert B.plan_tile("f32", n) in tiles
+        assert B.plan_tile("i32", n) in tiles
+    assert B.lib().fw_plan_tile(5, 10) == -1
+    B.plan_set("f32", 100, 200, tiles[-1])
+    assert B.plan_tile("f32", 150) == tiles[-1]
+    with pytest.raises(B.FwError):
+        B.plan_set("f32", 10, 5, tiles[0])
+    with pytest.raises(B.FwError):
+        B.plan_set("f32", 1, 5, 48)
+    B.plan_reset()
+
+
+def test_fw_path_host_reconstruction():
+    # 0 -> 2 -> 1 -> 3, 4 unreachable
+    P = np.array([[-1, 2, 0, 1, -1],
+                  [-1, -1, -1, 1, -1],
+                  [-1, 2, -1, 1, -1],
+                  [-1, -1, -1, -1, -1],
+                  [-1, -1, -1, -1, -1]], np.int32)
+    assert B.fw_path(P, 0, 3) == [0, 2, 1, 3]
+    assert B.fw_path(P, 0, 0) == [0]
+    assert B.fw_path(P, 0, 4) == []
+    bad = P.copy()
+    bad[0, 1] = 3  # 3 -> 1 -> 3 ... never returns to 0
+    bad[0, 3] = 1
+    with pytest.raises(B.FwError):
+        B.fw_path(bad, 0, 3)
