@@ -139,8 +139,10 @@ void fw_plan_reset(void);
 
 /*
  * fw_apsp_batched -- many independent graphs in one call, solved together by
- * one persistent kernel launch (graphs small enough for one workgroup's LDS
- * are solved whole in LDS; larger ones tile by tile inside one workgroup).
+ * one persistent kernel launch: every workgroup takes graphs from a device
+ * work counter, largest first, and solves each alone (whole-graph closure
+ * when n is at most the plan's tile, else the blocked schedule run inside the
+ * workgroup).
  *   d        HOST array of `count` device pointers, one n[g] x n[g] matrix
  *            each (leading dimension ld[g] >= n[g]); graphs must not alias.
  *   n, ld    HOST arrays of `count` sizes and leading dimensions.
@@ -161,6 +163,31 @@ int fw_apsp_batched(void *const *d, const int64_t *n, const int64_t *ld,
 
 /* Largest n fw_apsp_batched accepts for a dtype (with or without pred). */
 int64_t fw_batched_max_n(int dtype, int with_pred);
+
+/*
+ * Reusable batch plans.  fw_batch_plan_create validates the graphs exactly as
+ * fw_apsp_batched does and builds the descriptor table once (pinned host
+ * memory plus a device copy, both owned by the plan); the matrices must stay
+ * allocated for the plan's lifetime and are re-solved in place on every
+ * launch.  fw_batch_plan_launch enqueues on `stream`, by `mode`:
+ *   0  the table refresh (which also resets the device work counter) and the
+ *      persistent kernel, as two stream operations;
+ *   1  the same two operations captured once into a hipGraph, replayed by
+ *      every later launch (one graph launch per batch);
+ *   2  no persistent kernel: every graph through the single-graph stage
+ *      loop of fw_apsp_pred (the per-graph launch baseline).
+ * All modes give bit-identical results.  Launches of one plan must not
+ * overlap in time (they share the table).  fw_batch_plan_destroy synchronises
+ * the device and frees the plan.  fw_batch_plan_grid returns the persistent
+ * grid size (workgroups), or -1 for a NULL plan.
+ */
+typedef struct fw_batch_plan_s *fw_batch_plan;
+int fw_batch_plan_create(void *const *d, const int64_t *n, const int64_t *ld, int64_t count,
+                         int dtype, int32_t *const *pred, const int64_t *ld_pred,
+                         fw_batch_plan *out);
+int fw_batch_plan_launch(fw_batch_plan plan, int mode, void *stream);
+int fw_batch_plan_destroy(fw_batch_plan plan);
+int64_t fw_batch_plan_grid(fw_batch_plan plan);
 
 /*
  * fw_negative_cycle -- after a solve, write 1 to *flag_dev (device int32) if

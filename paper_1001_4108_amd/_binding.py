@@ -67,6 +67,11 @@ def _declare(L):
         "fw_apsp_batched": ([ctypes.POINTER(vp), P64, P64, i64, ci, ctypes.POINTER(vp), P64, vp],
                             ci),
         "fw_batched_max_n": ([ci, ci], i64),
+        "fw_batch_plan_create": ([ctypes.POINTER(vp), P64, P64, i64, ci, ctypes.POINTER(vp), P64,
+                                  ctypes.POINTER(vp)], ci),
+        "fw_batch_plan_launch": ([vp, ci, vp], ci),
+        "fw_batch_plan_destroy": ([vp], ci),
+        "fw_batch_plan_grid": ([vp], i64),
         "fw_negative_cycle": ([vp, ci, i64, i64, vp, vp], ci),
         "fw_path": ([vp, i64, i64, i64, i64, P64, i64], i64),
         "fw_profile_enable": ([ci], ci),
@@ -187,9 +192,16 @@ def plan_reset() -> None:
 
 def fw_apsp_batched(mats, preds=None, stream=None) -> None:
     """Solve a list of independent square device matrices (one dtype) together."""
-    count = len(mats)
-    if count == 0:
+    if len(mats) == 0:
         return
+    code, dev, ptrs, ns, lds, pptr, pld = _batch_arrays(mats, preds)
+    with torch.cuda.device(dev):
+        _check(lib().fw_apsp_batched(ptrs, ns, lds, len(mats), code, pptr, pld,
+                                     _stream(mats[0], stream)), "fw_apsp_batched")
+
+
+def _batch_arrays(mats, preds):
+    count = len(mats)
     code = _dtype_code(mats[0])
     dev = mats[0].device
     ptrs = (ctypes.c_void_p * count)()
@@ -211,9 +223,54 @@ def fw_apsp_batched(mats, preds=None, stream=None) -> None:
                 pptr[g], pld[g] = None, 0
             else:
                 pptr[g], pld[g] = _pred_args(m, q)
-    with torch.cuda.device(dev):
-        _check(lib().fw_apsp_batched(ptrs, ns, lds, count, code, pptr, pld,
-                                     _stream(mats[0], stream)), "fw_apsp_batched")
+    return code, dev, ptrs, ns, lds, pptr, pld
+
+
+class BatchPlan:
+    """A reusable batch (fw_batch_plan_*): the descriptor table is built once;
+    ``launch("graph")`` replays one captured hipGraph per call.  The
+    matrices are solved in place on every launch and must outlive the plan."""
+
+    def __init__(self, mats, preds=None):
+        if not mats:
+            raise ValueError("empty batch")
+        code, dev, ptrs, ns, lds, pptr, pld = _batch_arrays(mats, preds)
+        self.device = dev
+        self._mats = list(mats)
+        self._preds = list(preds) if preds is not None else None
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            _check(lib().fw_batch_plan_create(ptrs, ns, lds, len(mats), code, pptr, pld,
+                                              ctypes.byref(h)), "fw_batch_plan_create")
+        self._h = h
+
+    @property
+    def grid(self) -> int:
+        return int(lib().fw_batch_plan_grid(self._h))
+
+    MODES = {"kernel": 0, "graph": 1, "per_graph": 2}
+
+    def launch(self, mode: str = "graph", stream=None) -> None:
+        """mode: "graph" (captured persistent launch), "kernel" (eager
+        persistent launch) or "per_graph" (single-graph launches, baseline)."""
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        with torch.cuda.device(self.device):
+            _check(lib().fw_batch_plan_launch(self._h, self.MODES[mode],
+                                              _stream(self._mats[0], stream)),
+                   "fw_batch_plan_launch")
+
+    def destroy(self) -> None:
+        if self._h is not None:
+            with torch.cuda.device(self.device):
+                lib().fw_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def batched_max_n(dtype, with_pred: bool = False) -> int:

@@ -33,9 +33,13 @@ std::vector<PlanEntry> g_plan[2];
 void default_plan_locked() {
     for (int dt = 0; dt < 2; ++dt) {
         g_plan[dt].clear();
-        g_plan[dt].push_back({0, 256, 32});
-        g_plan[dt].push_back({257, 2048, 64});
-        g_plan[dt].push_back({2049, INT64_MAX, 128});
+        // n <= tile: one closure over the whole graph (the plain algorithm)
+        g_plan[dt].push_back({0, 32, 32});
+        g_plan[dt].push_back({33, 64, 64});
+        g_plan[dt].push_back({65, 128, 128});
+        // blocked
+        g_plan[dt].push_back({129, 1024, 64});
+        g_plan[dt].push_back({1025, INT64_MAX, 128});
     }
 }
 
@@ -179,6 +183,30 @@ int solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int
 }
 
 }  // namespace
+
+int plan_tile_for(int dtype, int64_t n) { return plan_tile(dtype, n); }
+
+int solve_single(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64_t ldp,
+                 hipStream_t st) {
+    return solve(d, dtype, (int)n, ld, pred, ldp, plan_tile(dtype, n), st);
+}
+
+int validate_matrix(const void *d, int dtype, int64_t n, int64_t ld, const int32_t *pred,
+                    int64_t ldp) {
+    return validate(d, dtype, n, ld, pred, ldp);
+}
+
+struct BatchHeader;
+struct BatchItem;
+hipError_t launch_batched_raw(int dtype, bool pred, BatchHeader *hdr, const BatchItem *items,
+                              int grid, hipStream_t st);
+
+hipError_t timed_launch_batched(double updates, hipStream_t st, int dtype, bool pred,
+                                BatchHeader *hdr, const BatchItem *items, int grid) {
+    return timed(kBatched, updates, st,
+                 [&] { return launch_batched_raw(dtype, pred, hdr, items, grid, st); });
+}
+
 }  // namespace fw
 
 using namespace fw;
