@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-phase HIP events (plain timed region)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=4.0,
+                    help="arrival window of the serving trace at the configured rate")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--batched-reps", type=int, default=5)
     return ap.parse_args()
 
@@ -126,6 +130,101 @@ def bench_batched(torch, fw, gen, dev, reps):
     out["check"] = "ok" if ok else "mismatch"
     out["speedup_vs_per_graph"] = out["per_graph"]["ms"] / out["graph"]["ms"]
     plan.destroy()
+    return out
+
+
+def run_trace(torch, fw, srv, bases, tr, limit_s):
+    """Open-loop replay: submit each request at its arrival time, then drain."""
+    import threading
+    import numpy as np
+    ids = {}
+    t0 = time.perf_counter_ns()
+    sub_err = []
+
+    def submitter():
+        try:
+            for r in range(len(tr.t)):
+                due = t0 + int(tr.t[r] * 1e9)
+                while True:
+                    now = time.perf_counter_ns()
+                    if now >= due:
+                        break
+                    if due - now > 200_000:
+                        time.sleep((due - now - 100_000) / 1e9)
+                n, o, b = int(tr.n[r]), int(tr.o[r]), int(tr.b[r])
+                ids[srv.submit(bases[b][o:o + n, o:o + n])] = r
+        except Exception as e:  # surfaced after the join
+            sub_err.append(e)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    recs = []
+    while th.is_alive():
+        recs += srv.poll(timeout_us=20000)
+    th.join()
+    if sub_err:
+        raise sub_err[0]
+    srv.drain(timeout_s=limit_s)
+    while len(recs) < len(tr.t):
+        got = srv.poll(timeout_us=100000)
+        if not got:
+            break
+        recs += got
+    lat = np.array([(c[6] - c[4]) / 1e6 for c in recs if c[2] == 0])
+    first = min(c[4] for c in recs)
+    last = max(c[6] for c in recs)
+    span = (last - first) / 1e9
+    upd = float(sum(float(c[1]) ** 3 for c in recs if c[2] == 0))
+    st = srv.stats()
+    return {"requests": len(tr.t), "completed": int((np.array([c[2] for c in recs]) == 0).sum()),
+            "offered_per_s": len(tr.t) / float(tr.t[-1]) if len(tr.t) > 1 else 0.0,
+            "solves_per_s": len(lat) / span, "updates_per_s": upd / span, "span_s": span,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "max_ms": float(lat.max()), "mean_group": float(np.mean([c[3] for c in recs])),
+            "batched_groups": st["batched_groups"], "single_groups": st["single_groups"],
+            "deferrals": st["deferrals"], "peak_bytes": st["peak_bytes"]}
+
+
+def bench_serving(torch, fw, gen, dev, seconds, rate):
+    """Poisson arrivals, n log-uniform in [64, 8192], fp32 windows of resident
+    base graphs; footprint admission into a 32 GiB budget, 4 worker streams."""
+    import numpy as np
+    tr_full = gen.serving_trace(rate=rate, duration=seconds)
+    bases = [torch.from_numpy(tr_full.base_graph(b)).to(dev) for b in range(tr_full.nbase)]
+    cfg = dict(budget_bytes=32 << 30, streams=4, small_n=512, max_batch=2048)
+    out = {"workload": f"Poisson arrivals at {rate:.0f} req/s for {seconds:.1f} s, n log-uniform "
+                       "in [64,8192], fp32, edge prob 0.3, integer weights [1,1000] (principal "
+                       "windows of 2 resident 8192-vertex base graphs)", "config": cfg}
+    with fw.Server(torch.float32, **cfg) as srv:
+        # warm-up: a few requests of each path
+        for n in (64, 300, 700, 2000):
+            srv.submit(bases[0][:n, :n])
+        srv.drain(timeout_s=60)
+        srv.poll()
+        out["at_rate"] = run_trace(torch, fw, srv, bases, tr_full, 600)
+        cap = out["at_rate"]["solves_per_s"]
+        out["capacity_solves_per_s"] = cap
+        for frac in (0.5, 0.9):
+            tr = gen.serving_trace(rate=cap * frac, duration=min(seconds, 3.0), seed=50 + int(frac * 10))
+            out[f"at_{frac:.1f}x_capacity"] = run_trace(torch, fw, srv, bases, tr, 600)
+    # correctness: a few requests of the trace solved through the server with
+    # copy-back, compared with the oracle
+    import oracle
+    rng = np.random.default_rng(9)
+    picks = [r for r in rng.permutation(len(tr_full.n)) if tr_full.n[r] <= 700][:6]
+    ok = True
+    with fw.Server(torch.float32, budget_bytes=1 << 30, streams=2, small_n=512) as srv:
+        dsts = []
+        for r in picks:
+            n, o, b = int(tr_full.n[r]), int(tr_full.o[r]), int(tr_full.b[r])
+            dst = torch.empty((n, n), dtype=torch.float32).pin_memory()
+            srv.submit(bases[b][o:o + n, o:o + n], dst_host=dst)
+            dsts.append((r, dst))
+        srv.drain(timeout_s=60)
+        for r, dst in dsts:
+            ok &= bool(np.array_equal(dst.numpy().view(np.uint32),
+                                      oracle.fw(tr_full.request_graph(r)).view(np.uint32)))
+    out["check"] = "ok" if ok else "mismatch"
     return out
 
 
@@ -211,6 +310,14 @@ def main():
         log(f"batched: {batched['graph']['graphs_per_s']:.0f} graphs/s (graph launch), "
             f"{batched['per_graph']['graphs_per_s']:.0f} graphs/s per-graph launches")
 
+    serving = None
+    if not args.no_serving:
+        log(f"serving: {args.serve_rate:.0f} req/s for {args.serve_seconds:.1f} s")
+        serving = bench_serving(torch, fw, gen, dev, args.serve_seconds, args.serve_rate)
+        a = serving["at_rate"]
+        log(f"serving: {a['solves_per_s']:.0f} solves/s, p50 {a['p50_ms']:.1f} ms, "
+            f"p99 {a['p99_ms']:.1f} ms at {args.serve_rate:.0f} req/s offered")
+
     cpu = None
     if not args.no_cpu:
         log(f"cpu baseline: {args.cpu_ksteps} oracle k-iterations")
@@ -227,6 +334,7 @@ def main():
         "frac_of_update_peak": value / UPDATE_PEAK,
         "check": "ok" if ok else "mismatch",
         "phases": phases, "roofline": roof, "cpu_baseline": cpu, "batched": batched,
+        "serving": serving,
         "paper_context": {"tesla_c1060_s_n16384": 53.06,
                           "speedup_vs_paper": 53.06 / (ms_per_step / 1e3) if n == 16384 else None},
     }

@@ -190,6 +190,86 @@ int fw_batch_plan_destroy(fw_batch_plan plan);
 int64_t fw_batch_plan_grid(fw_batch_plan plan);
 
 /*
+ * Serving loop (continuous batching).  Requests are admitted in arrival order
+ * while their device footprint (n x round_up(n, 4) x 4 bytes) fits
+ * `budget_bytes`; each admitted payload is copied into a resident slot.
+ * Whenever one of `streams` worker streams is free, every admitted request
+ * with n <= small_n (up to max_batch of them) goes into one persistent
+ * batched launch, or the oldest admitted larger request runs the single-graph
+ * stage loop alone; groups on different streams overlap on the device.
+ * Finished requests return their memory and wake the dispatcher, so waiting
+ * requests are admitted as soon as memory and streams free up.  A request's
+ * result is bit-identical to fw_apsp / fw_apsp_i32 on the same matrix alone.
+ * The server runs its own host threads (one dispatcher, one completion thread
+ * per stream); every stream keeps the default priority.
+ */
+typedef struct {
+    int dtype;            /* fw_dtype of every request                        */
+    int streams;          /* worker streams, 1 .. 16                          */
+    int64_t budget_bytes; /* device memory for resident request matrices      */
+    int64_t small_n;      /* n <= small_n: batched path                       */
+    int max_batch;        /* most requests per batched launch                 */
+    int64_t queue_cap;    /* most requests waiting for admission              */
+} fw_server_config;
+
+typedef struct {
+    int64_t id, n;
+    int status;           /* FW_OK, or the error that ended the request       */
+    int group_size;       /* requests in the launch group it ran in           */
+    int64_t t_submit_ns;  /* host steady-clock timestamps                     */
+    int64_t t_admit_ns;
+    int64_t t_done_ns;    /* completion observed (after any copy-back)        */
+} fw_completion;
+
+typedef struct {
+    int64_t submitted, admitted, completed, failed, rejected, deferrals;
+    int64_t batched_groups, single_groups, max_group;
+    int64_t waiting, bytes_in_use, peak_bytes, budget_bytes;
+} fw_server_stats;
+
+typedef struct fw_server_s *fw_server;
+
+/* Allocates the budget arena, worker streams and threads on the current
+ * device.  FW_ERR_INVALID for a bad config, FW_ERR_NOMEM if allocation fails. */
+int fw_server_create(const fw_server_config *cfg, fw_server *out);
+
+/*
+ * Submit one request (thread-safe, non-blocking).  `src` (host or device, n x n
+ * with leading dimension ld_src >= n) must stay valid until the request's
+ * completion is reported.  If dst_host is non-NULL the result is copied there
+ * (leading dimension ld_dst) before completion.  keep != 0 keeps the result
+ * resident until fw_server_release (fetch it with fw_server_fetch); otherwise
+ * its memory returns to the budget at completion.  Writes the request id.
+ * Errors: FW_ERR_INVALID for bad arguments, FW_ERR_UNSUPPORTED when the
+ * footprint exceeds the whole budget, FW_ERR_BUSY when queue_cap requests are
+ * already waiting.
+ */
+int fw_server_submit(fw_server s, const void *src, int64_t n, int64_t ld_src, void *dst_host,
+                     int64_t ld_dst, int keep, int64_t *id_out);
+
+/* Up to `cap` completion records (host array), waiting up to timeout_us for
+ * the first; returns how many were written (negative status on bad args). */
+int fw_server_poll(fw_server s, fw_completion *out, int cap, int64_t timeout_us);
+
+/* Copy a finished kept result to `dst` (host or device, ld_dst >= n),
+ * stream-ordered on `stream`.  FW_ERR_NOT_FOUND for an unknown id,
+ * FW_ERR_INVALID if the request is not finished or was not kept. */
+int fw_server_fetch(fw_server s, int64_t id, void *dst, int64_t ld_dst, void *stream);
+
+/* Return a finished kept request's memory to the budget. */
+int fw_server_release(fw_server s, int64_t id);
+
+/* Wait until every submitted request has completed (timeout_us < 0: no limit);
+ * FW_ERR_BUSY on timeout. */
+int fw_server_drain(fw_server s, int64_t timeout_us);
+
+int fw_server_get_stats(fw_server s, fw_server_stats *out);
+
+/* Cancel requests not yet admitted (status FW_ERR_BUSY), finish the running
+ * ones, join the threads and free everything. */
+int fw_server_destroy(fw_server s);
+
+/*
  * fw_negative_cycle -- after a solve, write 1 to *flag_dev (device int32) if
  * some d_ii < 0 (a negative cycle through i, section 3.1's excluded case),
  * else 0.  Stream-ordered.

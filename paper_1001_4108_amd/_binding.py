@@ -50,6 +50,25 @@ def lib() -> ctypes.CDLL:
     return _lib
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("streams", ctypes.c_int),
+                ("budget_bytes", ctypes.c_int64), ("small_n", ctypes.c_int64),
+                ("max_batch", ctypes.c_int), ("queue_cap", ctypes.c_int64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("n", ctypes.c_int64), ("status", ctypes.c_int),
+                ("group_size", ctypes.c_int), ("t_submit_ns", ctypes.c_int64),
+                ("t_admit_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "submitted", "admitted", "completed", "failed", "rejected", "deferrals",
+        "batched_groups", "single_groups", "max_group", "waiting", "bytes_in_use",
+        "peak_bytes", "budget_bytes")]
+
+
 def _declare(L):
     vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     P64 = ctypes.POINTER(ctypes.c_int64)
@@ -73,6 +92,14 @@ def _declare(L):
         "fw_batch_plan_destroy": ([vp], ci),
         "fw_batch_plan_grid": ([vp], i64),
         "fw_negative_cycle": ([vp, ci, i64, i64, vp, vp], ci),
+        "fw_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)], ci),
+        "fw_server_submit": ([vp, vp, i64, i64, vp, i64, ci, P64], ci),
+        "fw_server_poll": ([vp, ctypes.POINTER(Completion), ci, i64], ci),
+        "fw_server_fetch": ([vp, i64, vp, i64, vp], ci),
+        "fw_server_release": ([vp, i64], ci),
+        "fw_server_drain": ([vp, i64], ci),
+        "fw_server_get_stats": ([vp, ctypes.POINTER(ServerStats)], ci),
+        "fw_server_destroy": ([vp], ci),
         "fw_path": ([vp, i64, i64, i64, i64, P64, i64], i64),
         "fw_profile_enable": ([ci], ci),
         "fw_profile_read": ([ctypes.POINTER(ctypes.c_double), P64, ci], ci),
@@ -320,3 +347,86 @@ def profile_read():
     upd = (ctypes.c_double * 8)()
     lib().fw_profile_updates(upd, 8)
     return {KINDS[i]: (ms[i], cnt[i], upd[i]) for i in range(k)}
+
+
+class Server:
+    """Continuous-batching APSP server (fw_server_*): footprint admission into a
+    device budget, persistent batched launches for small requests, single-graph
+    stage loops for large ones, overlapped on several worker streams."""
+
+    def __init__(self, dtype=torch.float32, budget_bytes: int = 8 << 30, streams: int = 4,
+                 small_n: int = 512, max_batch: int = 1024, queue_cap: int = 1 << 20,
+                 device=None):
+        self.dtype = dtype
+        self.device = torch.device(device) if device is not None else \
+            torch.device("cuda", torch.cuda.current_device())
+        code = FW_F32 if dtype == torch.float32 else FW_I32
+        cfg = ServerConfig(code, streams, int(budget_bytes), int(small_n), int(max_batch),
+                           int(queue_cap))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().fw_server_create(ctypes.byref(cfg), ctypes.byref(h)), "fw_server_create")
+        self._h = h
+        self._buf = (Completion * 4096)()
+
+    def submit(self, src: torch.Tensor, keep: bool = False, dst_host=None) -> int:
+        """Queue APSP on the square matrix view ``src`` (device or host)."""
+        if src.dtype != self.dtype:
+            raise TypeError("request dtype differs from the server's")
+        if src.dim() != 2 or src.shape[0] != src.shape[1]:
+            raise ValueError("square matrix expected")
+        n = src.shape[0]
+        if n > 1 and src.stride(1) != 1:
+            raise ValueError("row-major matrix expected")
+        ld = max(src.stride(0), n) if n else 0
+        dptr, dld = None, 0
+        if dst_host is not None:
+            dptr, dld = dst_host.data_ptr(), max(dst_host.stride(0), n)
+        rid = ctypes.c_int64()
+        _check(lib().fw_server_submit(self._h, src.data_ptr() if n else None, n, ld, dptr, dld,
+                                      1 if keep else 0, ctypes.byref(rid)), "fw_server_submit")
+        return rid.value
+
+    def poll(self, timeout_us: int = 0):
+        k = lib().fw_server_poll(self._h, self._buf, len(self._buf), int(timeout_us))
+        if k < 0:
+            raise FwError(-k, "fw_server_poll")
+        return [(c.id, c.n, c.status, c.group_size, c.t_submit_ns, c.t_admit_ns, c.t_done_ns)
+                for c in self._buf[:k]]
+
+    def fetch(self, rid: int, dst: torch.Tensor, stream=None) -> torch.Tensor:
+        with torch.cuda.device(self.device):
+            _check(lib().fw_server_fetch(self._h, int(rid), dst.data_ptr(),
+                                         max(dst.stride(0), dst.shape[0]),
+                                         _stream(dst, stream) if dst.is_cuda else None),
+                   "fw_server_fetch")
+        return dst
+
+    def release(self, rid: int) -> None:
+        _check(lib().fw_server_release(self._h, int(rid)), "fw_server_release")
+
+    def drain(self, timeout_s: float = -1.0) -> None:
+        us = -1 if timeout_s < 0 else int(timeout_s * 1e6)
+        _check(lib().fw_server_drain(self._h, us), "fw_server_drain")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().fw_server_get_stats(self._h, ctypes.byref(st)), "fw_server_get_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self) -> None:
+        if self._h is not None:
+            lib().fw_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

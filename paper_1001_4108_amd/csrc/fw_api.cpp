@@ -196,11 +196,6 @@ int validate_matrix(const void *d, int dtype, int64_t n, int64_t ld, const int32
     return validate(d, dtype, n, ld, pred, ldp);
 }
 
-struct BatchHeader;
-struct BatchItem;
-hipError_t launch_batched_raw(int dtype, bool pred, BatchHeader *hdr, const BatchItem *items,
-                              int grid, hipStream_t st);
-
 hipError_t timed_launch_batched(double updates, hipStream_t st, int dtype, bool pred,
                                 BatchHeader *hdr, const BatchItem *items, int grid) {
     return timed(kBatched, updates, st,

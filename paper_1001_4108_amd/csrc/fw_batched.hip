@@ -24,20 +24,6 @@
 
 namespace fw {
 
-struct BatchItem {
-    void *d;
-    int32_t *p;
-    int64_t ld, ldp;
-    int32_t n, tile;
-    int32_t vec, pad;
-};
-
-struct BatchHeader {
-    int32_t next;   // work counter, 0 at launch
-    int32_t count;  // number of items
-    int32_t pad[14];
-};
-
 static_assert(sizeof(BatchHeader) == 64, "header keeps items 64-byte aligned");
 
 namespace {
@@ -172,6 +158,20 @@ int resident_grid(int dtype, bool pred) {
 
 }  // namespace
 
+int batched_resident_grid(int dtype, bool pred) { return resident_grid(dtype, pred); }
+
+void fill_batch_item(BatchItem &it, void *d, int dtype, int64_t n, int64_t ld, int32_t *p,
+                     int64_t ldp) {
+    it.d = d;
+    it.p = p;
+    it.ld = ld;
+    it.ldp = p ? ldp : 0;
+    it.n = (int32_t)n;
+    it.tile = n > 1 ? plan_tile_for(dtype, n) : 32;
+    it.vec = vec_ok(d, ld) && (!p || vec_ok(p, ldp)) ? 1 : 0;
+    it.pad = 0;
+}
+
 hipError_t launch_batched_raw(int dtype, bool pred, BatchHeader *hdr, const BatchItem *items,
                               int grid, hipStream_t st) {
     if (dtype == FW_F32) {
@@ -188,12 +188,7 @@ hipError_t launch_batched_raw(int dtype, bool pred, BatchHeader *hdr, const Batc
     return hipGetLastError();
 }
 
-// Library-internal helpers defined in fw_api.cpp.
-int plan_tile_for(int dtype, int64_t n);
-int solve_single(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64_t ldp,
-                 hipStream_t st);
-int validate_matrix(const void *d, int dtype, int64_t n, int64_t ld, const int32_t *pred,
-                    int64_t ldp);
+// Defined in fw_api.cpp.
 hipError_t timed_launch_batched(double updates, hipStream_t st, int dtype, bool pred,
                                 BatchHeader *hdr, const BatchItem *items, int grid);
 
@@ -235,15 +230,7 @@ int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t coun
         int s = validate_matrix(d[g], dtype, n[g], ld[g], pg, ldp);
         if (s != FW_OK) return s;
         if (n[g] > fw_batched_max_n(dtype, pg != nullptr)) return FW_ERR_UNSUPPORTED;
-        BatchItem &it = items[(size_t)g];
-        it.d = d[g];
-        it.p = pg;
-        it.ld = ld[g];
-        it.ldp = ldp;
-        it.n = (int32_t)n[g];
-        it.tile = n[g] > 1 ? plan_tile_for(dtype, n[g]) : 32;
-        it.vec = vec_ok(d[g], ld[g]) && (!pg || vec_ok(pg, ldp)) ? 1 : 0;
-        it.pad = 0;
+        fill_batch_item(items[(size_t)g], d[g], dtype, n[g], ld[g], pg, ldp);
         any_pred |= pg != nullptr;
         upd += (double)n[g] * (double)n[g] * (double)n[g];
     }

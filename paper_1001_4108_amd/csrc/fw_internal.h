@@ -28,6 +28,35 @@ hipError_t launch_pred_fix(int dtype, const void *d, int32_t *p, int n, int64_t 
 hipError_t launch_negcycle(int dtype, const void *d, int n, int64_t ld, int32_t *flag,
                            hipStream_t st);
 
+// Descriptor of one graph of a persistent batched launch.
+struct BatchItem {
+    void *d;
+    int32_t *p;
+    int64_t ld, ldp;
+    int32_t n, tile;
+    int32_t vec, pad;
+};
+
+// Head of a batched descriptor table (the items follow it).
+struct BatchHeader {
+    int32_t next;   // work counter, 0 at launch
+    int32_t count;  // number of items
+    int32_t pad[14];
+};
+
+// Persistent batched kernel (fw_batched.hip) and host helpers (fw_api.cpp)
+// shared by the batch plans and the server.
+hipError_t launch_batched_raw(int dtype, bool pred, BatchHeader *hdr, const BatchItem *items,
+                              int grid, hipStream_t st);
+int batched_resident_grid(int dtype, bool pred);
+void fill_batch_item(BatchItem &it, void *d, int dtype, int64_t n, int64_t ld, int32_t *p,
+                     int64_t ldp);
+int plan_tile_for(int dtype, int64_t n);
+int validate_matrix(const void *d, int dtype, int64_t n, int64_t ld, const int32_t *pred,
+                    int64_t ldp);
+int solve_single(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64_t ldp,
+                 hipStream_t st);
+
 // True when the vectorised (16-byte) load/store path may be used for a
 // matrix: 16-byte aligned base and a leading dimension divisible by 4.
 inline bool vec_ok(const void *ptr, int64_t ld) {
