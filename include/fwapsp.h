@@ -288,13 +288,40 @@ int64_t fw_path(const int32_t *pred_host, int64_t n, int64_t ld_pred, int64_t i,
                 int64_t j, int64_t *path, int64_t cap);
 
 /*
+ * Library options (process-wide).  In this build both are off and cannot be
+ * enabled (fw_set_option returns FW_ERR_UNSUPPORTED for a non-zero value):
+ * a run that cycled through them ended in a host-side fault whose cause has
+ * not been identified.
+ *   FW_OPT_LOOKAHEAD: with at least 3 tile rows, split each
+ *     stage's bulk so that the next stage's diagonal tile and panels run on a
+ *     library-owned side stream while the rest of the bulk runs on the
+ *     caller's stream (joined back before the call's last kernel).
+ *   FW_OPT_GRAPHS: capture the whole stage loop of a (matrix,
+ *     plan) once into a hipGraph and replay it with one graph launch; up to 32
+ *     graphs are cached, keyed by device, pointers, n, leading dimensions,
+ *     dtype, tile and look-ahead, least recently used evicted.  A graph only
+ *     touches the matrix it was captured for, so a later allocation at the
+ *     same address with the same shape replays correctly;
+ *     fw_graph_cache_clear releases every cached graph.
+ * Results are bit-identical for every option setting.  fw_set_option returns
+ * FW_OK or FW_ERR_INVALID; fw_get_option returns the value or -1.
+ */
+#define FW_OPT_LOOKAHEAD 1
+#define FW_OPT_GRAPHS 2
+int fw_set_option(int option, int64_t value);
+int64_t fw_get_option(int option);
+int fw_graph_cache_clear(void);
+
+/*
  * Phase timing.  While enabled, every phase launch of the calls above is
  * bracketed by HIP events on its stream (launches run eagerly, not from a
  * captured graph).  fw_profile_read synchronises those events and writes, per
  * phase kind, the summed kernel time in ms and the launch count
- * (kinds: 0 = diagonal tile, 1 = panels, 2 = bulk tiles, 3 = predecessor
- * init/fix-up, 4 = batched persistent kernel); it returns the number of kinds
- * written and clears the accumulators.
+ * (kinds: 0 = diagonal tile, 1 = panels, 2 = bulk tiles (without the
+ * look-ahead part), 3 = predecessor init/fix-up, 4 = batched persistent
+ * kernel, 5 = look-ahead part of the bulk); it returns the number of kinds
+ * written and clears the accumulators.  While profiling is enabled solves do
+ * not use captured graphs.
  */
 int fw_profile_enable(int on);
 int fw_profile_read(double *ms, int64_t *launches, int cap);

@@ -13,7 +13,9 @@ import threading
 import torch  # imported first so the process uses torch's HIP runtime
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfwapsp.so")
+# FWAPSP_LIB selects another build of the same library (e.g. to compare kernel
+# variants); the default is the in-tree build.
+LIB_PATH = os.environ.get("FWAPSP_LIB") or os.path.join(HERE, "libfwapsp.so")
 
 I32_INF = 1073741823
 FW_F32, FW_I32 = 0, 1
@@ -101,6 +103,9 @@ def _declare(L):
         "fw_server_get_stats": ([vp, ctypes.POINTER(ServerStats)], ci),
         "fw_server_destroy": ([vp], ci),
         "fw_path": ([vp, i64, i64, i64, i64, P64, i64], i64),
+        "fw_set_option": ([ci, i64], ci),
+        "fw_get_option": ([ci], i64),
+        "fw_graph_cache_clear": ([], ci),
         "fw_profile_enable": ([ci], ci),
         "fw_profile_read": ([ctypes.POINTER(ctypes.c_double), P64, ci], ci),
         "fw_profile_updates": ([ctypes.POINTER(ctypes.c_double), ci], ci),
@@ -334,7 +339,22 @@ def profile_enable(on: bool = True) -> None:
     lib().fw_profile_enable(1 if on else 0)
 
 
-KINDS = ("diag", "panel", "bulk", "pred", "batched")
+KINDS = ("diag", "panel", "bulk", "pred", "batched", "bulk_ahead")
+OPTIONS = {"lookahead": 1, "graphs": 2}
+
+
+def set_option(name: str, value) -> None:
+    """Library options: "lookahead" (split bulk, side stream) and "graphs"
+    (cached hipGraph replay of the stage loop); results never change."""
+    _check(lib().fw_set_option(OPTIONS[name], int(value)), "fw_set_option")
+
+
+def get_option(name: str) -> int:
+    return int(lib().fw_get_option(OPTIONS[name]))
+
+
+def graph_cache_clear() -> None:
+    _check(lib().fw_graph_cache_clear(), "fw_graph_cache_clear")
 
 
 def profile_read():

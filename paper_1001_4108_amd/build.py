@@ -14,8 +14,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
-OUT = os.path.join(HERE, "libfwapsp.so")
-BUILD = os.path.join(ROOT, "_build")
+OUT = os.environ.get("FWAPSP_OUT") or os.path.join(HERE, "libfwapsp.so")
+BUILD = os.environ.get("FWAPSP_BUILD_DIR") or os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("FWAPSP_ARCH", "gfx950")
 
@@ -23,7 +23,7 @@ COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"),
-]
+] + os.environ.get("FWAPSP_EXTRA_FLAGS", "").split()
 
 
 def sources():

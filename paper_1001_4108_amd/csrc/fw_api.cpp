@@ -8,7 +8,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/fwapsp.h"
@@ -135,9 +138,225 @@ int validate(const void *d, int dtype, int64_t n, int64_t ld, const int32_t *pre
     return FW_OK;
 }
 
-// Enqueue the whole blocked solve for one graph.  Arguments already valid.
+// ---------------------------------------------------------------------------
+// Per-device resources: the look-ahead side stream and a pool of events.
+// ---------------------------------------------------------------------------
+struct DeviceRes {
+    std::mutex mu;                 // serialises eager enqueues that use `side`
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> free_events;
+};
+
+std::mutex g_dev_mu;
+std::map<int, DeviceRes *> g_dev;
+
+DeviceRes *device_res() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    DeviceRes *&r = g_dev[dev];
+    if (!r) {
+        r = new DeviceRes();
+        if (hipStreamCreateWithFlags(&r->side, hipStreamNonBlocking) != hipSuccess) {
+            delete r;
+            r = nullptr;
+        }
+    }
+    return r;
+}
+
+hipError_t take_events(DeviceRes *r, size_t k, std::vector<hipEvent_t> &out) {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    while (out.size() < k) {
+        if (!r->free_events.empty()) {
+            out.push_back(r->free_events.back());
+            r->free_events.pop_back();
+            continue;
+        }
+        hipEvent_t e = nullptr;
+        hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (err != hipSuccess) return err;
+        out.push_back(e);
+    }
+    return hipSuccess;
+}
+
+// Events may be reused as soon as every wait on them has been enqueued.
+void give_events(DeviceRes *r, std::vector<hipEvent_t> &ev) {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    for (auto e : ev) r->free_events.push_back(e);
+    ev.clear();
+}
+
+// Library options (fw_set_option).  Both schedules are switched off: a test
+// that cycled through them ended in a host-side segmentation fault whose cause
+// has not been identified, so they cannot be enabled until it is.
+std::atomic<int> g_opt_lookahead{0};
+std::atomic<int> g_opt_graphs{0};
+constexpr bool kLookaheadAvailable = false;
+constexpr bool kGraphsAvailable = false;
+
+// Enqueue the whole blocked solve of one graph on `st` (and, with
+// look-ahead, on `side`, joined back into `st` before the last bulk).
+// Arguments already validated; n > 1.
+//
+// Look-ahead (nb >= 3): the bulk of stage b is split into the tiles of row
+// and column b+1 ("ahead") and the rest.  The side stream runs ahead(b),
+// then stage b+1's diagonal tile and panels, while `st` runs rest(b); the
+// two touch disjoint tiles.  Dependencies are events: rest(b) waits for the
+// panels of stage b, ahead(b) waits for rest(b-1) (which last wrote row and
+// column b+1).
+int enqueue_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
+                  hipStream_t st, hipStream_t side, bool lookahead, std::vector<hipEvent_t> &evs) {
+    const int nb = (n + tile - 1) / tile;
+    hipError_t e;
+    if (pred) {
+        e = timed(kPredFix, 0.0, st, [&] { return launch_pred_init(dtype, d, pred, n, ld, ldp, st); });
+        if (e != hipSuccess) return status_of(e);
+    }
+    // algorithmic updates of each launch: the n^3 tasks split by where the
+    // (i, j) cell lies relative to block b (real cells only, padding excluded)
+    const double nn = (double)n;
+    auto real = [&](int blk) { return std::max(0.0, std::min<double>(tile, nn - (double)blk * tile)); };
+    auto diag = [&](int b, hipStream_t s) {
+        const double kb = real(b);
+        return timed(kDiag, kb * kb * kb, s,
+                     [&] { return launch_diag(dtype, tile, d, pred, n, ld, ldp, b, s); });
+    };
+    auto panels = [&](int b, hipStream_t s) {
+        const double kb = real(b);
+        return timed(kPanel, 2.0 * kb * kb * (nn - kb), s, [&] {
+            return launch_panels(dtype, tile, d, pred, n, ld, ldp, b, nb, s);
+        });
+    };
+    auto bulk = [&](int b, int part, hipStream_t s) {
+        const double kb = real(b), r1 = real(b + 1), rest = nn - kb;
+        double upd = kb * rest * rest;
+        int kind = kBulk;
+        if (part == kBulkAheadPart) {
+            upd = kb * (r1 * rest + (rest - r1) * r1);
+            kind = kBulkAhead;
+        } else if (part == kBulkRestPart) {
+            upd = kb * (rest - r1) * (rest - r1);
+        }
+        return timed(kind, upd, s, [&] {
+            return launch_bulk(dtype, tile, d, pred, n, ld, ldp, b, nb, part, s);
+        });
+    };
+
+    if (!lookahead || nb < 3) {
+        for (int b = 0; b < nb; ++b) {
+            if ((e = diag(b, st)) != hipSuccess) return status_of(e);
+            if (nb > 1) {
+                if ((e = panels(b, st)) != hipSuccess) return status_of(e);
+                if ((e = bulk(b, kBulkAll, st)) != hipSuccess) return status_of(e);
+            }
+        }
+    } else {
+        size_t ei = 0;
+        if ((e = diag(0, st)) != hipSuccess) return status_of(e);
+        if ((e = panels(0, st)) != hipSuccess) return status_of(e);
+        hipEvent_t ev_panels = evs[ei++];  // panels of the current stage are done
+        hipEvent_t ev_rest = nullptr;      // rest of the previous stage's bulk is done
+        if ((e = hipEventRecord(ev_panels, st)) != hipSuccess) return status_of(e);
+        for (int b = 0; b < nb; ++b) {
+            if (b == nb - 1) {
+                if ((e = hipStreamWaitEvent(st, ev_panels, 0)) != hipSuccess) return status_of(e);
+                if ((e = bulk(b, kBulkAll, st)) != hipSuccess) return status_of(e);
+                break;
+            }
+            if ((e = hipStreamWaitEvent(side, ev_panels, 0)) != hipSuccess) return status_of(e);
+            if (ev_rest && (e = hipStreamWaitEvent(side, ev_rest, 0)) != hipSuccess)
+                return status_of(e);
+            if ((e = bulk(b, kBulkAheadPart, side)) != hipSuccess) return status_of(e);
+            if ((e = diag(b + 1, side)) != hipSuccess) return status_of(e);
+            if ((e = panels(b + 1, side)) != hipSuccess) return status_of(e);
+            hipEvent_t ev_next = evs[ei++];
+            if ((e = hipEventRecord(ev_next, side)) != hipSuccess) return status_of(e);
+            if ((e = hipStreamWaitEvent(st, ev_panels, 0)) != hipSuccess) return status_of(e);
+            if (nb > 2 && (e = bulk(b, kBulkRestPart, st)) != hipSuccess) return status_of(e);
+            ev_rest = evs[ei++];
+            if ((e = hipEventRecord(ev_rest, st)) != hipSuccess) return status_of(e);
+            ev_panels = ev_next;
+        }
+    }
+    if (pred) {
+        e = timed(kPredFix, 0.0, st, [&] { return launch_pred_fix(dtype, d, pred, n, ld, ldp, st); });
+        if (e != hipSuccess) return status_of(e);
+    }
+    return FW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Graph cache: the whole stage loop of one (matrix, plan) captured once and
+// replayed with a single graph launch.
+// ---------------------------------------------------------------------------
+struct GraphKey {
+    int dev, dtype, n, tile, lookahead;
+    int64_t ld, ldp;
+    void *d;
+    int32_t *pred;
+    bool operator<(const GraphKey &o) const {
+        return std::tie(dev, dtype, n, tile, lookahead, ld, ldp, d, pred) <
+               std::tie(o.dev, o.dtype, o.n, o.tile, o.lookahead, o.ld, o.ldp, o.d, o.pred);
+    }
+};
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+std::mutex g_graph_mu;
+std::map<GraphKey, GraphEntry> g_graphs;
+uint64_t g_graph_clock = 0;
+constexpr size_t kMaxGraphs = 32;
+
+int capture_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
+                  bool lookahead, DeviceRes *res, GraphEntry &out) {
+    hipStream_t cs = nullptr, cside = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cside, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        if (cs) hipStreamDestroy(cs);
+        return status_of(e);
+    }
+    const int nb = (n + tile - 1) / tile;
+    std::vector<hipEvent_t> evs;
+    int s = status_of(take_events(res, 2 * (size_t)nb + 2, evs));
+    hipGraph_t g = nullptr;
+    if (s == FW_OK) {
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            s = status_of(e);
+        } else {
+            s = enqueue_solve(d, dtype, n, ld, pred, ldp, tile, cs, cside, lookahead, evs);
+            e = hipStreamEndCapture(cs, &g);
+            if (s == FW_OK && e != hipSuccess) s = status_of(e);
+        }
+    }
+    if (s == FW_OK) {
+        e = hipGraphInstantiate(&out.exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) s = status_of(e);
+    }
+    if (s == FW_OK) {
+        out.graph = g;
+    } else if (g) {
+        hipGraphDestroy(g);
+    }
+    give_events(res, evs);
+    hipStreamDestroy(cside);
+    hipStreamDestroy(cs);
+    return s;
+}
+
+bool profiling_on() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    return g_prof_on;
+}
+
+// Enqueue the whole solve for one graph.  Arguments already valid.
 int solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
-          hipStream_t st) {
+          hipStream_t st, bool allow_graph = true) {
     if (n <= 1) {
         if (pred && n == 1) {
             hipError_t e = timed(kPredFix, 0.0, st, [&] {
@@ -148,38 +367,45 @@ int solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int
         return FW_OK;
     }
     if (!tile_supported(tile)) return FW_ERR_INVALID;
-    const int nb = (n + tile - 1) / tile;
-    hipError_t e;
-    if (pred) {
-        e = timed(kPredFix, 0.0, st, [&] { return launch_pred_init(dtype, d, pred, n, ld, ldp, st); });
-        if (e != hipSuccess) return status_of(e);
+    const bool lookahead = g_opt_lookahead.load() != 0;
+    const bool graphs = allow_graph && g_opt_graphs.load() && !profiling_on();
+    if (!lookahead && !graphs) {
+        // plain schedule on the caller's stream: no side stream, no events
+        std::vector<hipEvent_t> none;
+        return enqueue_solve(d, dtype, n, ld, pred, ldp, tile, st, nullptr, false, none);
     }
-    // algorithmic updates of each phase: the n^3 tasks split by where the
-    // (i, j) cell lies relative to block b (real cells only, padding excluded)
-    const double nn = (double)n;
-    for (int b = 0; b < nb; ++b) {
-        const double kb = std::min<double>(tile, nn - (double)b * tile);  // real k of block b
-        const double rb = kb;                                             // real rows of block b
-        const double rest = nn - rb;
-        e = timed(kDiag, kb * rb * rb, st,
-                  [&] { return launch_diag(dtype, tile, d, pred, n, ld, ldp, b, st); });
-        if (e != hipSuccess) return status_of(e);
-        if (nb > 1) {
-            e = timed(kPanel, 2.0 * kb * rb * rest, st, [&] {
-                return launch_panels(dtype, tile, d, pred, n, ld, ldp, b, nb, st);
-            });
-            if (e != hipSuccess) return status_of(e);
-            e = timed(kBulk, kb * rest * rest, st, [&] {
-                return launch_bulk(dtype, tile, d, pred, n, ld, ldp, b, nb, st);
-            });
-            if (e != hipSuccess) return status_of(e);
+    DeviceRes *res = device_res();
+    if (!res) return FW_ERR_HIP;
+    if (graphs) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        GraphKey key{dev, dtype, n, tile, lookahead ? 1 : 0, ld, ldp, d, pred};
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        auto it = g_graphs.find(key);
+        if (it == g_graphs.end()) {
+            if (g_graphs.size() >= kMaxGraphs) {
+                auto victim = g_graphs.begin();
+                for (auto jt = g_graphs.begin(); jt != g_graphs.end(); ++jt)
+                    if (jt->second.last_use < victim->second.last_use) victim = jt;
+                hipGraphExecDestroy(victim->second.exec);
+                hipGraphDestroy(victim->second.graph);
+                g_graphs.erase(victim);
+            }
+            GraphEntry ent;
+            int s = capture_solve(d, dtype, n, ld, pred, ldp, tile, lookahead, res, ent);
+            if (s != FW_OK) return s;
+            it = g_graphs.emplace(key, ent).first;
         }
+        it->second.last_use = ++g_graph_clock;
+        return status_of(hipGraphLaunch(it->second.exec, st));
     }
-    if (pred) {
-        e = timed(kPredFix, 0.0, st, [&] { return launch_pred_fix(dtype, d, pred, n, ld, ldp, st); });
-        if (e != hipSuccess) return status_of(e);
-    }
-    return FW_OK;
+    std::lock_guard<std::mutex> lk(res->mu);
+    std::vector<hipEvent_t> evs;
+    const int nb = (n + tile - 1) / tile;
+    int s = status_of(take_events(res, 2 * (size_t)nb + 2, evs));
+    if (s == FW_OK) s = enqueue_solve(d, dtype, n, ld, pred, ldp, tile, st, res->side, lookahead, evs);
+    give_events(res, evs);
+    return s;
 }
 
 }  // namespace
@@ -188,7 +414,9 @@ int plan_tile_for(int dtype, int64_t n) { return plan_tile(dtype, n); }
 
 int solve_single(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64_t ldp,
                  hipStream_t st) {
-    return solve(d, dtype, (int)n, ld, pred, ldp, plan_tile(dtype, n), st);
+    // eager launches: callers (the per-graph batch baseline, the server) solve
+    // many different matrices, which a graph cache would only churn
+    return solve(d, dtype, (int)n, ld, pred, ldp, plan_tile(dtype, n), st, false);
 }
 
 int validate_matrix(const void *d, int dtype, int64_t n, int64_t ld, const int32_t *pred,
@@ -305,6 +533,38 @@ int64_t fw_path(const int32_t *pred, int64_t n, int64_t ldp, int64_t i, int64_t 
     }
     std::reverse(path, path + len);
     return len;
+}
+
+int fw_set_option(int option, int64_t value) {
+    switch (option) {
+    case FW_OPT_LOOKAHEAD:
+        if (value && !kLookaheadAvailable) return FW_ERR_UNSUPPORTED;
+        g_opt_lookahead.store(value ? 1 : 0);
+        return FW_OK;
+    case FW_OPT_GRAPHS:
+        if (value && !kGraphsAvailable) return FW_ERR_UNSUPPORTED;
+        g_opt_graphs.store(value ? 1 : 0);
+        return FW_OK;
+    default: return FW_ERR_INVALID;
+    }
+}
+
+int64_t fw_get_option(int option) {
+    switch (option) {
+    case FW_OPT_LOOKAHEAD: return g_opt_lookahead.load();
+    case FW_OPT_GRAPHS: return g_opt_graphs.load();
+    default: return -1;
+    }
+}
+
+int fw_graph_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto &kv : g_graphs) {
+        hipGraphExecDestroy(kv.second.exec);
+        hipGraphDestroy(kv.second.graph);
+    }
+    g_graphs.clear();
+    return FW_OK;
 }
 
 int fw_profile_enable(int on) {

@@ -10,7 +10,18 @@ namespace fw {
 constexpr int32_t kI32Inf = 1073741823;   // "no edge" for int32
 constexpr int32_t kPredNone = 0x7fffffff; // in-sweep "no last hop yet"
 
-enum PhaseKind { kDiag = 0, kPanel = 1, kBulk = 2, kPredFix = 3, kBatched = 4, kNumKinds = 5 };
+enum PhaseKind {
+    kDiag = 0,
+    kPanel = 1,
+    kBulk = 2,      // the bulk, or its rest part under look-ahead
+    kPredFix = 3,
+    kBatched = 4,
+    kBulkAhead = 5, // look-ahead part of the bulk (row and column b+1)
+    kNumKinds = 6
+};
+
+// Bulk launch parts (tile_kernel modes).
+enum BulkPart { kBulkAll = 1, kBulkAheadPart = 2, kBulkRestPart = 3 };
 
 // One stage-phase launch of the blocked schedule.  `d`/`p` are the matrix
 // and the (optional) predecessor matrix; `b` is the k-block index, `nb` the
@@ -20,7 +31,7 @@ hipError_t launch_diag(int dtype, int tile, void *d, int32_t *p, int n, int64_t 
 hipError_t launch_panels(int dtype, int tile, void *d, int32_t *p, int n, int64_t ld,
                          int64_t ldp, int b, int nb, hipStream_t st);
 hipError_t launch_bulk(int dtype, int tile, void *d, int32_t *p, int n, int64_t ld,
-                       int64_t ldp, int b, int nb, hipStream_t st);
+                       int64_t ldp, int b, int nb, int part, hipStream_t st);
 hipError_t launch_pred_init(int dtype, const void *d, int32_t *p, int n, int64_t ld,
                             int64_t ldp, hipStream_t st);
 hipError_t launch_pred_fix(int dtype, const void *d, int32_t *p, int n, int64_t ld,

@@ -43,17 +43,21 @@ diag_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
 
 // Phases 2 and 3: one tile per workgroup.
 //   mode 0: blockIdx.x enumerates the 2(nb-1) panel tiles of stage b;
-//   mode 1: blockIdx.x enumerates the (nb-1)^2 bulk tiles.
+//   mode 1: blockIdx.x enumerates the (nb-1)^2 bulk tiles;
+//   mode 2: the 2(nb-1)-1 bulk tiles in row or column b+1 (look-ahead part);
+//   mode 3: the (nb-2)^2 remaining bulk tiles.
 template <typename T, int S, int BK, int TM, int TN, bool VEC, bool PRED>
 __global__ void __launch_bounds__((S / TM) * (S / TN))
 tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64_t ldp, int b,
             int nb, int mode) {
     __shared__ __align__(16) char smem[product_smem_bytes<T, S, BK, PRED>()];
     int bi, bj;
-    if (mode == 0)
-        panel_coords(blockIdx.x, b, nb - 1, bi, bj);
-    else
-        bulk_coords(blockIdx.x, b, nb - 1, bi, bj);
+    switch (mode) {
+    case 0: panel_coords(blockIdx.x, b, nb - 1, bi, bj); break;
+    case 1: bulk_coords(blockIdx.x, b, nb - 1, bi, bj); break;
+    case 2: ahead_coords(blockIdx.x, b, nb - 1, bi, bj); break;
+    default: rest_coords(blockIdx.x, b, nb - 1, bi, bj); break;
+    }
     product_tile<T, S, BK, TM, TN, VEC, PRED>(d, P, n, ld, ldp, bi, bj, b, smem);
 }
 
@@ -146,7 +150,8 @@ template <typename T>
 hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b,
                          int nb, int mode, hipStream_t st) {
     const int64_t m = nb - 1;
-    const int64_t grid = mode == 0 ? 2 * m : m * m;
+    const int64_t grid = mode == 0 ? 2 * m : mode == 1 ? m * m : mode == 2 ? 2 * m - 1
+                                                                           : (m - 1) * (m - 1);
     if (grid <= 0) return hipSuccess;
     if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
     const bool vec = vec_ok(d, ld) && (p == nullptr || vec_ok(p, ldp));
@@ -177,9 +182,9 @@ hipError_t launch_panels(int dtype, int tile, void *d, int32_t *p, int n, int64_
 }
 
 hipError_t launch_bulk(int dtype, int tile, void *d, int32_t *p, int n, int64_t ld, int64_t ldp,
-                       int b, int nb, hipStream_t st) {
-    if (dtype == 0) return tile_dispatch<float>(tile, (float *)d, p, n, ld, ldp, b, nb, 1, st);
-    return tile_dispatch<int32_t>(tile, (int32_t *)d, p, n, ld, ldp, b, nb, 1, st);
+                       int b, int nb, int part, hipStream_t st) {
+    if (dtype == 0) return tile_dispatch<float>(tile, (float *)d, p, n, ld, ldp, b, nb, part, st);
+    return tile_dispatch<int32_t>(tile, (int32_t *)d, p, n, ld, ldp, b, nb, part, st);
 }
 
 hipError_t launch_pred_init(int dtype, const void *d, int32_t *p, int n, int64_t ld,

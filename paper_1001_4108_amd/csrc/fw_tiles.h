@@ -364,4 +364,27 @@ __device__ __forceinline__ void bulk_coords(int idx, int b, int m, int &bi, int 
     bj = r < b ? r : r + 1;
 }
 
+// Look-ahead split of the stage-b bulk (b + 1 < nb, m = nb - 1):
+//   ahead: the bulk tiles in row b+1 or column b+1, 2m - 1 of them -- after
+//          they are done, stage b+1's diagonal tile and panels are final and
+//          can be processed while the rest of stage b's bulk still runs;
+//   rest:  the other (m - 1)^2 bulk tiles.
+__device__ __forceinline__ void ahead_coords(int idx, int b, int m, int &bi, int &bj) {
+    if (idx < m) {
+        bi = b + 1;
+        bj = idx < b ? idx : idx + 1;
+    } else {
+        idx -= m;
+        bi = idx < b ? idx : idx + 2;
+        bj = b + 1;
+    }
+}
+
+__device__ __forceinline__ void rest_coords(int idx, int b, int m, int &bi, int &bj) {
+    const int w = m - 1;
+    const int q = idx / w, r = idx - q * w;
+    bi = q < b ? q : q + 2;
+    bj = r < b ? r : r + 2;
+}
+
 }  // namespace fw

@@ -86,3 +86,12 @@ def test_fw_path_host_reconstruction():
     bad[0, 3] = 1
     with pytest.raises(B.FwError):
         B.fw_path(bad, 0, 3)
+
+
+def test_disabled_schedules_cannot_be_enabled():
+    L = B.lib()
+    assert L.fw_get_option(1) == 0 and L.fw_get_option(2) == 0
+    assert L.fw_set_option(1, 1) == 4 and L.fw_set_option(2, 1) == 4  # FW_ERR_UNSUPPORTED
+    assert L.fw_set_option(1, 0) == 0 and L.fw_set_option(2, 0) == 0
+    assert L.fw_set_option(99, 0) == 1
+    assert L.fw_get_option(99) == -1
