@@ -39,6 +39,37 @@ UPDATE_PEAK = VALU_LANE_OPS_PER_S / MIN_INSTR_PER_UPDATE
 ONE_INSTR_64LANE_PEAK = 256 * 64 * 2.4e9
 
 
+PROFILE = os.path.join(ROOT, "profiles", "tile_kernel_bulk_f32_t128_n16384.md")
+KERNEL_SOURCES = ("paper_1001_4108_amd/csrc/fw_tiles.h", "paper_1001_4108_amd/csrc/fw_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per bulk launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (already scaled by the copy-kernel calibration), or
+    None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.split(":", 1)[0].strip() in (
+                "kernel_source_sha256", "bulk_fetch_bytes_per_launch",
+                "bulk_write_bytes_per_launch"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if vals.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    try:
+        return float(vals["bulk_fetch_bytes_per_launch"]) + float(vals["bulk_write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,7 +328,9 @@ def main():
             ach = per_launch_upd / per_launch_s
             roof = {"bound": "alu", "kernel": "tile_kernel (bulk, mode 1)",
                     "achieved": ach / 1e12, "peak": UPDATE_PEAK / 1e12, "unit": "Tupd/s",
-                    "frac": ach / UPDATE_PEAK, "traffic": None,
+                    "frac": ach / UPDATE_PEAK, "traffic": measured_traffic(),
+                    "traffic_unit": "bytes per bulk launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                    "copy-calibrated)",
                     "avg_launch_us": per_launch_s * 1e6,
                     "updates_per_launch": per_launch_upd,
                     "lane_ops_per_s": ach * MIN_INSTR_PER_UPDATE,
