@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-phase HIP events (plain timed region)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-negative", action="store_true",
+                    help="skip the n=8192 int32 negative-weight solve with predecessors")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="arrival window of the serving trace at the configured rate")
@@ -126,18 +128,64 @@ def pack_graphs(graphs, torch, dev):
     return pool, views
 
 
+def bench_negative(torch, fw, gen, dev, reps=3):
+    """n=8192 int32 with negative weights (potential-reweighted), distances plus
+    predecessors, and the same solve without predecessors."""
+    import numpy as np
+    import oracle
+    g = gen.negative_graph_8192()
+    n = g.w.shape[0]
+    pristine = torch.from_numpy(g.w).to(dev)
+    work = torch.empty_like(pristine)
+    P = torch.empty((n, n), dtype=torch.int32, device=dev)
+    out = {"workload": "single graph n=8192 int32, edge prob 0.2, base weights [1,1000] "
+                       "reweighted by potentials in [-500,500], INT32_MAX/2 absent",
+           "n": n, "tile": fw.plan_tile(torch.int32, n)}
+    for mode, pp in (("with_pred", P), ("distances_only", None)):
+        work.copy_(pristine)
+        fw.fw_apsp_pred(work, pp)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            work.copy_(pristine)
+            fw.fw_apsp_pred(work, pp)
+        torch.cuda.synchronize(dev)
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        out[mode] = {"ms": ms, "updates_per_s": float(n) ** 3 / (ms / 1e3)}
+    # the last solve was distances only; redo with predecessors for the check
+    work.copy_(pristine)
+    fw.fw_apsp_pred(work, P)
+    srcs = np.array([17, 4321, 8000])
+    idx = torch.from_numpy(srcs).to(dev)
+    rows = work[idx].cpu().numpy()
+    base = oracle.dijkstra_rows(g.base, srcs)
+    ref = (base.astype(np.int64) + g.pot[srcs][:, None] - g.pot[None, :]).astype(np.int32)
+    ok = bool(np.array_equal(rows, ref)) and bool(np.array_equal(
+        P[idx].cpu().numpy(), oracle.canonical_pred(ref, g.w, rows=srcs)))
+    out["check"] = "ok" if ok else "mismatch"
+    return out
+
+
 def bench_batched(torch, fw, gen, dev, reps):
     """Ragged batch: 4096 graphs, n log-uniform in [16, 512], fp32."""
     import numpy as np
     import oracle
     graphs = gen.ragged_batch()
     sizes = np.array([w.shape[0] for w in graphs], dtype=np.float64)
+    # tile per size bucket, picked by the library's autotuner for the batched
+    # launch (installed into the plan table the batch plan reads)
+    buckets = [(16, 32), (33, 64), (65, 128), (129, 256), (257, 512)]
+    tuned = fw.autotune(torch.float32, buckets, objective="batched", batch=256, reps=3)
     pool, views = pack_graphs(graphs, torch, dev)
     pristine = pool.clone()
     plan = fw.BatchPlan(views)
     out = {"workload": "ragged batch of 4096 fp32 graphs, n log-uniform in [16,512], edge "
                        "prob 0.4, integer weights [1,100]",
-           "graphs": len(graphs), "updates": float((sizes ** 3).sum()), "grid": plan.grid}
+           "graphs": len(graphs), "updates": float((sizes ** 3).sum()), "grid": plan.grid,
+           "autotuned_tiles": {f"{lo}-{hi}": {"tile": v["tile"],
+                                              "ms_by_tile": {str(t): round(m, 4)
+                                                             for t, m in v["ms"].items()}}
+                               for (lo, hi), v in tuned.items()}}
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     for mode, nrep in (("graph", reps), ("kernel", reps), ("per_graph", max(1, reps // 2))):
@@ -336,6 +384,13 @@ def main():
                     "lane_ops_per_s": ach * MIN_INSTR_PER_UPDATE,
                     "frac_vs_3.93e13_upd_per_s": ach / ONE_INSTR_64LANE_PEAK}
 
+    negative = None
+    if not args.no_negative:
+        log("negative-weight int32 n=8192 with predecessors")
+        negative = bench_negative(torch, fw, gen, dev)
+        log(f"negative: {negative['with_pred']['ms']:.1f} ms with predecessors, "
+            f"{negative['distances_only']['ms']:.1f} ms distances only")
+
     batched = None
     if not args.no_batched:
         log("batched: 4096 ragged graphs")
@@ -366,7 +421,8 @@ def main():
                    "n": n, "tile": tile, "global_batch": 1, "parallelism": "single-gpu"},
         "frac_of_update_peak": value / UPDATE_PEAK,
         "check": "ok" if ok else "mismatch",
-        "phases": phases, "roofline": roof, "cpu_baseline": cpu, "batched": batched,
+        "phases": phases, "roofline": roof, "cpu_baseline": cpu, "negative_int32_pred": negative,
+        "batched": batched,
         "serving": serving,
         "paper_context": {"tesla_c1060_s_n16384": 53.06,
                           "speedup_vs_paper": 53.06 / (ms_per_step / 1e3) if n == 16384 else None},

@@ -138,6 +138,22 @@ int fw_plan_set(int dtype, int64_t n_lo, int64_t n_hi, int tile);
 void fw_plan_reset(void);
 
 /*
+ * fw_autotune -- the plan table's autotuner.  For each size bucket
+ * [lo[k], hi[k]] (2 <= lo <= hi <= 65536) it times every tile of
+ * fw_plan_tiles() at the bucket's geometric-middle size n and installs the
+ * fastest with fw_plan_set.  objective 0 times one single-graph solve,
+ * objective 1 one persistent batched launch of `batch` graphs of size n (the
+ * batched path reads the same table).  Each (bucket, tile) is run reps + 1
+ * times, the first as a warm-up, and scored by the median.  Writes the chosen
+ * tile of bucket k to tile_out[k] and, if ms_out is non-NULL, the median ms of
+ * tile t to ms_out[k * ntiles + t].  Synchronous; allocates and frees its own
+ * zero-filled scratch matrices (the sweep's run time does not depend on the
+ * data).  Errors: FW_ERR_INVALID for bad arguments, FW_ERR_NOMEM/FW_ERR_HIP.
+ */
+int fw_autotune(int dtype, const int64_t *lo, const int64_t *hi, int nbuckets, int objective,
+                int batch, int reps, int *tile_out, double *ms_out);
+
+/*
  * fw_apsp_batched -- many independent graphs in one call, solved together by
  * one persistent kernel launch: every workgroup takes graphs from a device
  * work counter, largest first, and solves each alone (whole-graph closure

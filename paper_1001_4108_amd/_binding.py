@@ -85,6 +85,8 @@ def _declare(L):
         "fw_plan_tile": ([ci, i64], ci),
         "fw_plan_set": ([ci, i64, i64, ci], ci),
         "fw_plan_reset": ([], None),
+        "fw_autotune": ([ci, P64, P64, ci, ci, ci, ci, ctypes.POINTER(ci),
+                         ctypes.POINTER(ctypes.c_double)], ci),
         "fw_apsp_batched": ([ctypes.POINTER(vp), P64, P64, i64, ci, ctypes.POINTER(vp), P64, vp],
                             ci),
         "fw_batched_max_n": ([ci, ci], i64),
@@ -220,6 +222,48 @@ def plan_set(dtype, n_lo: int, n_hi: int, tile: int) -> None:
 
 def plan_reset() -> None:
     lib().fw_plan_reset()
+
+
+def autotune(dtype, buckets, objective: str = "single", batch: int = 256, reps: int = 3,
+             device=None) -> dict:
+    """Time every tile per size bucket on the device and install the fastest.
+
+    ``buckets`` is a list of (lo, hi) sizes; ``objective`` is "single" (one
+    solve) or "batched" (one persistent launch of ``batch`` graphs).  Returns
+    {(lo, hi): {"tile": t, "ms": {tile: median_ms}}}.
+    """
+    code = FW_F32 if dtype in (torch.float32, "f32", FW_F32) else FW_I32
+    k = len(buckets)
+    lo = (ctypes.c_int64 * k)(*[int(b[0]) for b in buckets])
+    hi = (ctypes.c_int64 * k)(*[int(b[1]) for b in buckets])
+    tiles = plan_tiles()
+    out = (ctypes.c_int * k)()
+    ms = (ctypes.c_double * (k * len(tiles)))()
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    with torch.cuda.device(dev):
+        _check(lib().fw_autotune(code, lo, hi, k, 1 if objective == "batched" else 0, int(batch),
+                                 int(reps), out, ms), "fw_autotune")
+    return {(int(buckets[i][0]), int(buckets[i][1])):
+            {"tile": out[i], "ms": {t: ms[i * len(tiles) + j] for j, t in enumerate(tiles)}}
+            for i in range(k)}
+
+
+def save_plan(result: dict, path: str, dtype="f32", objective="single") -> None:
+    """Persist an autotune result as JSON."""
+    import json
+    rows = [{"lo": lo, "hi": hi, "tile": v["tile"], "ms": {str(t): m for t, m in v["ms"].items()}}
+            for (lo, hi), v in result.items()]
+    with open(path, "w") as f:
+        json.dump({"dtype": str(dtype), "objective": objective, "buckets": rows}, f, indent=1)
+
+
+def load_plan(path: str) -> None:
+    """Install a saved autotune result into the plan table."""
+    import json
+    spec = json.load(open(path))
+    dt = "i32" if "int32" in spec["dtype"] or spec["dtype"] == "i32" else "f32"
+    for row in spec["buckets"]:
+        plan_set(dt, row["lo"], row["hi"], row["tile"])
 
 
 def fw_apsp_batched(mats, preds=None, stream=None) -> None:

@@ -419,6 +419,10 @@ int solve_single(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64
     return solve(d, dtype, (int)n, ld, pred, ldp, plan_tile(dtype, n), st, false);
 }
 
+int solve_with_tile(void *d, int dtype, int n, int64_t ld, int tile, hipStream_t st) {
+    return solve(d, dtype, n, ld, nullptr, 0, tile, st, false);
+}
+
 int validate_matrix(const void *d, int dtype, int64_t n, int64_t ld, const int32_t *pred,
                     int64_t ldp) {
     return validate(d, dtype, n, ld, pred, ldp);

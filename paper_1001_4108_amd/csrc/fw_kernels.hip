@@ -125,13 +125,27 @@ hipError_t diag_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, in
     return hipGetLastError();
 }
 
+#ifndef FW_PRED128_TM
+#define FW_PRED128_TM 4
+#define FW_PRED128_TN 4
+#define FW_PRED128_BK 32
+#endif
+
 template <typename T, bool VEC, bool PRED>
 hipError_t tile_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b, int nb,
                   int mode, unsigned grid, hipStream_t st) {
     switch (tile) {
     case 128:
-        tile_kernel<T, 128, 16, 8, 8, VEC, PRED><<<grid, 256, 0, st>>>(d, p, n, ld, ldp, b, nb,
-                                                                      mode);
+        if constexpr (PRED) {
+            // the predecessor update keeps twice the state per cell; 4 x 4
+            // sub-tiles over 1024 threads keep it at 4 waves per SIMD
+            constexpr int TMP = FW_PRED128_TM, TNP = FW_PRED128_TN;
+            tile_kernel<T, 128, FW_PRED128_BK, TMP, TNP, VEC, PRED>
+                <<<grid, (128 / TMP) * (128 / TNP), 0, st>>>(d, p, n, ld, ldp, b, nb, mode);
+        } else {
+            tile_kernel<T, 128, 16, 8, 8, VEC, PRED><<<grid, 256, 0, st>>>(d, p, n, ld, ldp, b,
+                                                                          nb, mode);
+        }
         break;
     case 64:
         tile_kernel<T, 64, 16, 4, 4, VEC, PRED><<<grid, 256, 0, st>>>(d, p, n, ld, ldp, b, nb,

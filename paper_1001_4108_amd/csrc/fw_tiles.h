@@ -153,7 +153,11 @@ __device__ __forceinline__ void closure_tile(T *__restrict__ d, int32_t *__restr
         }
     }
 
-    for (int kb = 0; kb < G; ++kb) {
+    // steps k >= n only involve padded (isolated) vertices and change no real
+    // cell, so the loop stops at the first register row past the last real k
+    const int kreal = n - base < S ? n - base : S;
+    const int kb_end = (kreal + TM - 1) / TM;
+    for (int kb = 0; kb < kb_end; ++kb) {
 #pragma unroll
         for (int r = 0; r < TM; ++r) {
             const int buf = (kb * TM + r) & 1;

@@ -95,3 +95,17 @@ def test_disabled_schedules_cannot_be_enabled():
     assert L.fw_set_option(1, 0) == 0 and L.fw_set_option(2, 0) == 0
     assert L.fw_set_option(99, 0) == 1
     assert L.fw_get_option(99) == -1
+
+
+def test_autotune_argument_validation():
+    import ctypes
+    L = B.lib()
+    lo = (ctypes.c_int64 * 1)(64)
+    hi = (ctypes.c_int64 * 1)(32)   # hi < lo
+    out = (ctypes.c_int * 1)()
+    assert L.fw_autotune(0, lo, hi, 1, 0, 1, 1, out, None) == 1
+    hi[0] = 128
+    assert L.fw_autotune(5, lo, hi, 1, 0, 1, 1, out, None) == 1   # dtype
+    assert L.fw_autotune(0, lo, hi, 1, 2, 1, 1, out, None) == 1   # objective
+    assert L.fw_autotune(0, lo, hi, 1, 1, 0, 1, out, None) == 1   # empty batch
+    assert L.fw_autotune(0, lo, hi, 0, 0, 1, 1, out, None) == 1   # no buckets

@@ -1,0 +1,36 @@
+"""The autotuner installs a measured tile per bucket; results stay bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1001_4108_amd as fw
+from paper_1001_4108_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("objective", ["single", "batched"])
+def test_autotune_installs_fastest_tile(objective, tmp_path):
+    fw.plan_reset()
+    buckets = [(20, 40), (100, 300)]
+    res = fw.autotune(torch.float32, buckets, objective=objective, batch=32, reps=2)
+    tiles = fw.plan_tiles()
+    for (lo, hi), v in res.items():
+        assert v["tile"] in tiles
+        assert all(ms > 0 for ms in v["ms"].values())
+        assert v["ms"][v["tile"]] == min(v["ms"].values())
+        for n in (lo, hi, (lo + hi) // 2):
+            assert fw.plan_tile(torch.float32, n) == v["tile"]
+    path = tmp_path / "plan.json"
+    fw.save_plan(res, str(path), objective=objective)
+    fw.plan_reset()
+    fw.load_plan(str(path))
+    for (lo, hi), v in res.items():
+        assert fw.plan_tile(torch.float32, lo) == v["tile"]
+    W = gen.dense_graph(173, 0.2, 1, 9, seed=4)
+    d = torch.from_numpy(W).cuda()
+    fw.fw_apsp(d)
+    torch.cuda.synchronize()
+    assert np.array_equal(d.cpu().numpy().view(np.uint32), oracle.fw(W).view(np.uint32))
+    fw.plan_reset()
