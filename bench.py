@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-phase HIP events (plain timed region)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-maxmin", action="store_true",
+                    help="skip the n=16384 widest-path (max, min) solve")
     ap.add_argument("--no-negative", action="store_true",
                     help="skip the n=8192 int32 negative-weight solve with predecessors")
     ap.add_argument("--no-serving", action="store_true")
@@ -126,6 +128,34 @@ def pack_graphs(graphs, torch, dev):
     views = [pool[o:o + w.shape[0] * l].view(w.shape[0], l)[:, :w.shape[0]]
              for w, l, o in zip(graphs, lds, offs)]
     return pool, views
+
+
+def bench_maxmin(torch, fw, W, dev, reps=3):
+    """Widest paths over the (max, min) semiring on the same n=16384 edges
+    (absent = -INF, diagonal +INF): the same kernels, another semiring."""
+    import numpy as np
+    import oracle
+    from paper_1001_4108_amd import gen
+    n = W.shape[0]
+    Wm = np.where(np.isinf(W), np.float32(-np.inf), W).astype(np.float32)
+    np.fill_diagonal(Wm, np.inf)
+    pristine = torch.from_numpy(Wm).to(dev)
+    work = torch.empty_like(pristine)
+    work.copy_(pristine)
+    fw.fw_apsp_semiring(work, "maxmin")
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        work.copy_(pristine)
+        fw.fw_apsp_semiring(work, "maxmin")
+    torch.cuda.synchronize(dev)
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    srcs = gen.dijkstra_sources_16384(n, 2) if n >= 2 else np.arange(n)
+    rows = work[torch.from_numpy(srcs).to(dev)].cpu().numpy()
+    ok = bool(np.array_equal(rows.view(np.uint32),
+                             oracle.widest_rows(Wm, srcs).astype(np.float32).view(np.uint32)))
+    return {"workload": f"widest paths, n={n} fp32 (the same edges, absent -INF)", "ms": ms,
+            "updates_per_s": float(n) ** 3 / (ms / 1e3), "check": "ok" if ok else "mismatch"}
 
 
 def bench_negative(torch, fw, gen, dev, reps=3):
@@ -384,6 +414,11 @@ def main():
                     "lane_ops_per_s": ach * MIN_INSTR_PER_UPDATE,
                     "frac_vs_3.93e13_upd_per_s": ach / ONE_INSTR_64LANE_PEAK}
 
+    maxmin = None
+    if not args.no_maxmin:
+        log("widest paths (max, min) n=16384")
+        maxmin = bench_maxmin(torch, fw, W, dev)
+
     negative = None
     if not args.no_negative:
         log("negative-weight int32 n=8192 with predecessors")
@@ -421,7 +456,7 @@ def main():
                    "n": n, "tile": tile, "global_batch": 1, "parallelism": "single-gpu"},
         "frac_of_update_peak": value / UPDATE_PEAK,
         "check": "ok" if ok else "mismatch",
-        "phases": phases, "roofline": roof, "cpu_baseline": cpu, "negative_int32_pred": negative,
+        "phases": phases, "roofline": roof, "cpu_baseline": cpu, "negative_int32_pred": negative, "maxmin": maxmin,
         "batched": batched,
         "serving": serving,
         "paper_context": {"tesla_c1060_s_n16384": 53.06,

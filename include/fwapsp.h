@@ -116,6 +116,28 @@ int fw_apsp_plan(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred,
                  int64_t ld_pred, int tile, void *stream);
 
 /*
+ * fw_apsp_semiring -- the same in-place blocked sweep over another closed
+ * semiring (section 3.2's schedule is valid for any of them).
+ *   FW_SR_MINPLUS  shortest paths, exactly fw_apsp / fw_apsp_i32;
+ *   FW_SR_MAXMIN   widest (bottleneck) paths: d_ij becomes the largest, over
+ *                  all i -> j paths, of the smallest edge weight on the path,
+ *                  i.e. the update is d_ij <- max(d_ij, min(d_ik, d_kj)).
+ *                  Absent edges must hold the max-identity (-INF for fp32,
+ *                  INT32_MIN for int32; for non-negative weights 0 works);
+ *                  the diagonal is kept unless a cycle through i is wider
+ *                  (use +INF / INT32_MAX for "a vertex reaches itself").  Over
+ *                  int32 weights in {0, 1} with 1 on the diagonal this is the
+ *                  transitive closure.  min and max are exact, so results are
+ *                  bit-identical to the triple loop for every input (no
+ *                  precondition, no negative-cycle issue).
+ * d, n, ld, stream as fw_apsp; dtype is fw_dtype.  Errors: FW_ERR_INVALID for
+ * a bad semiring or the argument errors of fw_apsp.
+ */
+#define FW_SR_MINPLUS 0
+#define FW_SR_MAXMIN 1
+int fw_apsp_semiring(void *d, int dtype, int semiring, int64_t n, int64_t ld, void *stream);
+
+/*
  * Tile sizes fw_apsp_plan accepts: writes up to `cap` of them to `tiles`
  * (host memory) and returns how many exist.
  */

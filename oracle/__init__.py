@@ -14,6 +14,10 @@ built by ``oracle/build.py``):
 * ``dijkstra_rows(W, srcs)``-- textbook dense Dijkstra in float64, for rows
                                of solves too large for ``fw``.
 * ``reach_row(W, src)``     -- breadth-first reachability over the edges.
+* ``fw_maxmin(w)``          -- the same loop over the (max, min) semiring
+                               (widest paths; transitive closure on {0, 1}).
+* ``widest_rows(W, srcs)``  -- bottleneck Dijkstra, rows of large widest-path
+                               solves.
 
 Parity status: every function here is pinned by ``tests/test_oracle_pins.py``
 (brute-force path enumeration, closed forms, library routines, invariants).
@@ -47,6 +51,9 @@ def _load():
     lib.oracle_dijkstra_rows.argtypes = [vp, ci, i64, i64, vp, i64, vp, i64, ci]
     lib.oracle_dijkstra_rows.restype = ci
     lib.oracle_max_threads.restype = ci
+    lib.oracle_fw_maxmin_f32.argtypes = [vp, i64, i64, ci]
+    lib.oracle_fw_maxmin_i32.argtypes = [vp, i64, i64, ci]
+    lib.oracle_widest_rows_f32.argtypes = [vp, i64, i64, vp, i64, vp, i64, ci]
     _lib = lib
     return lib
 
@@ -95,6 +102,33 @@ def fw_inplace(d: np.ndarray, nthreads: int = 0, k_begin: int = 0, k_end=None) -
     lib = _load()
     fn = lib.oracle_fw_f32 if code == 0 else lib.oracle_fw_i32
     fn(d.ctypes.data, n, ld, k_begin, k_end, nthreads)
+
+
+def fw_maxmin(w: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """Widest-path (max, min) closure of Fig. FW-Alg's loop on a copy of ``w``.
+
+    Absent edges must hold -INF (float32) or INT32_MIN (int32).
+    """
+    code = _dtype_code(w)
+    d = np.array(w, copy=True, order="C")
+    n, ld = _square_rowmajor(d)
+    lib = _load()
+    fn = lib.oracle_fw_maxmin_f32 if code == 0 else lib.oracle_fw_maxmin_i32
+    fn(d.ctypes.data, n, ld, nthreads)
+    return d
+
+
+def widest_rows(W: np.ndarray, srcs, nthreads: int = 0) -> np.ndarray:
+    """float64 widest-path widths from each source (bottleneck Dijkstra), fp32
+    input with -INF for absent edges; the source's own entry is +inf."""
+    if W.dtype != np.float32:
+        raise TypeError("widest_rows takes float32")
+    n, ld = _square_rowmajor(W)
+    srcs = np.ascontiguousarray(srcs, dtype=np.int64)
+    out = np.empty((len(srcs), n), dtype=np.float64)
+    _load().oracle_widest_rows_f32(W.ctypes.data, n, ld, srcs.ctypes.data, len(srcs),
+                                   out.ctypes.data, n, nthreads)
+    return out
 
 
 def reach_row(w: np.ndarray, src: int) -> np.ndarray:

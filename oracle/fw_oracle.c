@@ -267,3 +267,93 @@ int oracle_dijkstra_rows(const void *W, int dtype, int64_t n, int64_t ld,
     }
     return 0;
 }
+
+/*
+ * Widest (bottleneck) paths: the Floyd-Warshall loop of Fig. FW-Alg over the
+ * (max, min) semiring, the same k-ordered triple loop with
+ *     w_ij <- max(w_ij, min(w_ik, w_kj)),
+ * i.e. d_ij = the largest, over all i -> j paths, of the smallest edge weight
+ * on the path.  Absent edges carry the max-identity (-INF for fp32,
+ * INT32_MIN for int32).  Over weights in {0, 1} this is the transitive
+ * closure.  min and max are exact, and row k / column k cannot change in
+ * iteration k (min(w_kk, w_kj) <= w_kj), so rows may run in parallel for any
+ * input.  max(a, b) := (b > a) ? b : a.
+ */
+void oracle_fw_maxmin_f32(float *w, int64_t n, int64_t ld, int nthreads) {
+    int nt = oracle_threads(nthreads);
+    for (int64_t k = 0; k < n; ++k) {
+        const float *wk = w + k * ld;
+#pragma omp parallel for schedule(static) num_threads(nt)
+        for (int64_t i = 0; i < n; ++i) {
+            if (i == k) continue;
+            float *restrict wi = w + i * ld;
+            const float *restrict wkr = wk;
+            const float wik = wi[k];
+            for (int64_t j = 0; j < n; ++j) {
+                float s = (wkr[j] < wik) ? wkr[j] : wik;
+                wi[j] = (s > wi[j]) ? s : wi[j];
+            }
+        }
+    }
+}
+
+void oracle_fw_maxmin_i32(int32_t *w, int64_t n, int64_t ld, int nthreads) {
+    int nt = oracle_threads(nthreads);
+    for (int64_t k = 0; k < n; ++k) {
+        const int32_t *wk = w + k * ld;
+#pragma omp parallel for schedule(static) num_threads(nt)
+        for (int64_t i = 0; i < n; ++i) {
+            if (i == k) continue;
+            int32_t *restrict wi = w + i * ld;
+            const int32_t *restrict wkr = wk;
+            const int32_t wik = wi[k];
+            for (int64_t j = 0; j < n; ++j) {
+                int32_t s = (wkr[j] < wik) ? wkr[j] : wik;
+                wi[j] = (s > wi[j]) ? s : wi[j];
+            }
+        }
+    }
+}
+
+/*
+ * Single-source widest paths by the bottleneck variant of Dijkstra's
+ * algorithm (dense O(n^2) form): width[src] = +inf, every other vertex starts
+ * at -inf; repeatedly finalise the unvisited vertex of largest width u and
+ * relax width[v] <- max(width[v], min(width[u], w_uv)) over the edges of W
+ * (entries other than -INF; the diagonal is skipped).  Used to check rows of
+ * large (max, min) solves.  out[s*ldo + v] = width from srcs[s] to v.
+ */
+void oracle_widest_rows_f32(const float *W, int64_t n, int64_t ld, const int64_t *srcs,
+                            int64_t nsrc, double *out, int64_t ldo, int nthreads) {
+    int nt = oracle_threads(nthreads);
+#pragma omp parallel num_threads(nt)
+    {
+        uint8_t *done = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < nsrc; ++s) {
+            double *wd = out + s * ldo;
+            for (int64_t v = 0; v < n; ++v) wd[v] = -INFINITY;
+            memset(done, 0, (size_t)n);
+            wd[srcs[s]] = INFINITY;
+            for (int64_t it = 0; it < n; ++it) {
+                int64_t u = -1;
+                double best = -INFINITY;
+                for (int64_t v = 0; v < n; ++v)
+                    if (!done[v] && (u < 0 || wd[v] > best)) {
+                        best = wd[v];
+                        u = v;
+                    }
+                if (u < 0 || best == -INFINITY) break;
+                done[u] = 1;
+                for (int64_t v = 0; v < n; ++v) {
+                    if (done[v] || v == u) continue;
+                    const float e = W[u * ld + v];
+                    if (isinf(e) && e < 0.0f) continue;
+                    const double c = best < (double)e ? best : (double)e;
+                    if (c > wd[v]) wd[v] = c;
+                }
+            }
+        }
+        free(done);
+    }
+}

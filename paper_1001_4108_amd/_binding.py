@@ -82,6 +82,7 @@ def _declare(L):
         "fw_apsp_pred": ([vp, ci, i64, i64, vp, i64, vp], ci),
         "fw_apsp_plan": ([vp, ci, i64, i64, vp, i64, ci, vp], ci),
         "fw_plan_tiles": ([ctypes.POINTER(ci), ci], ci),
+        "fw_apsp_semiring": ([vp, ci, ci, i64, i64, vp], ci),
         "fw_plan_tile": ([ci, i64], ci),
         "fw_plan_set": ([ci, i64, i64, ci], ci),
         "fw_plan_reset": ([], None),
@@ -202,6 +203,29 @@ def fw_apsp_plan(d: torch.Tensor, tile: int, pred: torch.Tensor | None = None, s
         _check(lib().fw_apsp_plan(p, code, n, ld, pp, pld, int(tile), _stream(d, stream)),
                "fw_apsp_plan")
     return d, pred
+
+
+SEMIRINGS = {"minplus": 0, "maxmin": 1}
+
+
+def fw_apsp_semiring(d: torch.Tensor, semiring: str = "maxmin", stream=None) -> torch.Tensor:
+    """In-place closure of ``d`` over "minplus" (shortest paths) or "maxmin"
+    (widest paths; transitive closure over int32 {0, 1})."""
+    code = _dtype_code(d)
+    p, n, ld = _matrix(d, "d")
+    with torch.cuda.device(d.device):
+        _check(lib().fw_apsp_semiring(p, code, SEMIRINGS[semiring], n, ld, _stream(d, stream)),
+               "fw_apsp_semiring")
+    return d
+
+
+def fw_transitive_closure(adj: torch.Tensor, stream=None) -> torch.Tensor:
+    """Reachability in place on an int32 0/1 adjacency matrix (1 = edge; the
+    diagonal is set to 1 first)."""
+    if adj.dtype != torch.int32:
+        raise TypeError("transitive closure takes an int32 0/1 matrix")
+    adj.fill_diagonal_(1)
+    return fw_apsp_semiring(adj, "maxmin", stream)
 
 
 def plan_tiles() -> list[int]:

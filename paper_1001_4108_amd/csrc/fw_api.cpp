@@ -207,7 +207,8 @@ constexpr bool kGraphsAvailable = false;
 // panels of stage b, ahead(b) waits for rest(b-1) (which last wrote row and
 // column b+1).
 int enqueue_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
-                  hipStream_t st, hipStream_t side, bool lookahead, std::vector<hipEvent_t> &evs) {
+                  hipStream_t st, hipStream_t side, bool lookahead, std::vector<hipEvent_t> &evs,
+                  int sr = kMinPlus) {
     const int nb = (n + tile - 1) / tile;
     hipError_t e;
     if (pred) {
@@ -221,12 +222,12 @@ int enqueue_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t 
     auto diag = [&](int b, hipStream_t s) {
         const double kb = real(b);
         return timed(kDiag, kb * kb * kb, s,
-                     [&] { return launch_diag(dtype, tile, d, pred, n, ld, ldp, b, s); });
+                     [&] { return launch_diag(dtype, sr, tile, d, pred, n, ld, ldp, b, s); });
     };
     auto panels = [&](int b, hipStream_t s) {
         const double kb = real(b);
         return timed(kPanel, 2.0 * kb * kb * (nn - kb), s, [&] {
-            return launch_panels(dtype, tile, d, pred, n, ld, ldp, b, nb, s);
+            return launch_panels(dtype, sr, tile, d, pred, n, ld, ldp, b, nb, s);
         });
     };
     auto bulk = [&](int b, int part, hipStream_t s) {
@@ -240,7 +241,7 @@ int enqueue_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t 
             upd = kb * (rest - r1) * (rest - r1);
         }
         return timed(kind, upd, s, [&] {
-            return launch_bulk(dtype, tile, d, pred, n, ld, ldp, b, nb, part, s);
+            return launch_bulk(dtype, sr, tile, d, pred, n, ld, ldp, b, nb, part, s);
         });
     };
 
@@ -356,7 +357,7 @@ bool profiling_on() {
 
 // Enqueue the whole solve for one graph.  Arguments already valid.
 int solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
-          hipStream_t st, bool allow_graph = true) {
+          hipStream_t st, bool allow_graph = true, int sr = kMinPlus) {
     if (n <= 1) {
         if (pred && n == 1) {
             hipError_t e = timed(kPredFix, 0.0, st, [&] {
@@ -369,10 +370,10 @@ int solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int
     if (!tile_supported(tile)) return FW_ERR_INVALID;
     const bool lookahead = g_opt_lookahead.load() != 0;
     const bool graphs = allow_graph && g_opt_graphs.load() && !profiling_on();
-    if (!lookahead && !graphs) {
+    if ((!lookahead && !graphs) || sr != kMinPlus) {
         // plain schedule on the caller's stream: no side stream, no events
         std::vector<hipEvent_t> none;
-        return enqueue_solve(d, dtype, n, ld, pred, ldp, tile, st, nullptr, false, none);
+        return enqueue_solve(d, dtype, n, ld, pred, ldp, tile, st, nullptr, false, none, sr);
     }
     DeviceRes *res = device_res();
     if (!res) return FW_ERR_HIP;
@@ -480,6 +481,15 @@ int fw_apsp_plan(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64
     if (s != FW_OK) return s;
     if (!tile_supported(tile)) return FW_ERR_INVALID;
     return solve(d, dtype, (int)n, ld, pred, ld_pred, tile, (hipStream_t)stream);
+}
+
+int fw_apsp_semiring(void *d, int dtype, int semiring, int64_t n, int64_t ld, void *stream) {
+    if (semiring != FW_SR_MINPLUS && semiring != FW_SR_MAXMIN) return FW_ERR_INVALID;
+    int s = validate(d, dtype, n, ld, nullptr, 0);
+    if (s != FW_OK) return s;
+    if (n <= 1) return FW_OK;
+    return solve(d, dtype, (int)n, ld, nullptr, 0, plan_tile(dtype, n), (hipStream_t)stream, false,
+                 semiring == FW_SR_MAXMIN ? kMaxMin : kMinPlus);
 }
 
 int fw_plan_tiles(int *tiles, int cap) {

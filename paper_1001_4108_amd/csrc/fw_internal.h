@@ -20,17 +20,20 @@ enum PhaseKind {
     kNumKinds = 6
 };
 
+// Closed semirings the sweep runs over.
+enum Semiring { kMinPlus = 0, kMaxMin = 1 };
+
 // Bulk launch parts (tile_kernel modes).
 enum BulkPart { kBulkAll = 1, kBulkAheadPart = 2, kBulkRestPart = 3 };
 
 // One stage-phase launch of the blocked schedule.  `d`/`p` are the matrix
 // and the (optional) predecessor matrix; `b` is the k-block index, `nb` the
 // number of tile rows.  Returns hipSuccess or the launch error.
-hipError_t launch_diag(int dtype, int tile, void *d, int32_t *p, int n, int64_t ld,
+hipError_t launch_diag(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
                        int64_t ldp, int b, hipStream_t st);
-hipError_t launch_panels(int dtype, int tile, void *d, int32_t *p, int n, int64_t ld,
+hipError_t launch_panels(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
                          int64_t ldp, int b, int nb, hipStream_t st);
-hipError_t launch_bulk(int dtype, int tile, void *d, int32_t *p, int n, int64_t ld,
+hipError_t launch_bulk(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
                        int64_t ldp, int b, int nb, int part, hipStream_t st);
 hipError_t launch_pred_init(int dtype, const void *d, int32_t *p, int n, int64_t ld,
                             int64_t ldp, hipStream_t st);

@@ -33,12 +33,12 @@ namespace fw {
 namespace {
 
 // Phase 1: closure of the diagonal tile (b, b) -- one workgroup.
-template <typename T, int S, int TM, bool PRED>
+template <typename T, int S, int TM, bool PRED, class A>
 __global__ void __launch_bounds__((S / TM) * (S / TM))
 diag_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64_t ldp,
             int b) {
     __shared__ __align__(16) char smem[closure_smem_bytes<T, S, PRED>()];
-    closure_tile<T, S, TM, PRED>(d, P, n, ld, ldp, b * S, smem);
+    closure_tile<T, S, TM, PRED, A>(d, P, n, ld, ldp, b * S, smem);
 }
 
 // Phases 2 and 3: one tile per workgroup.
@@ -46,7 +46,7 @@ diag_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
 //   mode 1: blockIdx.x enumerates the (nb-1)^2 bulk tiles;
 //   mode 2: the 2(nb-1)-1 bulk tiles in row or column b+1 (look-ahead part);
 //   mode 3: the (nb-2)^2 remaining bulk tiles.
-template <typename T, int S, int BK, int TM, int TN, bool VEC, bool PRED>
+template <typename T, int S, int BK, int TM, int TN, bool VEC, bool PRED, class A>
 __global__ void __launch_bounds__((S / TM) * (S / TN))
 tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64_t ldp, int b,
             int nb, int mode) {
@@ -58,7 +58,7 @@ tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
     case 2: ahead_coords(blockIdx.x, b, nb - 1, bi, bj); break;
     default: rest_coords(blockIdx.x, b, nb - 1, bi, bj); break;
     }
-    product_tile<T, S, BK, TM, TN, VEC, PRED>(d, P, n, ld, ldp, bi, bj, b, smem);
+    product_tile<T, S, BK, TM, TN, VEC, PRED, A>(d, P, n, ld, ldp, bi, bj, b, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -113,13 +113,13 @@ dim3 elementwise_grid(int n) {
 //    64   16   4 x 4     256       4 (256)
 //    32   16   4 x 4      64       2 (256)
 // ---------------------------------------------------------------------------
-template <typename T, bool PRED>
+template <typename T, bool PRED, class A>
 hipError_t diag_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b,
                   hipStream_t st) {
     switch (tile) {
-    case 128: diag_kernel<T, 128, 4, PRED><<<1, 1024, 0, st>>>(d, p, n, ld, ldp, b); break;
-    case 64: diag_kernel<T, 64, 4, PRED><<<1, 256, 0, st>>>(d, p, n, ld, ldp, b); break;
-    case 32: diag_kernel<T, 32, 2, PRED><<<1, 256, 0, st>>>(d, p, n, ld, ldp, b); break;
+    case 128: diag_kernel<T, 128, 4, PRED, A><<<1, 1024, 0, st>>>(d, p, n, ld, ldp, b); break;
+    case 64: diag_kernel<T, 64, 4, PRED, A><<<1, 256, 0, st>>>(d, p, n, ld, ldp, b); break;
+    case 32: diag_kernel<T, 32, 2, PRED, A><<<1, 256, 0, st>>>(d, p, n, ld, ldp, b); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -131,7 +131,7 @@ hipError_t diag_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, in
 #define FW_PRED128_BK 32
 #endif
 
-template <typename T, bool VEC, bool PRED>
+template <typename T, bool VEC, bool PRED, class A>
 hipError_t tile_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b, int nb,
                   int mode, unsigned grid, hipStream_t st) {
     switch (tile) {
@@ -140,27 +140,27 @@ hipError_t tile_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, in
             // the predecessor update keeps twice the state per cell; 4 x 4
             // sub-tiles over 1024 threads keep it at 4 waves per SIMD
             constexpr int TMP = FW_PRED128_TM, TNP = FW_PRED128_TN;
-            tile_kernel<T, 128, FW_PRED128_BK, TMP, TNP, VEC, PRED>
+            tile_kernel<T, 128, FW_PRED128_BK, TMP, TNP, VEC, PRED, A>
                 <<<grid, (128 / TMP) * (128 / TNP), 0, st>>>(d, p, n, ld, ldp, b, nb, mode);
         } else {
-            tile_kernel<T, 128, 16, 8, 8, VEC, PRED><<<grid, 256, 0, st>>>(d, p, n, ld, ldp, b,
-                                                                          nb, mode);
+            tile_kernel<T, 128, 16, 8, 8, VEC, PRED, A><<<grid, 256, 0, st>>>(d, p, n, ld, ldp,
+                                                                             b, nb, mode);
         }
         break;
     case 64:
-        tile_kernel<T, 64, 16, 4, 4, VEC, PRED><<<grid, 256, 0, st>>>(d, p, n, ld, ldp, b, nb,
-                                                                     mode);
+        tile_kernel<T, 64, 16, 4, 4, VEC, PRED, A><<<grid, 256, 0, st>>>(d, p, n, ld, ldp, b, nb,
+                                                                        mode);
         break;
     case 32:
-        tile_kernel<T, 32, 16, 4, 4, VEC, PRED><<<grid, 64, 0, st>>>(d, p, n, ld, ldp, b, nb,
-                                                                    mode);
+        tile_kernel<T, 32, 16, 4, 4, VEC, PRED, A><<<grid, 64, 0, st>>>(d, p, n, ld, ldp, b, nb,
+                                                                       mode);
         break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, class A, bool ALLOW_PRED>
 hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b,
                          int nb, int mode, hipStream_t st) {
     const int64_t m = nb - 1;
@@ -169,36 +169,57 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
     if (grid <= 0) return hipSuccess;
     if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
     const bool vec = vec_ok(d, ld) && (p == nullptr || vec_ok(p, ldp));
-    if (p) {
-        return vec ? tile_t<T, true, true>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid, st)
-                   : tile_t<T, false, true>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid,
-                                            st);
+    if constexpr (ALLOW_PRED) {
+        if (p) {
+            return vec ? tile_t<T, true, true, A>(tile, d, p, n, ld, ldp, b, nb, mode,
+                                                  (unsigned)grid, st)
+                       : tile_t<T, false, true, A>(tile, d, p, n, ld, ldp, b, nb, mode,
+                                                   (unsigned)grid, st);
+        }
+    } else {
+        if (p) return hipErrorInvalidValue;
     }
-    return vec ? tile_t<T, true, false>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid, st)
-               : tile_t<T, false, false>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid, st);
+    return vec ? tile_t<T, true, false, A>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid, st)
+               : tile_t<T, false, false, A>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid,
+                                            st);
+}
+
+template <typename T>
+hipError_t tile_any(int sr, int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b,
+                    int nb, int mode, hipStream_t st) {
+    if (sr == kMaxMin)
+        return tile_dispatch<T, ArMaxMin<T>, false>(tile, d, p, n, ld, ldp, b, nb, mode, st);
+    return tile_dispatch<T, Ar<T>, true>(tile, d, p, n, ld, ldp, b, nb, mode, st);
 }
 
 }  // namespace
 
-hipError_t launch_diag(int dtype, int tile, void *d, int32_t *p, int n, int64_t ld, int64_t ldp,
-                       int b, hipStream_t st) {
+hipError_t launch_diag(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
+                       int64_t ldp, int b, hipStream_t st) {
+    if (sr == kMaxMin) {
+        if (p) return hipErrorInvalidValue;
+        if (dtype == 0)
+            return diag_t<float, false, ArMaxMin<float>>(tile, (float *)d, p, n, ld, ldp, b, st);
+        return diag_t<int32_t, false, ArMaxMin<int32_t>>(tile, (int32_t *)d, p, n, ld, ldp, b,
+                                                         st);
+    }
     if (dtype == 0)
-        return p ? diag_t<float, true>(tile, (float *)d, p, n, ld, ldp, b, st)
-                 : diag_t<float, false>(tile, (float *)d, p, n, ld, ldp, b, st);
-    return p ? diag_t<int32_t, true>(tile, (int32_t *)d, p, n, ld, ldp, b, st)
-             : diag_t<int32_t, false>(tile, (int32_t *)d, p, n, ld, ldp, b, st);
+        return p ? diag_t<float, true, Ar<float>>(tile, (float *)d, p, n, ld, ldp, b, st)
+                 : diag_t<float, false, Ar<float>>(tile, (float *)d, p, n, ld, ldp, b, st);
+    return p ? diag_t<int32_t, true, Ar<int32_t>>(tile, (int32_t *)d, p, n, ld, ldp, b, st)
+             : diag_t<int32_t, false, Ar<int32_t>>(tile, (int32_t *)d, p, n, ld, ldp, b, st);
 }
 
-hipError_t launch_panels(int dtype, int tile, void *d, int32_t *p, int n, int64_t ld,
+hipError_t launch_panels(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
                          int64_t ldp, int b, int nb, hipStream_t st) {
-    if (dtype == 0) return tile_dispatch<float>(tile, (float *)d, p, n, ld, ldp, b, nb, 0, st);
-    return tile_dispatch<int32_t>(tile, (int32_t *)d, p, n, ld, ldp, b, nb, 0, st);
+    if (dtype == 0) return tile_any<float>(sr, tile, (float *)d, p, n, ld, ldp, b, nb, 0, st);
+    return tile_any<int32_t>(sr, tile, (int32_t *)d, p, n, ld, ldp, b, nb, 0, st);
 }
 
-hipError_t launch_bulk(int dtype, int tile, void *d, int32_t *p, int n, int64_t ld, int64_t ldp,
-                       int b, int nb, int part, hipStream_t st) {
-    if (dtype == 0) return tile_dispatch<float>(tile, (float *)d, p, n, ld, ldp, b, nb, part, st);
-    return tile_dispatch<int32_t>(tile, (int32_t *)d, p, n, ld, ldp, b, nb, part, st);
+hipError_t launch_bulk(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
+                       int64_t ldp, int b, int nb, int part, hipStream_t st) {
+    if (dtype == 0) return tile_any<float>(sr, tile, (float *)d, p, n, ld, ldp, b, nb, part, st);
+    return tile_any<int32_t>(sr, tile, (int32_t *)d, p, n, ld, ldp, b, nb, part, st);
 }
 
 hipError_t launch_pred_init(int dtype, const void *d, int32_t *p, int n, int64_t ld,

@@ -47,6 +47,31 @@ template <> struct Ar<int32_t> {
     __device__ __forceinline__ static bool unreachable(int32_t v) { return v > kI32Inf / 2; }
 };
 
+// The (max, min) semiring through the same code: "add" is min (a path is as
+// wide as its narrowest edge) and "min" is max (keep the widest path).  The
+// padding value is the max-identity, so padded vertices stay isolated.  Over
+// {0, 1} this is the transitive closure.  min and max are exact, so every
+// order of the updates gives the same bits.
+template <typename T> struct ArMaxMin;
+
+template <> struct ArMaxMin<float> {
+    __device__ __forceinline__ static float inf() { return -__builtin_inff(); }
+    __device__ __forceinline__ static float add(float a, float b) { return __builtin_fminf(a, b); }
+    __device__ __forceinline__ static float min2(float a, float b) { return __builtin_fmaxf(a, b); }
+    __device__ __forceinline__ static float min3(float a, float b, float c) {
+        return __builtin_fmaxf(__builtin_fmaxf(a, b), c);
+    }
+};
+
+template <> struct ArMaxMin<int32_t> {
+    __device__ __forceinline__ static int32_t inf() { return (int32_t)0x80000000; }
+    __device__ __forceinline__ static int32_t add(int32_t a, int32_t b) { return a < b ? a : b; }
+    __device__ __forceinline__ static int32_t min2(int32_t a, int32_t b) { return a > b ? a : b; }
+    __device__ __forceinline__ static int32_t min3(int32_t a, int32_t b, int32_t c) {
+        return min2(min2(a, b), c);
+    }
+};
+
 // Lexicographic minimum of (distance, last hop): the candidate replaces the
 // current pair when it is strictly shorter, or equally short with a smaller
 // last hop.  This keeps, for every pair, the smallest last hop over all
@@ -130,7 +155,7 @@ constexpr int closure_smem_bytes() {
     return 4 * S * (int)sizeof(T) + (PRED ? 2 * S * 4 : 0);
 }
 
-template <typename T, int S, int TM, bool PRED>
+template <typename T, int S, int TM, bool PRED, class A = Ar<T>>
 __device__ __forceinline__ void closure_tile(T *__restrict__ d, int32_t *__restrict__ P, int n,
                                              int64_t ld, int64_t ldp, int base, char *smem) {
     constexpr int G = S / TM;
@@ -148,7 +173,7 @@ __device__ __forceinline__ void closure_tile(T *__restrict__ d, int32_t *__restr
         for (int q = 0; q < TM; ++q) {
             const int gj = base + tx * TM + q;
             const bool ok = gi < n && gj < n;
-            c[r][q] = ok ? d[(int64_t)gi * ld + gj] : Ar<T>::inf();
+            c[r][q] = ok ? d[(int64_t)gi * ld + gj] : A::inf();
             if constexpr (PRED) pc[r][q] = ok ? P[(int64_t)gi * ldp + gj] : kPredNone;
         }
     }
@@ -185,11 +210,11 @@ __device__ __forceinline__ void closure_tile(T *__restrict__ d, int32_t *__restr
             for (int i = 0; i < TM; ++i)
 #pragma unroll
                 for (int j = 0; j < TM; ++j) {
-                    const T cand = Ar<T>::add(ck[i], rk[j]);
+                    const T cand = A::add(ck[i], rk[j]);
                     if constexpr (PRED)
                         lex_update(c[i][j], pc[i][j], cand, pk[j]);
                     else
-                        c[i][j] = Ar<T>::min2(c[i][j], cand);
+                        c[i][j] = A::min2(c[i][j], cand);
                 }
         }
     }
@@ -229,7 +254,7 @@ constexpr int product_smem_bytes() {
     return 4 * BK * S * (int)sizeof(T) + (PRED ? 2 * BK * S * 4 : 0);
 }
 
-template <typename T, int S, int BK, int TM, int TN, bool VEC, bool PRED>
+template <typename T, int S, int BK, int TM, int TN, bool VEC, bool PRED, class A = Ar<T>>
 __device__ __forceinline__ void product_tile(T *__restrict__ d, int32_t *__restrict__ P, int n,
                                              int64_t ld, int64_t ldp, int bi, int bj, int b,
                                              char *smem) {
@@ -253,7 +278,7 @@ __device__ __forceinline__ void product_tile(T *__restrict__ d, int32_t *__restr
     const int tx = tid % GX, ty = tid / GX;
     const int row0 = bi * S, col0 = bj * S, k0 = b * S;
     const bool full = (row0 + S <= n) && (col0 + S <= n) && (k0 + S <= n);
-    const T INF = Ar<T>::inf();
+    const T INF = A::inf();
 
     const int ia = tid / TPA, ka = (tid % TPA) * EA;
     const int kbr = tid / TPB, jb = (tid % TPB) * EB;
@@ -323,16 +348,16 @@ __device__ __forceinline__ void product_tile(T *__restrict__ d, int32_t *__restr
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
                     for (int j = 0; j < TN; ++j) {
-                        lex_update(acc[i][j], accp[i][j], Ar<T>::add(a0[i], b0[j]), p0[j]);
-                        lex_update(acc[i][j], accp[i][j], Ar<T>::add(a1[i], b1[j]), p1[j]);
+                        lex_update(acc[i][j], accp[i][j], A::add(a0[i], b0[j]), p0[j]);
+                        lex_update(acc[i][j], accp[i][j], A::add(a1[i], b1[j]), p1[j]);
                     }
             } else {
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
                     for (int j = 0; j < TN; ++j)
-                        acc[i][j] = Ar<T>::min3(acc[i][j], Ar<T>::add(a0[i], b0[j]),
-                                                Ar<T>::add(a1[i], b1[j]));
+                        acc[i][j] = A::min3(acc[i][j], A::add(a0[i], b0[j]),
+                                                A::add(a1[i], b1[j]));
             }
         }
         if (s + 1 < NS) stash(cur ^ 1);
