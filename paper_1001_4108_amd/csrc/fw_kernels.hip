@@ -45,7 +45,10 @@ diag_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
 //   mode 0: blockIdx.x enumerates the 2(nb-1) panel tiles of stage b;
 //   mode 1: blockIdx.x enumerates the (nb-1)^2 bulk tiles;
 //   mode 2: the 2(nb-1)-1 bulk tiles in row or column b+1 (look-ahead part);
-//   mode 3: the (nb-2)^2 remaining bulk tiles.
+//   mode 3: the (nb-2)^2 remaining bulk tiles;
+//   mode 4: the 2(nb-1)-1 bulk tiles in the last block row or column (the
+//           part of the bulk that bulk_dma_kernel leaves when the last block
+//           is partial).
 template <typename T, int S, int BK, int TM, int TN, bool VEC, bool PRED, class A>
 __global__ void __launch_bounds__((S / TM) * (S / TN))
 tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64_t ldp, int b,
@@ -56,9 +59,29 @@ tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
     case 0: panel_coords(blockIdx.x, b, nb - 1, bi, bj); break;
     case 1: bulk_coords(blockIdx.x, b, nb - 1, bi, bj); break;
     case 2: ahead_coords(blockIdx.x, b, nb - 1, bi, bj); break;
-    default: rest_coords(blockIdx.x, b, nb - 1, bi, bj); break;
+    case 3: rest_coords(blockIdx.x, b, nb - 1, bi, bj); break;
+    default: edge_coords(blockIdx.x, b, nb - 1, bi, bj); break;
     }
     product_tile<T, S, BK, TM, TN, VEC, PRED, A>(d, P, n, ld, ldp, bi, bj, b, smem);
+}
+
+#ifndef FW_BULK_DMA
+#define FW_BULK_DMA 1
+#endif
+#ifndef FW_BULK_DMA_WAVES
+#define FW_BULK_DMA_WAVES 4
+#endif
+
+// Phase 3 for 128-wide tiles without predecessors and with 16-byte aligned
+// rows: the bulk tiles among the first nf full blocks (blockIdx.x enumerates
+// (nf-1)^2 of them, mf = nf - 1), slices copied into LDS directly
+// (bulk_tile_dma); four waves per SIMD.
+template <typename T, class A>
+__global__ void __launch_bounds__(256, FW_BULK_DMA_WAVES)
+bulk_dma_kernel(T *__restrict__ d, int64_t ld, int b, int mf) {
+    int bi, bj;
+    bulk_coords(blockIdx.x, b, mf, bi, bj);
+    bulk_tile_dma<T, A>(d, ld, bi, bj, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -125,6 +148,7 @@ hipError_t diag_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, in
     return hipGetLastError();
 }
 
+
 #ifndef FW_PRED128_TM
 #define FW_PRED128_TM 4
 #define FW_PRED128_TN 4
@@ -179,6 +203,24 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
     } else {
         if (p) return hipErrorInvalidValue;
     }
+#if FW_BULK_DMA
+    // Stage with a full k-block: full tiles through bulk_dma_kernel, the
+    // tiles of a partial last block (if any) through tile_kernel mode 4.
+    // The per-lane copy offsets are 32-bit: ld stays below 2^25.
+    const int nf = n / 128;
+    if (mode == 1 && tile == 128 && vec && b < nf && ld < (int64_t(1) << 25)) {
+        const int64_t mf = nf - 1;
+        if (mf > 0) {
+            bulk_dma_kernel<T, A><<<(unsigned)(mf * mf), 256, 0, st>>>(d, ld, b, (int)mf);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (nf < nb)
+            return tile_t<T, true, false, A>(tile, d, p, n, ld, ldp, b, nb, 4,
+                                             (unsigned)(2 * m - 1), st);
+        return hipSuccess;
+    }
+#endif
     return vec ? tile_t<T, true, false, A>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid, st)
                : tile_t<T, false, false, A>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid,
                                             st);

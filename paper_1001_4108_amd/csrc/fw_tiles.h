@@ -373,6 +373,132 @@ __device__ __forceinline__ void product_tile(T *__restrict__ d, int32_t *__restr
     }
 }
 
+// ---------------------------------------------------------------------------
+// bulk_tile_dma: the 128 x 128 tile update of product_tile (no predecessors)
+// for a tile that lies inside the matrix with a full k-block, the k-slices
+// moved from global memory straight into LDS by gfx950's global->LDS dwordx4
+// loads instead of through registers.  A thread keeps only its 8 x 8 cells
+// and one k-pair of operands, so four waves fit on a SIMD where the
+// register-staged form fits three, and the copy costs no LDS store
+// instructions.
+//
+// LDS layout (four separate arrays, so that the compiler's wait-count
+// tracking can tell the buffer being filled from the one being read):
+//   A slice: 128 rows x 16 k, row-major as in global memory; the four
+//            16-byte chunks of row r are permuted, chunk c stored at
+//            position c ^ ((r / 8) % 4), so that the 4 rows one wave reads
+//            together fall in different banks;
+//   B slice: 16 k x 128 columns, as in global memory.
+// Requirements on the caller: 256 threads, 16-byte aligned rows (base
+// aligned, ld % 4 == 0), tile and k-block inside the matrix.  Per cell the
+// same candidates are formed, one add each, as in product_tile, hence the
+// same bits.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+    using type = float2;
+};
+template <>
+struct Pair<int32_t> {
+    using type = int2;
+};
+
+template <typename T, class A = Ar<T>>
+__device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int64_t ld, int bi, int bj,
+                                              int b) {
+    static_assert(sizeof(T) == 4, "32-bit values");
+    constexpr int S = 128, BK = 16, TM = 8, NS = S / BK;
+    static_assert(NS % 2 == 0, "slices alternate between two buffers");
+    __shared__ __align__(16) T A0[S * BK];
+    __shared__ __align__(16) T A1[S * BK];
+    __shared__ __align__(16) T B0[BK * S];
+    __shared__ __align__(16) T B1[BK * S];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tx = tid & 15, ty = tid >> 4;
+    const int64_t row0 = (int64_t)bi * S, col0 = (int64_t)bj * S, k0 = (int64_t)b * S;
+
+    T acc[TM][TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+        row_load<T, TM, true>(acc[i], d, (int)row0 + ty * TM + i, (int)col0 + tx * TM, 0, ld,
+                              true, T(0));
+
+    // Copy sources: wave-uniform bases plus 32-bit per-lane offsets.  The
+    // wave copies A rows 32*wave + lane/4 (and +16) and B k-rows
+    // 4*wave + lane/32 (and +2) of each slice.
+    const T *a_base = d + (row0 + wave * 32) * ld + k0;
+    const T *b_base = d + (k0 + wave * 4) * ld + col0;
+    const int ar = wave * 32 + (lane >> 2);
+    const uint32_t a_off0 = (uint32_t)((lane >> 2) * ld) + (((lane & 3) ^ ((ar >> 3) & 3)) << 2);
+    const uint32_t a_off1 =
+        (uint32_t)(((lane >> 2) + 16) * ld) + (((lane & 3) ^ (((ar + 16) >> 3) & 3)) << 2);
+    const uint32_t b_off0 = (uint32_t)((lane >> 5) * ld) + ((lane & 31) << 2);
+    const uint32_t b_off1 = b_off0 + (uint32_t)(2 * ld);
+    auto issue = [&](int s, T *Ad, T *Bd) {
+        const T *as = a_base + s * BK;
+        const T *bs = b_base + (int64_t)s * BK * ld;
+        T *a = Ad + wave * 32 * BK;
+        T *bb = Bd + wave * 4 * S;
+        __builtin_amdgcn_global_load_lds(as + a_off0, (lds_void_t *)a, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(as + a_off1, (lds_void_t *)(a + 16 * BK), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(bs + b_off0, (lds_void_t *)bb, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(bs + b_off1, (lds_void_t *)(bb + 2 * S), 16, 0, 0);
+    };
+    auto compute = [&](const T *Ab, const T *Bb) {
+        // one k-pair per iteration (see product_tile)
+#pragma unroll 1
+        for (int kk = 0; kk < BK; kk += 2) {
+            const int aoff = ty * (TM * BK) + (((kk >> 2) ^ (ty & 3)) << 2) + (kk & 3);
+            T a0[TM], a1[TM], b0[TM], b1[TM];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const typename Pair<T>::type v =
+                    *reinterpret_cast<const typename Pair<T>::type *>(Ab + aoff + i * BK);
+                a0[i] = v.x;
+                a1[i] = v.y;
+            }
+#pragma unroll
+            for (int j = 0; j < TM; ++j) {
+                b0[j] = Bb[kk * S + tx * TM + j];
+                b1[j] = Bb[(kk + 1) * S + tx * TM + j];
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TM; ++j)
+                    acc[i][j] = A::min3(acc[i][j], A::add(a0[i], b0[j]), A::add(a1[i], b1[j]));
+        }
+    };
+
+    // vmcnt(0): this wave's copies (and its C loads) have landed; the
+    // barrier after it makes every wave's copies visible and guarantees that
+    // every wave is done reading the buffer the next copy overwrites
+    constexpr int kWaitVm0 = 0x0F70;
+    issue(0, A0, B0);
+#pragma unroll 1
+    for (int s = 0; s < NS; s += 2) {
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        __syncthreads();
+        issue(s + 1, A1, B1);
+        compute(A0, B0);
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        __syncthreads();
+        if (s + 2 < NS) issue(s + 2, A0, B0);
+        compute(A1, B1);
+    }
+
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+        row_store<T, TM, true>(acc[i], d, (int)row0 + ty * TM + i, (int)col0 + tx * TM, 0, ld,
+                               true);
+}
+
 // Tile coordinates of the stage-b panel tile number idx (0 <= idx < 2m,
 // m = nb - 1): the row panel (b, j != b) first, then the column panel.
 __device__ __forceinline__ void panel_coords(int idx, int b, int m, int &bi, int &bj) {
@@ -406,6 +532,21 @@ __device__ __forceinline__ void ahead_coords(int idx, int b, int m, int &bi, int
         idx -= m;
         bi = idx < b ? idx : idx + 2;
         bj = b + 1;
+    }
+}
+
+// Bulk tiles of stage b (b < nb - 1) that lie in the last block row or
+// column, nb - 1 being a partial block: 2m - 1 of them (m = nb - 1).  The
+// other bulk tiles are the (m - 1)^2 of bulk_coords over the first nb - 1
+// blocks.
+__device__ __forceinline__ void edge_coords(int idx, int b, int m, int &bi, int &bj) {
+    if (idx < m) {
+        bi = m;
+        bj = idx < b ? idx : idx + 1;
+    } else {
+        idx -= m;
+        bi = idx < b ? idx : idx + 1;
+        bj = m;
     }
 }
 
