@@ -423,11 +423,23 @@ __device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int64_t ld, int
     const int tx = tid & 15, ty = tid >> 4;
     const int64_t row0 = (int64_t)bi * S, col0 = (int64_t)bj * S, k0 = (int64_t)b * S;
 
+    // thread (tx, ty) owns rows 8*ty .. 8*ty + 7 and the two 4-column groups
+    // starting at 4*tx and 64 + 4*tx: the 16 column groups a B read touches
+    // are contiguous, so the read has no bank conflicts
     T acc[TM][TM];
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
-        row_load<T, TM, true>(acc[i], d, (int)row0 + ty * TM + i, (int)col0 + tx * TM, 0, ld,
-                              true, T(0));
+    for (int i = 0; i < TM; ++i) {
+        T *row = d + (row0 + ty * TM + i) * ld + col0 + tx * 4;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const typename Vec4<T>::type x =
+                *reinterpret_cast<const typename Vec4<T>::type *>(row + h * 64);
+            acc[i][4 * h] = x[0];
+            acc[i][4 * h + 1] = x[1];
+            acc[i][4 * h + 2] = x[2];
+            acc[i][4 * h + 3] = x[3];
+        }
+    }
 
     // Copy sources: wave-uniform bases plus 32-bit per-lane offsets.  The
     // wave copies A rows 32*wave + lane/4 (and +16) and B k-rows
@@ -465,8 +477,9 @@ __device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int64_t ld, int
             }
 #pragma unroll
             for (int j = 0; j < TM; ++j) {
-                b0[j] = Bb[kk * S + tx * TM + j];
-                b1[j] = Bb[(kk + 1) * S + tx * TM + j];
+                const int c = (j >> 2) * 64 + tx * 4 + (j & 3);
+                b0[j] = Bb[kk * S + c];
+                b1[j] = Bb[(kk + 1) * S + c];
             }
 #pragma unroll
             for (int i = 0; i < TM; ++i)
@@ -494,9 +507,18 @@ __device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int64_t ld, int
     }
 
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
-        row_store<T, TM, true>(acc[i], d, (int)row0 + ty * TM + i, (int)col0 + tx * TM, 0, ld,
-                               true);
+    for (int i = 0; i < TM; ++i) {
+        T *row = d + (row0 + ty * TM + i) * ld + col0 + tx * 4;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            typename Vec4<T>::type x;
+            x[0] = acc[i][4 * h];
+            x[1] = acc[i][4 * h + 1];
+            x[2] = acc[i][4 * h + 2];
+            x[3] = acc[i][4 * h + 3];
+            *reinterpret_cast<typename Vec4<T>::type *>(row + h * 64) = x;
+        }
+    }
 }
 
 // Tile coordinates of the stage-b panel tile number idx (0 <= idx < 2m,
