@@ -68,6 +68,9 @@ tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
 #ifndef FW_BULK_DMA
 #define FW_BULK_DMA 1
 #endif
+#ifndef FW_PANEL_STRIPS
+#define FW_PANEL_STRIPS 1
+#endif
 #ifndef FW_BULK_DMA_WAVES
 #define FW_BULK_DMA_WAVES 4
 #endif
@@ -82,6 +85,25 @@ bulk_dma_kernel(T *__restrict__ d, int64_t ld, int b, int mf) {
     int bi, bj;
     bulk_coords(blockIdx.x, b, mf, bi, bj);
     bulk_tile_dma<T, A>(d, ld, bi, bj, b);
+}
+
+// Phase 2 for 128-wide tiles without predecessors: each panel tile as four
+// strips (strip_tile), blockIdx.x = 4 * (panel tile number) + strip.  Row
+// panel tiles (b, j) are cut into 32-column strips, column panel tiles
+// (i, b) into 32-row strips.
+template <typename T, bool VEC, class A>
+__global__ void __launch_bounds__(256)
+panel_strip_kernel(T *__restrict__ d, int n, int64_t ld, int b, int nb) {
+    constexpr int S = 128, W = 32;
+    __shared__ __align__(16) char smem[strip_smem_bytes<T, S, W, S, 16>()];  // R + CW = 160 either way
+    const int m = nb - 1;
+    const int t = blockIdx.x >> 2, q = blockIdx.x & 3;
+    int bi, bj;
+    panel_coords(t, b, m, bi, bj);
+    if (t < m)  // row panel: rows of block b, a 32-column strip of block bj
+        strip_tile<T, S, W, S, 16, 4, 4, VEC, A>(d, n, ld, b * S, bj * S + q * W, b * S, smem);
+    else        // column panel: a 32-row strip of block bi, columns of block b
+        strip_tile<T, W, S, S, 16, 4, 4, VEC, A>(d, n, ld, bi * S + q * W, b * S, b * S, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -203,6 +225,16 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
     } else {
         if (p) return hipErrorInvalidValue;
     }
+#if FW_PANEL_STRIPS
+    if (mode == 0 && tile == 128) {
+        if (4 * grid > 0x7fffffffLL) return hipErrorInvalidValue;
+        if (vec)
+            panel_strip_kernel<T, true, A><<<(unsigned)(4 * grid), 256, 0, st>>>(d, n, ld, b, nb);
+        else
+            panel_strip_kernel<T, false, A><<<(unsigned)(4 * grid), 256, 0, st>>>(d, n, ld, b, nb);
+        return hipGetLastError();
+    }
+#endif
 #if FW_BULK_DMA
     // Stage with a full k-block: full tiles through bulk_dma_kernel, the
     // tiles of a partial last block (if any) through tile_kernel mode 4.

@@ -521,6 +521,94 @@ __device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int64_t ld, int
     }
 }
 
+// ---------------------------------------------------------------------------
+// strip_tile: the panel update of product_tile on one strip of a panel tile,
+// R rows x CW columns with the full k-block of K, so that a stage's 2(nb-1)
+// panel tiles give four times as many workgroups (one 128 x 128 tile per
+// workgroup leaves a CU with a single wave per SIMD).  A row-panel tile is
+// cut into column strips and a column-panel tile into row strips: the panel
+// operand a strip reads (its own columns of B, or its own rows of A) is then
+// exactly the part it writes, and no two workgroups touch the same cell.
+// Same per-cell candidates as product_tile, hence the same bits.
+// ---------------------------------------------------------------------------
+template <typename T, int R, int CW, int K, int BK>
+constexpr int strip_smem_bytes() {
+    return 2 * BK * (R + CW) * (int)sizeof(T);
+}
+
+template <typename T, int R, int CW, int K, int BK, int TM, int TN, bool VEC, class A = Ar<T>>
+__device__ __forceinline__ void strip_tile(T *__restrict__ d, int n, int64_t ld, int row0,
+                                           int col0, int k0, char *smem) {
+    constexpr int GX = CW / TN, GY = R / TM, NT = GX * GY;
+    constexpr int EA = R * BK / NT, TPA = BK / EA;   // A slice: elements per thread
+    constexpr int EB = BK * CW / NT, TPB = CW / EB;  // B slice
+    constexpr int NS = K / BK;
+    static_assert(EA * NT == R * BK && EB * NT == BK * CW, "slice split");
+    static_assert(TPA * EA == BK && TPB * EB == CW, "slice rows");
+    static_assert(!VEC || TN % 4 == 0, "vector split");
+    // a slice share of fewer than 4 values per thread is loaded element-wise
+    constexpr bool VA = VEC && EA % 4 == 0, VB = VEC && EB % 4 == 0;
+    static_assert(BK % 2 == 0 && K % BK == 0, "k-steps are fused in pairs");
+
+    T(*As)[BK][R] = reinterpret_cast<T(*)[BK][R]>(smem);
+    T(*Bs)[BK][CW] = reinterpret_cast<T(*)[BK][CW]>(smem + 2 * BK * R * sizeof(T));
+
+    const int tid = threadIdx.x;
+    const int tx = tid % GX, ty = tid / GX;
+    const bool full = (row0 + R <= n) && (col0 + CW <= n) && (k0 + K <= n);
+    const T INF = A::inf();
+    const int ia = tid / TPA, ka = (tid % TPA) * EA;
+    const int kbr = tid / TPB, jb = (tid % TPB) * EB;
+
+    T ra[EA], rb[EB];
+    auto fetch = [&](int s) {
+        row_load<T, EA, VA>(ra, d, row0 + ia, k0 + s * BK + ka, n, ld, full, INF);
+        row_load<T, EB, VB>(rb, d, k0 + s * BK + kbr, col0 + jb, n, ld, full, INF);
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < EA; ++e) As[buf][ka + e][ia] = ra[e];
+#pragma unroll
+        for (int e = 0; e < EB; ++e) Bs[buf][kbr][jb + e] = rb[e];
+    };
+
+    T acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+        row_load<T, TN, VEC>(acc[i], d, row0 + ty * TM + i, col0 + tx * TN, n, ld, full, INF);
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int s = 0; s < NS; ++s) {
+        const int cur = s & 1;
+        if (s + 1 < NS) fetch(s + 1);
+#pragma unroll 1
+        for (int kk = 0; kk < BK; kk += 2) {
+            T a0[TM], a1[TM], b0[TN], b1[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                a0[i] = As[cur][kk][ty * TM + i];
+                a1[i] = As[cur][kk + 1][ty * TM + i];
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                b0[j] = Bs[cur][kk][tx * TN + j];
+                b1[j] = Bs[cur][kk + 1][tx * TN + j];
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = A::min3(acc[i][j], A::add(a0[i], b0[j]), A::add(a1[i], b1[j]));
+        }
+        if (s + 1 < NS) stash(cur ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+        row_store<T, TN, VEC>(acc[i], d, row0 + ty * TM + i, col0 + tx * TN, n, ld, full);
+}
+
 // Tile coordinates of the stage-b panel tile number idx (0 <= idx < 2m,
 // m = nb - 1): the row panel (b, j != b) first, then the column panel.
 __device__ __forceinline__ void panel_coords(int idx, int b, int m, int &bi, int &bj) {
