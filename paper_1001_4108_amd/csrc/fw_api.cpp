@@ -230,7 +230,9 @@ int enqueue_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t 
             return launch_panels(dtype, sr, tile, d, pred, n, ld, ldp, b, nb, s);
         });
     };
-    auto bulk = [&](int b, int part, hipStream_t s) {
+    // close_next: the launch also closes the next diagonal tile (its updates
+    // are counted with the bulk's, the launch that does them)
+    auto bulk = [&](int b, int part, hipStream_t s, bool close_next = false) {
         const double kb = real(b), r1 = real(b + 1), rest = nn - kb;
         double upd = kb * rest * rest;
         int kind = kBulk;
@@ -240,17 +242,21 @@ int enqueue_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t 
         } else if (part == kBulkRestPart) {
             upd = kb * (rest - r1) * (rest - r1);
         }
+        if (close_next) upd += r1 * r1 * r1;
         return timed(kind, upd, s, [&] {
-            return launch_bulk(dtype, sr, tile, d, pred, n, ld, ldp, b, nb, part, s);
+            return launch_bulk(dtype, sr, tile, d, pred, n, ld, ldp, b, nb, part, close_next, s);
         });
     };
 
     if (!lookahead || nb < 3) {
+        bool closed = false;  // the previous bulk launch closed this stage's diagonal tile
         for (int b = 0; b < nb; ++b) {
-            if ((e = diag(b, st)) != hipSuccess) return status_of(e);
+            if (!closed && (e = diag(b, st)) != hipSuccess) return status_of(e);
+            closed = false;
             if (nb > 1) {
                 if ((e = panels(b, st)) != hipSuccess) return status_of(e);
-                if ((e = bulk(b, kBulkAll, st)) != hipSuccess) return status_of(e);
+                closed = bulk_closes_next_diag(tile, d, pred, n, ld, b);
+                if ((e = bulk(b, kBulkAll, st, closed)) != hipSuccess) return status_of(e);
             }
         }
     } else {

@@ -68,6 +68,9 @@ tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
 #ifndef FW_BULK_DMA
 #define FW_BULK_DMA 1
 #endif
+#ifndef FW_FUSE_DIAG
+#define FW_FUSE_DIAG 1
+#endif
 #ifndef FW_PANEL_STRIPS
 #define FW_PANEL_STRIPS 1
 #endif
@@ -79,12 +82,21 @@ tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
 // rows: the bulk tiles among the first nf full blocks (blockIdx.x enumerates
 // (nf-1)^2 of them, mf = nf - 1), slices copied into LDS directly
 // (bulk_tile_dma); four waves per SIMD.
+//
+// With close_next (b + 1 < nf), the workgroup of tile (b+1, b+1) -- the next
+// stage's diagonal tile, whose stage-b value it alone computes -- also runs
+// that tile's closure, which replaces the next stage's phase-1 launch.  It
+// takes blockIdx 0 (swapped with the tile enumerated first) so that it is
+// dispatched early and its longer run overlaps the rest of the bulk.
 template <typename T, class A>
 __global__ void __launch_bounds__(256, FW_BULK_DMA_WAVES)
-bulk_dma_kernel(T *__restrict__ d, int64_t ld, int b, int mf) {
+bulk_dma_kernel(T *__restrict__ d, int n, int64_t ld, int b, int mf, int close_next) {
+    int idx = blockIdx.x;
+    const int dix = b * mf + b;  // enumeration index of tile (b+1, b+1)
+    if (close_next) idx = idx == 0 ? dix : idx == dix ? 0 : idx;
     int bi, bj;
-    bulk_coords(blockIdx.x, b, mf, bi, bj);
-    bulk_tile_dma<T, A>(d, ld, bi, bj, b);
+    bulk_coords(idx, b, mf, bi, bj);
+    bulk_tile_dma<T, A>(d, n, ld, bi, bj, b, close_next && idx == dix);
 }
 
 // Phase 2 for 128-wide tiles without predecessors: each panel tile as four
@@ -206,15 +218,29 @@ hipError_t tile_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, in
     return hipGetLastError();
 }
 
+// The bulk of stage b goes through bulk_dma_kernel: 128-wide tiles, no
+// predecessors, 16-byte aligned rows, a full k-block, and 32-bit per-lane
+// copy offsets (ld below 2^25).
+bool bulk_copy_path(int tile, bool vec, int n, int64_t ld, int b) {
+#if FW_BULK_DMA
+    return tile == 128 && vec && b < n / 128 && ld < (int64_t(1) << 25);
+#else
+    (void)tile, (void)vec, (void)n, (void)ld, (void)b;
+    return false;
+#endif
+}
+
 template <typename T, class A, bool ALLOW_PRED>
 hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b,
-                         int nb, int mode, hipStream_t st) {
+                         int nb, int mode, bool close_next, hipStream_t st) {
     const int64_t m = nb - 1;
     const int64_t grid = mode == 0 ? 2 * m : mode == 1 ? m * m : mode == 2 ? 2 * m - 1
                                                                            : (m - 1) * (m - 1);
-    if (grid <= 0) return hipSuccess;
+    if (grid <= 0) return close_next ? hipErrorInvalidValue : hipSuccess;
     if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
     const bool vec = vec_ok(d, ld) && (p == nullptr || vec_ok(p, ldp));
+    if (close_next && (p || mode != 1 || !bulk_copy_path(tile, vec, n, ld, b)))
+        return hipErrorInvalidValue;
     if constexpr (ALLOW_PRED) {
         if (p) {
             return vec ? tile_t<T, true, true, A>(tile, d, p, n, ld, ldp, b, nb, mode,
@@ -235,15 +261,15 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
         return hipGetLastError();
     }
 #endif
-#if FW_BULK_DMA
     // Stage with a full k-block: full tiles through bulk_dma_kernel, the
     // tiles of a partial last block (if any) through tile_kernel mode 4.
-    // The per-lane copy offsets are 32-bit: ld stays below 2^25.
     const int nf = n / 128;
-    if (mode == 1 && tile == 128 && vec && b < nf && ld < (int64_t(1) << 25)) {
+    if (mode == 1 && bulk_copy_path(tile, vec, n, ld, b)) {
         const int64_t mf = nf - 1;
+        if (close_next && b + 1 >= nf) return hipErrorInvalidValue;
         if (mf > 0) {
-            bulk_dma_kernel<T, A><<<(unsigned)(mf * mf), 256, 0, st>>>(d, ld, b, (int)mf);
+            bulk_dma_kernel<T, A><<<(unsigned)(mf * mf), 256, 0, st>>>(d, n, ld, b, (int)mf,
+                                                                      close_next ? 1 : 0);
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -252,7 +278,6 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
                                              (unsigned)(2 * m - 1), st);
         return hipSuccess;
     }
-#endif
     return vec ? tile_t<T, true, false, A>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid, st)
                : tile_t<T, false, false, A>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid,
                                             st);
@@ -260,10 +285,11 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
 
 template <typename T>
 hipError_t tile_any(int sr, int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b,
-                    int nb, int mode, hipStream_t st) {
+                    int nb, int mode, bool close_next, hipStream_t st) {
     if (sr == kMaxMin)
-        return tile_dispatch<T, ArMaxMin<T>, false>(tile, d, p, n, ld, ldp, b, nb, mode, st);
-    return tile_dispatch<T, Ar<T>, true>(tile, d, p, n, ld, ldp, b, nb, mode, st);
+        return tile_dispatch<T, ArMaxMin<T>, false>(tile, d, p, n, ld, ldp, b, nb, mode,
+                                                     close_next, st);
+    return tile_dispatch<T, Ar<T>, true>(tile, d, p, n, ld, ldp, b, nb, mode, close_next, st);
 }
 
 }  // namespace
@@ -286,14 +312,28 @@ hipError_t launch_diag(int dtype, int sr, int tile, void *d, int32_t *p, int n, 
 
 hipError_t launch_panels(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
                          int64_t ldp, int b, int nb, hipStream_t st) {
-    if (dtype == 0) return tile_any<float>(sr, tile, (float *)d, p, n, ld, ldp, b, nb, 0, st);
-    return tile_any<int32_t>(sr, tile, (int32_t *)d, p, n, ld, ldp, b, nb, 0, st);
+    if (dtype == 0)
+        return tile_any<float>(sr, tile, (float *)d, p, n, ld, ldp, b, nb, 0, false, st);
+    return tile_any<int32_t>(sr, tile, (int32_t *)d, p, n, ld, ldp, b, nb, 0, false, st);
+}
+
+bool bulk_closes_next_diag(int tile, const void *d, const int32_t *p, int n, int64_t ld,
+                           int b) {
+#if FW_FUSE_DIAG
+    return p == nullptr && bulk_copy_path(tile, vec_ok(d, ld), n, ld, b) && b + 1 < n / 128;
+#else
+    (void)tile, (void)d, (void)p, (void)n, (void)ld, (void)b;
+    return false;
+#endif
 }
 
 hipError_t launch_bulk(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
-                       int64_t ldp, int b, int nb, int part, hipStream_t st) {
-    if (dtype == 0) return tile_any<float>(sr, tile, (float *)d, p, n, ld, ldp, b, nb, part, st);
-    return tile_any<int32_t>(sr, tile, (int32_t *)d, p, n, ld, ldp, b, nb, part, st);
+                       int64_t ldp, int b, int nb, int part, bool close_next, hipStream_t st) {
+    if (dtype == 0)
+        return tile_any<float>(sr, tile, (float *)d, p, n, ld, ldp, b, nb, part, close_next,
+                               st);
+    return tile_any<int32_t>(sr, tile, (int32_t *)d, p, n, ld, ldp, b, nb, part, close_next,
+                             st);
 }
 
 hipError_t launch_pred_init(int dtype, const void *d, int32_t *p, int n, int64_t ld,

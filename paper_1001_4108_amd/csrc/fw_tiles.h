@@ -155,9 +155,12 @@ constexpr int closure_smem_bytes() {
     return 4 * S * (int)sizeof(T) + (PRED ? 2 * S * 4 : 0);
 }
 
-template <typename T, int S, int TM, bool PRED, class A = Ar<T>>
+// FULL: the caller guarantees a tile inside the matrix with 16-byte aligned
+// rows (no predecessors); cells move as 16-byte row pieces, no bounds tests.
+template <typename T, int S, int TM, bool PRED, class A = Ar<T>, bool FULL = false>
 __device__ __forceinline__ void closure_tile(T *__restrict__ d, int32_t *__restrict__ P, int n,
                                              int64_t ld, int64_t ldp, int base, char *smem) {
+    static_assert(!FULL || (!PRED && TM % 4 == 0), "full-tile form: no predecessors");
     constexpr int G = S / TM;
     T(*rowb)[S] = reinterpret_cast<T(*)[S]>(smem);
     T(*colb)[S] = reinterpret_cast<T(*)[S]>(smem + 2 * S * sizeof(T));
@@ -166,15 +169,22 @@ __device__ __forceinline__ void closure_tile(T *__restrict__ d, int32_t *__restr
     const int tx = threadIdx.x % G, ty = threadIdx.x / G;
     T c[TM][TM];
     int32_t pc[TM][TM];
+    if constexpr (FULL) {
 #pragma unroll
-    for (int r = 0; r < TM; ++r) {
-        const int gi = base + ty * TM + r;
+        for (int r = 0; r < TM; ++r)
+            row_load<T, TM, true>(c[r], d, base + ty * TM + r, base + tx * TM, n, ld, true,
+                                  A::inf());
+    } else {
 #pragma unroll
-        for (int q = 0; q < TM; ++q) {
-            const int gj = base + tx * TM + q;
-            const bool ok = gi < n && gj < n;
-            c[r][q] = ok ? d[(int64_t)gi * ld + gj] : A::inf();
-            if constexpr (PRED) pc[r][q] = ok ? P[(int64_t)gi * ldp + gj] : kPredNone;
+        for (int r = 0; r < TM; ++r) {
+            const int gi = base + ty * TM + r;
+#pragma unroll
+            for (int q = 0; q < TM; ++q) {
+                const int gj = base + tx * TM + q;
+                const bool ok = gi < n && gj < n;
+                c[r][q] = ok ? d[(int64_t)gi * ld + gj] : A::inf();
+                if constexpr (PRED) pc[r][q] = ok ? P[(int64_t)gi * ldp + gj] : kPredNone;
+            }
         }
     }
 
@@ -186,14 +196,22 @@ __device__ __forceinline__ void closure_tile(T *__restrict__ d, int32_t *__restr
 #pragma unroll
         for (int r = 0; r < TM; ++r) {
             const int buf = (kb * TM + r) & 1;
-            if (ty == kb) {
+            int oty = ty, otx = tx;
+            if constexpr (FULL) {
+                // opaque copies (no instruction is emitted): otherwise the
+                // compiler threads the owner tests, equal across the TM
+                // unrolled steps, and duplicates the step code per owner
+                // class, which costs far more registers than the tile
+                asm volatile("" : "+v"(oty), "+v"(otx));
+            }
+            if (oty == kb) {
 #pragma unroll
                 for (int q = 0; q < TM; ++q) {
                     rowb[buf][tx * TM + q] = c[r][q];
                     if constexpr (PRED) rowp[buf][tx * TM + q] = pc[r][q];
                 }
             }
-            if (tx == kb) {
+            if (otx == kb) {
 #pragma unroll
                 for (int q = 0; q < TM; ++q) colb[buf][ty * TM + q] = c[q][r];
             }
@@ -216,18 +234,37 @@ __device__ __forceinline__ void closure_tile(T *__restrict__ d, int32_t *__restr
                     else
                         c[i][j] = A::min2(c[i][j], cand);
                 }
+            if constexpr (FULL) {
+                // finish this step's updates here: left alone, the compiler
+                // sinks them past later barriers and keeps every step's row
+                // and column live
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TM; ++j) asm volatile("" : "+v"(c[i][j]));
+            }
         }
     }
 
+    if constexpr (FULL) {
+        // addresses recomputed from opaque copies rather than kept live
+        // through the k loop
+        int sty = ty, stx = tx;
+        asm volatile("" : "+v"(sty), "+v"(stx));
 #pragma unroll
-    for (int r = 0; r < TM; ++r) {
-        const int gi = base + ty * TM + r;
+        for (int r = 0; r < TM; ++r)
+            row_store<T, TM, true>(c[r], d, base + sty * TM + r, base + stx * TM, n, ld, true);
+    } else {
 #pragma unroll
-        for (int q = 0; q < TM; ++q) {
-            const int gj = base + tx * TM + q;
-            if (gi < n && gj < n) {
-                d[(int64_t)gi * ld + gj] = c[r][q];
-                if constexpr (PRED) P[(int64_t)gi * ldp + gj] = pc[r][q];
+        for (int r = 0; r < TM; ++r) {
+            const int gi = base + ty * TM + r;
+#pragma unroll
+            for (int q = 0; q < TM; ++q) {
+                const int gj = base + tx * TM + q;
+                if (gi < n && gj < n) {
+                    d[(int64_t)gi * ld + gj] = c[r][q];
+                    if constexpr (PRED) P[(int64_t)gi * ldp + gj] = pc[r][q];
+                }
             }
         }
     }
@@ -392,7 +429,8 @@ __device__ __forceinline__ void product_tile(T *__restrict__ d, int32_t *__restr
 // Requirements on the caller: 256 threads, 16-byte aligned rows (base
 // aligned, ld % 4 == 0), tile and k-block inside the matrix.  Per cell the
 // same candidates are formed, one add each, as in product_tile, hence the
-// same bits.
+// same bits.  With `close` (uniform per workgroup; the tile is (b+1, b+1))
+// the tile's closure for stage b+1 follows the store.
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) void lds_void_t;
 
@@ -408,8 +446,8 @@ struct Pair<int32_t> {
 };
 
 template <typename T, class A = Ar<T>>
-__device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int64_t ld, int bi, int bj,
-                                              int b) {
+__device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int n, int64_t ld, int bi,
+                                              int bj, int b, bool close) {
     static_assert(sizeof(T) == 4, "32-bit values");
     constexpr int S = 128, BK = 16, TM = 8, NS = S / BK;
     static_assert(NS % 2 == 0, "slices alternate between two buffers");
@@ -506,9 +544,14 @@ __device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int64_t ld, int
         compute(A1, B1);
     }
 
+    // store addresses recomputed from opaque copies of the thread ids (no
+    // instruction is emitted): the load addresses would otherwise stay live
+    // through the k loop, 16 VGPRs
+    int stx = tx, sty = ty;
+    asm volatile("" : "+v"(stx), "+v"(sty));
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
-        T *row = d + (row0 + ty * TM + i) * ld + col0 + tx * 4;
+        T *row = d + (row0 + sty * TM + i) * ld + col0 + stx * 4;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             typename Vec4<T>::type x;
@@ -518,6 +561,14 @@ __device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int64_t ld, int
             x[3] = acc[i][4 * h + 3];
             *reinterpret_cast<typename Vec4<T>::type *>(row + h * 64) = x;
         }
+    }
+    if (close) {
+        // the next stage's diagonal tile: reread by the same workgroup (the
+        // barrier orders its stores before the loads) and closed in place;
+        // the product's LDS buffers are free by now
+        __syncthreads();
+        closure_tile<T, S, TM, false, A, true>(d, nullptr, n, ld, 0, (int)row0,
+                                               reinterpret_cast<char *>(A0));
     }
 }
 
