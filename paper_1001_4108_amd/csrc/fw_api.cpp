@@ -435,10 +435,10 @@ int validate_matrix(const void *d, int dtype, int64_t n, int64_t ld, const int32
     return validate(d, dtype, n, ld, pred, ldp);
 }
 
-hipError_t timed_launch_batched(double updates, hipStream_t st, int dtype, bool pred,
+hipError_t timed_launch_batched(double updates, hipStream_t st, int dtype, bool pred, bool big,
                                 BatchHeader *hdr, const BatchItem *items, int grid) {
     return timed(kBatched, updates, st,
-                 [&] { return launch_batched_raw(dtype, pred, hdr, items, grid, st); });
+                 [&] { return launch_batched_raw(dtype, pred, hdr, items, grid, st, big); });
 }
 
 }  // namespace fw

@@ -1,17 +1,21 @@
-// Batched solves: many independent graphs in one persistent launch.
+// Batched solves: many independent graphs in one batch plan.
 //
-// Each workgroup repeatedly takes the next graph from a device work counter
-// (graphs are ordered largest first) and solves it alone:
+// Graphs of FW_STAGED_MIN_N vertices and more are stage-batched: per tile
+// size, each stage b of the blocked schedule (section 3.2) is three launches
+// shared by every graph that has a stage b -- all their diagonal tiles, all
+// their panel tiles, all their bulk tiles -- so a large graph is spread over
+// the whole GPU instead of one workgroup.  The smaller graphs go through one
+// persistent launch in which each workgroup repeatedly takes the next graph
+// from a device work counter (largest first) and solves it alone:
 //   * n <= tile: closure_tile over the whole graph -- the plain algorithm of
 //     section 3.1 with one barrier per k-step;
-//   * n >  tile: the blocked schedule of section 3.2 run inside the
-//     workgroup (diagonal tile, panel tiles, bulk tiles, workgroup barriers
-//     between the phases).
+//   * n >  tile: the blocked schedule run inside the workgroup (diagonal
+//     tile, panel tiles, bulk tiles, workgroup barriers between the phases).
 // The tile comes from the same plan table as single-graph solves and the
 // per-cell work is the same code (fw_tiles.h), so a graph's bits do not
 // depend on whether it was solved alone or in a batch.
 //
-// No workgroup ever waits for another one, so the grid always drains.
+// No workgroup ever waits for another one, so every grid drains.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,9 +34,10 @@ namespace {
 
 constexpr int kBatchThreads = 256;
 
-template <typename T, bool PRED>
+// LDS of the persistent kernel whose largest tile is MAXS.
+template <typename T, bool PRED, int MAXS>
 constexpr int batch_smem_bytes() {
-    return product_smem_bytes<T, 128, 16, PRED>();
+    return product_smem_bytes<T, MAXS, 16, PRED>();
 }
 
 template <typename T, int S, int TMC, int TM, bool VEC, bool PRED>
@@ -57,7 +62,7 @@ __device__ void blocked_in_wg(T *d, int32_t *p, int n, int64_t ld, int64_t ldp, 
     }
 }
 
-template <typename T, bool PRED>
+template <typename T, bool PRED, int MAXS>
 __device__ void solve_graph(const BatchItem &it, char *smem) {
     T *d = static_cast<T *>(it.d);
     int32_t *p = PRED ? it.p : nullptr;
@@ -83,10 +88,12 @@ __device__ void solve_graph(const BatchItem &it, char *smem) {
                 blocked_in_wg<T, 64, 4, 4, false, PRED>(d, p, n, ld, ldp, smem);
             break;
         default:
-            if (it.vec)
-                blocked_in_wg<T, 128, 8, 8, true, PRED>(d, p, n, ld, ldp, smem);
-            else
-                blocked_in_wg<T, 128, 8, 8, false, PRED>(d, p, n, ld, ldp, smem);
+            if constexpr (MAXS == 128) {
+                if (it.vec)
+                    blocked_in_wg<T, 128, 8, 8, true, PRED>(d, p, n, ld, ldp, smem);
+                else
+                    blocked_in_wg<T, 128, 8, 8, false, PRED>(d, p, n, ld, ldp, smem);
+            }
             break;
         }
     }
@@ -100,10 +107,13 @@ __device__ void solve_graph(const BatchItem &it, char *smem) {
     }
 }
 
-template <typename T, bool PRED>
-__global__ void __launch_bounds__(kBatchThreads, PRED ? 2 : 3)
+// MAXS: the largest tile among the graphs of the launch.  Without the
+// 128-wide path the kernel needs under 100 VGPRs, so more workgroups share a
+// CU.
+template <typename T, bool PRED, int MAXS>
+__global__ void __launch_bounds__(kBatchThreads, PRED ? 2 : (MAXS == 128 ? 3 : 5))
 batched_kernel(BatchHeader *hdr, const BatchItem *items) {
-    __shared__ __align__(16) char smem[batch_smem_bytes<T, PRED>()];
+    __shared__ __align__(16) char smem[batch_smem_bytes<T, PRED, MAXS>()];
     __shared__ int cur;
     const int count = hdr->count;
     for (;;) {
@@ -114,10 +124,165 @@ batched_kernel(BatchHeader *hdr, const BatchItem *items) {
         if (g >= count) break;
         const BatchItem it = items[g];
         if (PRED && it.p != nullptr)
-            solve_graph<T, PRED>(it, smem);
+            solve_graph<T, PRED, MAXS>(it, smem);
         else
-            solve_graph<T, false>(it, smem);
+            solve_graph<T, false, MAXS>(it, smem);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Stage-batched graphs.  Graphs above a size threshold are not solved by one
+// workgroup each: their stages run as launches shared by every such graph of
+// one tile size -- for each k-block b, one launch of all diagonal tiles, one
+// of all panel tiles and one of all bulk tiles of the graphs that still have
+// a stage b (kernel boundaries order the phases, as in a single solve).  A
+// launch's workgroups are listed in a table of (graph, tile number) pairs,
+// built on the host when the plan is created.
+// ---------------------------------------------------------------------------
+enum StagedKind { kStagedDiag = 0, kStagedPanel = 1, kStagedBulk = 2, kStagedPredInit = 3,
+                  kStagedPredFix = 4 };
+
+struct StagedWork {
+    int32_t item;   // index into the plan's item array
+    int32_t local;  // tile number within the phase (panel_coords / bulk_coords)
+};
+
+template <typename T, int S, int BK, int TM, bool VEC, bool PRED>
+__device__ void staged_product(const BatchItem &it, int kind, int b, int local, char *smem) {
+    T *d = static_cast<T *>(it.d);
+    int32_t *p = PRED ? it.p : nullptr;
+    const int m = (it.n + S - 1) / S - 1;
+    int bi, bj;
+    if (kind == kStagedPanel)
+        panel_coords(local, b, m, bi, bj);
+    else
+        bulk_coords(local, b, m, bi, bj);
+    product_tile<T, S, BK, TM, TM, VEC, PRED>(d, p, it.n, it.ld, it.ldp, bi, bj, b, smem);
+}
+
+// Panels, bulk and predecessor set-up / fix-up of many graphs of tile size S.
+// Kinds 3-4 take one workgroup per graph.  Geometry: TM x TM sub-tiles over
+// (S/TM)^2 threads, with 4 x 4 over 1024 threads for predecessors at tile
+// 128 (as in single solves); the minimum waves per SIMD follow the register
+// footprint of each form.
+#ifndef FW_STAGED64_TM
+#define FW_STAGED64_TM 4
+#endif
+#ifndef FW_STAGED64_BK
+#define FW_STAGED64_BK 16
+#endif
+template <typename T, int S, bool PRED>
+constexpr int staged_tm() {
+    return S == 32 ? 2 : S == 64 ? (PRED ? 4 : FW_STAGED64_TM) : (PRED ? 4 : 8);
+}
+template <typename T, int S, bool PRED>
+constexpr int staged_bk() {
+    return (PRED && S == 128) ? 32 : (!PRED && S == 64) ? FW_STAGED64_BK : 16;
+}
+template <typename T, int S, bool PRED>
+constexpr int staged_threads() {
+    return (S / staged_tm<T, S, PRED>()) * (S / staged_tm<T, S, PRED>());
+}
+template <typename T, int S, bool PRED>
+constexpr int staged_waves() {
+    return PRED ? 2 : S == 32 ? 8 : S == 64 ? (staged_tm<T, S, PRED>() == 8 ? 3 : 5) : 3;
+}
+template <typename T, int S, bool PRED>
+__global__ void __launch_bounds__((staged_threads<T, S, PRED>()), (staged_waves<T, S, PRED>()))
+staged_kernel(const BatchItem *items, const StagedWork *work, int kind, int b) {
+    constexpr int BK = staged_bk<T, S, PRED>();
+    constexpr int NT = staged_threads<T, S, PRED>();
+    __shared__ __align__(16) char smem[product_smem_bytes<T, S, BK, PRED>()];
+    const StagedWork w = work[blockIdx.x];
+    const BatchItem it = items[w.item];
+    if (kind == kStagedPredInit || kind == kStagedPredFix) {
+        if constexpr (PRED) {
+            T *d = static_cast<T *>(it.d);
+            const int n = it.n;
+            for (int64_t c = threadIdx.x; c < (int64_t)n * n; c += NT) {
+                const int i = (int)(c / n), j = (int)(c - (int64_t)i * n);
+                const T v = d[(int64_t)i * it.ld + j];
+                int32_t &q = it.p[(int64_t)i * it.ldp + j];
+                if (kind == kStagedPredInit)
+                    q = (i != j && !Ar<T>::absent(v)) ? i : kPredNone;
+                else if (i == j || q == kPredNone || Ar<T>::unreachable(v))
+                    q = -1;
+            }
+        }
+        return;
+    }
+    constexpr int TM = staged_tm<T, S, PRED>();
+    constexpr bool V = S != 32;  // 2 x 2 sub-tiles at tile 32 are loaded element-wise
+    if (PRED && it.p != nullptr) {
+        if (V && it.vec)
+            staged_product<T, S, BK, TM, V, PRED>(it, kind, b, w.local, smem);
+        else
+            staged_product<T, S, BK, TM, false, PRED>(it, kind, b, w.local, smem);
+    } else {
+        // a graph without predecessors in a plan with some: same geometry
+        if (V && it.vec)
+            staged_product<T, S, BK, TM, V, false>(it, kind, b, w.local, smem);
+        else
+            staged_product<T, S, BK, TM, false, false>(it, kind, b, w.local, smem);
+    }
+}
+
+// Diagonal tiles of stage b of many graphs: (S / TMC)^2 threads, the
+// geometry of the single-graph phase-1 kernel.
+template <int S>
+constexpr int staged_diag_tm() {
+    return S == 32 ? 2 : 4;
+}
+template <typename T, int S, bool PRED>
+__global__ void __launch_bounds__((S / staged_diag_tm<S>()) * (S / staged_diag_tm<S>()))
+staged_diag_kernel(const BatchItem *items, const StagedWork *work, int b) {
+    __shared__ __align__(16) char smem[closure_smem_bytes<T, S, PRED>()];
+    const BatchItem it = items[work[blockIdx.x].item];
+    T *d = static_cast<T *>(it.d);
+    if (PRED && it.p != nullptr)
+        closure_tile<T, S, staged_diag_tm<S>(), PRED>(d, it.p, it.n, it.ld, it.ldp, b * S, smem);
+    else
+        closure_tile<T, S, staged_diag_tm<S>(), false>(d, nullptr, it.n, it.ld, 0, b * S, smem);
+}
+
+template <typename T, bool PRED>
+hipError_t launch_staged_t(int tile, const BatchItem *items, const StagedWork *work, int kind,
+                           int b, unsigned grid, hipStream_t st) {
+    if (kind == kStagedDiag) {
+        switch (tile) {
+        case 32: staged_diag_kernel<T, 32, PRED><<<grid, 256, 0, st>>>(items, work, b); break;
+        case 64: staged_diag_kernel<T, 64, PRED><<<grid, 256, 0, st>>>(items, work, b); break;
+        case 128: staged_diag_kernel<T, 128, PRED><<<grid, 1024, 0, st>>>(items, work, b); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    switch (tile) {
+    case 32:
+        staged_kernel<T, 32, PRED>
+            <<<grid, staged_threads<T, 32, PRED>(), 0, st>>>(items, work, kind, b);
+        break;
+    case 64:
+        staged_kernel<T, 64, PRED>
+            <<<grid, staged_threads<T, 64, PRED>(), 0, st>>>(items, work, kind, b);
+        break;
+    case 128:
+        staged_kernel<T, 128, PRED>
+            <<<grid, staged_threads<T, 128, PRED>(), 0, st>>>(items, work, kind, b);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_staged(int dtype, bool pred, int tile, const BatchItem *items,
+                         const StagedWork *work, int kind, int b, unsigned grid, hipStream_t st) {
+    if (grid == 0) return hipSuccess;
+    if (dtype == FW_F32)
+        return pred ? launch_staged_t<float, true>(tile, items, work, kind, b, grid, st)
+                    : launch_staged_t<float, false>(tile, items, work, kind, b, grid, st);
+    return pred ? launch_staged_t<int32_t, true>(tile, items, work, kind, b, grid, st)
+                : launch_staged_t<int32_t, false>(tile, items, work, kind, b, grid, st);
 }
 
 int status_of(hipError_t e) {
@@ -126,30 +291,36 @@ int status_of(hipError_t e) {
     return FW_ERR_HIP;
 }
 
-const void *kernel_ptr(int dtype, bool pred) {
-    if (dtype == FW_F32)
-        return pred ? (const void *)batched_kernel<float, true>
-                    : (const void *)batched_kernel<float, false>;
-    return pred ? (const void *)batched_kernel<int32_t, true>
-                : (const void *)batched_kernel<int32_t, false>;
+template <typename T>
+const void *kernel_ptr_t(bool pred, bool big) {
+    if (pred)
+        return big ? (const void *)batched_kernel<T, true, 128>
+                   : (const void *)batched_kernel<T, true, 64>;
+    return big ? (const void *)batched_kernel<T, false, 128>
+               : (const void *)batched_kernel<T, false, 64>;
+}
+
+const void *kernel_ptr(int dtype, bool pred, bool big) {
+    return dtype == FW_F32 ? kernel_ptr_t<float>(pred, big) : kernel_ptr_t<int32_t>(pred, big);
 }
 
 // Workgroups per CU of each batched kernel, per device.
 std::mutex g_occ_mu;
 std::map<std::pair<int, int>, int> g_grid;
 
-int resident_grid(int dtype, bool pred) {
+// big: the launch holds 128-wide tiles (the kernel with the 128-wide path).
+int resident_grid(int dtype, bool pred, bool big = true) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return -1;
-    const int key2 = dtype * 2 + (pred ? 1 : 0);
+    const int key2 = dtype * 4 + (pred ? 2 : 0) + (big ? 1 : 0);
     std::lock_guard<std::mutex> lk(g_occ_mu);
     auto it = g_grid.find({dev, key2});
     if (it != g_grid.end()) return it->second;
     int cus = 0, per = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return -1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel_ptr(dtype, pred), kBatchThreads,
-                                                     0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel_ptr(dtype, pred, big),
+                                                     kBatchThreads, 0) != hipSuccess)
         return -1;
     const int grid = cus * std::max(per, 1);
     g_grid[{dev, key2}] = grid;
@@ -158,7 +329,7 @@ int resident_grid(int dtype, bool pred) {
 
 }  // namespace
 
-int batched_resident_grid(int dtype, bool pred) { return resident_grid(dtype, pred); }
+int batched_resident_grid(int dtype, bool pred) { return resident_grid(dtype, pred, true); }
 
 void fill_batch_item(BatchItem &it, void *d, int dtype, int64_t n, int64_t ld, int32_t *p,
                      int64_t ldp) {
@@ -172,24 +343,33 @@ void fill_batch_item(BatchItem &it, void *d, int dtype, int64_t n, int64_t ld, i
     it.pad = 0;
 }
 
-hipError_t launch_batched_raw(int dtype, bool pred, BatchHeader *hdr, const BatchItem *items,
-                              int grid, hipStream_t st) {
-    if (dtype == FW_F32) {
-        if (pred)
-            batched_kernel<float, true><<<grid, kBatchThreads, 0, st>>>(hdr, items);
+template <typename T>
+void launch_batched_t(bool pred, bool big, BatchHeader *hdr, const BatchItem *items, int grid,
+                      hipStream_t st) {
+    if (pred) {
+        if (big)
+            batched_kernel<T, true, 128><<<grid, kBatchThreads, 0, st>>>(hdr, items);
         else
-            batched_kernel<float, false><<<grid, kBatchThreads, 0, st>>>(hdr, items);
+            batched_kernel<T, true, 64><<<grid, kBatchThreads, 0, st>>>(hdr, items);
     } else {
-        if (pred)
-            batched_kernel<int32_t, true><<<grid, kBatchThreads, 0, st>>>(hdr, items);
+        if (big)
+            batched_kernel<T, false, 128><<<grid, kBatchThreads, 0, st>>>(hdr, items);
         else
-            batched_kernel<int32_t, false><<<grid, kBatchThreads, 0, st>>>(hdr, items);
+            batched_kernel<T, false, 64><<<grid, kBatchThreads, 0, st>>>(hdr, items);
     }
+}
+
+hipError_t launch_batched_raw(int dtype, bool pred, BatchHeader *hdr, const BatchItem *items,
+                              int grid, hipStream_t st, bool big) {
+    if (dtype == FW_F32)
+        launch_batched_t<float>(pred, big, hdr, items, grid, st);
+    else
+        launch_batched_t<int32_t>(pred, big, hdr, items, grid, st);
     return hipGetLastError();
 }
 
 // Defined in fw_api.cpp.
-hipError_t timed_launch_batched(double updates, hipStream_t st, int dtype, bool pred,
+hipError_t timed_launch_batched(double updates, hipStream_t st, int dtype, bool pred, bool big,
                                 BatchHeader *hdr, const BatchItem *items, int grid);
 
 }  // namespace fw
@@ -198,16 +378,31 @@ using namespace fw;
 
 // A batch plan: descriptor table in pinned host memory and on the device,
 // plus, once launched through a graph, the captured graph.
+// Graphs with at least this many vertices run stage-batched; smaller ones
+// are solved one per workgroup by the persistent kernel.
+#ifndef FW_STAGED_MIN_N
+#define FW_STAGED_MIN_N 33
+#endif
+
+struct StagedLaunch {
+    int kind, tile, b;
+    int64_t offset, count;  // slice of the work table
+};
+
 struct fw_batch_plan_s {
     int dtype = 0;
     bool pred = false;
     int64_t count = 0;
-    int grid = 0;
+    int64_t n_staged = 0;   // items [0, n_staged) are stage-batched
+    int grid = 0;           // persistent grid for the other items
+    bool big = false;       // some persistent item has a 128-wide tile
     int device = 0;
     double updates = 0;
     size_t bytes = 0;
     void *host = nullptr;   // BatchHeader + items (pinned)
     void *dev = nullptr;    // device copy
+    std::vector<StagedLaunch> staged;
+    StagedWork *work = nullptr;  // device work table (uploaded at creation)
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -234,29 +429,96 @@ int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t coun
         any_pred |= pg != nullptr;
         upd += (double)n[g] * (double)n[g] * (double)n[g];
     }
-    // largest graphs first: the workgroups that take them start earliest
+    // largest graphs first: the stage-batched ones form a prefix, and in the
+    // persistent part the workgroups that take the largest start earliest
     std::stable_sort(items.begin(), items.end(),
                      [](const BatchItem &a, const BatchItem &b) { return a.n > b.n; });
+    int64_t n_staged = 0;
+    while (n_staged < count && items[(size_t)n_staged].n >= FW_STAGED_MIN_N) ++n_staged;
+    // the persistent launch's own updates (phase timing attributes them to it)
+    upd = 0;
+    for (int64_t g = n_staged; g < count; ++g) {
+        const double ng = items[(size_t)g].n;
+        upd += ng * ng * ng;
+    }
     pl->dtype = dtype;
     pl->pred = any_pred;
     pl->count = count;
+    pl->n_staged = n_staged;
     pl->updates = upd;
     pl->bytes = sizeof(BatchHeader) + sizeof(BatchItem) * (size_t)std::max<int64_t>(count, 1);
     if (hipGetDevice(&pl->device) != hipSuccess) return FW_ERR_HIP;
-    const int grid = resident_grid(dtype, any_pred);
+    for (int64_t g = n_staged; g < count; ++g) pl->big |= items[(size_t)g].tile > 64;
+    const int grid = resident_grid(dtype, any_pred, pl->big);
     if (grid <= 0) return FW_ERR_HIP;
-    pl->grid = (int)std::min<int64_t>(grid, std::max<int64_t>(count, 1));
+    pl->grid = (int)std::min<int64_t>(grid, std::max<int64_t>(count - n_staged, 1));
     if (hipHostMalloc(&pl->host, pl->bytes, hipHostMallocDefault) != hipSuccess)
         return FW_ERR_NOMEM;
     if (hipMalloc(&pl->dev, pl->bytes) != hipSuccess) return FW_ERR_NOMEM;
     auto *hdr = static_cast<BatchHeader *>(pl->host);
     *hdr = BatchHeader{};
     hdr->next = 0;
-    hdr->count = (int32_t)count;
+    hdr->count = (int32_t)(count - n_staged);  // the persistent part
     if (count)
         std::copy(items.begin(), items.end(),
                   reinterpret_cast<BatchItem *>(static_cast<char *>(pl->host) + sizeof(BatchHeader)));
-    return FW_OK;
+    if (n_staged == 0) return FW_OK;
+
+    // Stage-batched part: per tile size, the launch sequence and its work
+    // table.  Within a tile group the graphs stay sorted by size, so the
+    // graphs that still have a stage b are a prefix of the group.
+    std::vector<StagedWork> work;
+    std::map<int, std::vector<int32_t>> groups;
+    for (int64_t g = 0; g < n_staged; ++g) groups[items[(size_t)g].tile].push_back((int32_t)g);
+    auto add_launch = [&](int kind, int tile, int b, int64_t first) {
+        if ((int64_t)work.size() > first)
+            pl->staged.push_back({kind, tile, b, first, (int64_t)work.size() - first});
+    };
+    for (auto &kv : groups) {
+        const int tile = kv.first;
+        const std::vector<int32_t> &gs = kv.second;
+        auto blocks = [&](int32_t g) { return (items[(size_t)g].n + tile - 1) / tile; };
+        int64_t first = (int64_t)work.size();
+        for (int32_t g : gs)
+            if (items[(size_t)g].p) work.push_back({g, 0});
+        add_launch(kStagedPredInit, tile, 0, first);
+        const int nb_max = blocks(gs.front());
+        for (int b = 0; b < nb_max; ++b) {
+            first = (int64_t)work.size();
+            for (int32_t g : gs)
+                if (blocks(g) > b) work.push_back({g, 0});
+            add_launch(kStagedDiag, tile, b, first);
+            first = (int64_t)work.size();
+            for (int32_t g : gs) {
+                const int m = blocks(g) - 1;
+                if (blocks(g) > b)
+                    for (int t = 0; t < 2 * m; ++t) work.push_back({g, t});
+            }
+            add_launch(kStagedPanel, tile, b, first);
+            first = (int64_t)work.size();
+            for (int32_t g : gs) {
+                const int m = blocks(g) - 1;
+                if (blocks(g) > b)
+                    for (int t = 0; t < m * m; ++t) work.push_back({g, t});
+            }
+            add_launch(kStagedBulk, tile, b, first);
+        }
+        first = (int64_t)work.size();
+        for (int32_t g : gs)
+            if (items[(size_t)g].p) work.push_back({g, 0});
+        add_launch(kStagedPredFix, tile, 0, first);
+    }
+    for (const StagedLaunch &l : pl->staged)
+        if (l.count > 0x7fffffffLL) return FW_ERR_UNSUPPORTED;
+    // the table never changes: uploaded once, on a private stream
+    const size_t wbytes = sizeof(StagedWork) * work.size();
+    if (hipMalloc(&pl->work, wbytes) != hipSuccess) return FW_ERR_NOMEM;
+    hipStream_t up = nullptr;
+    if (hipStreamCreateWithFlags(&up, hipStreamNonBlocking) != hipSuccess) return FW_ERR_HIP;
+    hipError_t e = hipMemcpyAsync(pl->work, work.data(), wbytes, hipMemcpyHostToDevice, up);
+    if (e == hipSuccess) e = hipStreamSynchronize(up);
+    hipStreamDestroy(up);
+    return status_of(e);
 }
 
 // Enqueue: refresh the device table (which also resets the work counter) and
@@ -269,13 +531,22 @@ int enqueue_plan(fw_batch_plan_s *pl, hipStream_t st, bool capturing) {
     auto *hdr = static_cast<BatchHeader *>(pl->dev);
     auto *items =
         reinterpret_cast<const BatchItem *>(static_cast<char *>(pl->dev) + sizeof(BatchHeader));
+    for (const StagedLaunch &l : pl->staged) {
+        e = launch_staged(pl->dtype, pl->pred, l.tile, items, pl->work + l.offset, l.kind, l.b,
+                          (unsigned)l.count, st);
+        if (e != hipSuccess) return status_of(e);
+    }
+    if (pl->count == pl->n_staged) return FW_OK;
+    const BatchItem *rest = items + pl->n_staged;
     if (capturing)
-        return status_of(launch_batched_raw(pl->dtype, pl->pred, hdr, items, pl->grid, st));
-    return status_of(
-        timed_launch_batched(pl->updates, st, pl->dtype, pl->pred, hdr, items, pl->grid));
+        return status_of(
+            launch_batched_raw(pl->dtype, pl->pred, hdr, rest, pl->grid, st, pl->big));
+    return status_of(timed_launch_batched(pl->updates, st, pl->dtype, pl->pred, pl->big, hdr,
+                                          rest, pl->grid));
 }
 
 void free_plan(fw_batch_plan_s *pl) {
+    if (pl->work) hipFree(pl->work);
     if (pl->exec) hipGraphExecDestroy(pl->exec);
     if (pl->graph) hipGraphDestroy(pl->graph);
     if (pl->cap_stream) hipStreamDestroy(pl->cap_stream);

@@ -64,8 +64,10 @@ struct BatchHeader {
 
 // Persistent batched kernel (fw_batched.hip) and host helpers (fw_api.cpp)
 // shared by the batch plans and the server.
+// big: some item has a 128-wide tile (selects the kernel form that has the
+// 128-wide path; the other one runs more workgroups per CU).
 hipError_t launch_batched_raw(int dtype, bool pred, BatchHeader *hdr, const BatchItem *items,
-                              int grid, hipStream_t st);
+                              int grid, hipStream_t st, bool big = true);
 int batched_resident_grid(int dtype, bool pred);
 void fill_batch_item(BatchItem &it, void *d, int dtype, int64_t n, int64_t ld, int32_t *p,
                      int64_t ldp);

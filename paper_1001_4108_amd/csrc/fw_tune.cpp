@@ -5,8 +5,9 @@
 // run time of Floyd-Warshall does not depend on the graph), so the timings
 // hold for every input of that size.  Two objectives:
 //   0  one single-graph solve of the bucket's representative size;
-//   1  one persistent batched launch of `batch` graphs of that size (the
-//      batched path's plan comes from the same table).
+//   1  one batch-plan launch of `batch` graphs of that size (persistent or
+//      stage-batched, whichever the plan uses for that size; batch plans read
+//      the same table).
 // The representative size is the geometric middle of the bucket.
 #include <hip/hip_runtime.h>
 
@@ -33,15 +34,11 @@ int status_of(hipError_t e) {
 
 struct TuneScratch {
     void *mat = nullptr;     // device matrices
-    void *host_tab = nullptr;
-    void *dev_tab = nullptr;
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     ~TuneScratch() {
         if (st) hipStreamSynchronize(st);
         if (mat) hipFree(mat);
-        if (dev_tab) hipFree(dev_tab);
-        if (host_tab) hipHostFree(host_tab);
         if (e0) hipEventDestroy(e0);
         if (e1) hipEventDestroy(e1);
         if (st) hipStreamDestroy(st);
@@ -79,59 +76,40 @@ extern "C" int fw_autotune(int dtype, const int64_t *lo, const int64_t *hi, int 
         if ((e = hipMalloc(&sc.mat, per * (size_t)count)) != hipSuccess) return status_of(e);
         if ((e = hipMemsetAsync(sc.mat, 0, per * (size_t)count, sc.st)) != hipSuccess)
             return status_of(e);
-        if (objective == 1) {
-            const size_t tb = sizeof(BatchHeader) + sizeof(BatchItem) * (size_t)count;
-            if (sc.host_tab) hipHostFree(sc.host_tab);
-            if (sc.dev_tab) hipFree(sc.dev_tab);
-            sc.host_tab = sc.dev_tab = nullptr;
-            if ((e = hipHostMalloc(&sc.host_tab, tb, hipHostMallocDefault)) != hipSuccess)
-                return status_of(e);
-            if ((e = hipMalloc(&sc.dev_tab, tb)) != hipSuccess) return status_of(e);
-        }
+        std::vector<void *> ptrs((size_t)count);
+        std::vector<int64_t> ns((size_t)count, n), lds((size_t)count, ld);
+        for (int g = 0; g < count; ++g) ptrs[(size_t)g] = static_cast<char *>(sc.mat) + per * (size_t)g;
         double best = 1e300;
         int best_tile = tiles[0];
         for (int t = 0; t < ntiles; ++t) {
             const int tile = tiles[t];
-            std::vector<double> times;
-            for (int r = 0; r <= reps; ++r) {  // the first run is a warm-up
-                const size_t tb = sizeof(BatchHeader) + sizeof(BatchItem) * (size_t)count;
-                if (objective == 1) {
-                    // the previous launch must be done before its table is rewritten
-                    if ((e = hipStreamSynchronize(sc.st)) != hipSuccess) return status_of(e);
-                    auto *hdr = static_cast<BatchHeader *>(sc.host_tab);
-                    auto *items = reinterpret_cast<BatchItem *>(static_cast<char *>(sc.host_tab) +
-                                                                sizeof(BatchHeader));
-                    *hdr = BatchHeader{};
-                    hdr->count = count;
-                    for (int g = 0; g < count; ++g) {
-                        fill_batch_item(items[g], static_cast<char *>(sc.mat) + per * (size_t)g,
-                                        dtype, n, ld, nullptr, 0);
-                        items[g].tile = tile;
-                    }
-                }
-                if ((e = hipEventRecord(sc.e0, sc.st)) != hipSuccess) return status_of(e);
-                if (objective == 0) {
-                    int s = solve_with_tile(sc.mat, dtype, n, ld, tile, sc.st);
-                    if (s != FW_OK) return s;
-                } else {
-                    if ((e = hipMemcpyAsync(sc.dev_tab, sc.host_tab, tb, hipMemcpyHostToDevice,
-                                            sc.st)) != hipSuccess)
-                        return status_of(e);
-                    const int grid = std::min(count, batched_resident_grid(dtype, false));
-                    if (grid <= 0) return FW_ERR_HIP;
-                    e = launch_batched_raw(
-                        dtype, false, static_cast<BatchHeader *>(sc.dev_tab),
-                        reinterpret_cast<const BatchItem *>(static_cast<char *>(sc.dev_tab) +
-                                                            sizeof(BatchHeader)),
-                        grid, sc.st);
-                    if (e != hipSuccess) return status_of(e);
-                }
-                if ((e = hipEventRecord(sc.e1, sc.st)) != hipSuccess) return status_of(e);
-                if ((e = hipEventSynchronize(sc.e1)) != hipSuccess) return status_of(e);
-                float ms = 0.f;
-                if ((e = hipEventElapsedTime(&ms, sc.e0, sc.e1)) != hipSuccess) return status_of(e);
-                if (r) times.push_back(ms);
+            // the candidate tile is installed for the bucket while it is timed
+            // (batch plans read the table when they are built)
+            int s = fw_plan_set(dtype, lo[k], hi[k], tile);
+            if (s != FW_OK) return s;
+            fw_batch_plan plan = nullptr;
+            if (objective == 1) {
+                s = fw_batch_plan_create(ptrs.data(), ns.data(), lds.data(), count, dtype, nullptr,
+                                         nullptr, &plan);
+                if (s != FW_OK) return s;
             }
+            std::vector<double> times;
+            for (int r = 0; r <= reps && s == FW_OK; ++r) {  // the first run is a warm-up
+                if ((e = hipEventRecord(sc.e0, sc.st)) != hipSuccess) s = status_of(e);
+                if (s == FW_OK)
+                    s = objective == 0 ? solve_with_tile(sc.mat, dtype, n, ld, tile, sc.st)
+                                       : fw_batch_plan_launch(plan, 0, sc.st);
+                if (s == FW_OK && (e = hipEventRecord(sc.e1, sc.st)) != hipSuccess)
+                    s = status_of(e);
+                if (s == FW_OK && (e = hipEventSynchronize(sc.e1)) != hipSuccess)
+                    s = status_of(e);
+                float ms = 0.f;
+                if (s == FW_OK && (e = hipEventElapsedTime(&ms, sc.e0, sc.e1)) != hipSuccess)
+                    s = status_of(e);
+                if (s == FW_OK && r) times.push_back(ms);
+            }
+            if (plan) fw_batch_plan_destroy(plan);
+            if (s != FW_OK) return s;
             const double med = median(times);
             if (ms_out) ms_out[(size_t)k * (size_t)ntiles + (size_t)t] = med;
             if (med < best) {
