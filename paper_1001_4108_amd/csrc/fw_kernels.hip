@@ -27,7 +27,29 @@
 //
 // The workgroup-level bodies (closure_tile, product_tile) live in
 // fw_tiles.h.  MFMA is not used: min-plus is not a multiply-add contraction.
+#include <type_traits>
+
 #include "fw_tiles.h"
+
+// Build-time switches (variant builds override them with -D): the direct
+// global->LDS bulk kernel, keyed int32 predecessor tiles, the next diagonal
+// closed inside the bulk launch, strip-split panels, waves per SIMD of the
+// bulk kernel.
+#ifndef FW_BULK_DMA
+#define FW_BULK_DMA 1
+#endif
+#ifndef FW_PRED_KEYS
+#define FW_PRED_KEYS 1
+#endif
+#ifndef FW_FUSE_DIAG
+#define FW_FUSE_DIAG 1
+#endif
+#ifndef FW_PANEL_STRIPS
+#define FW_PANEL_STRIPS 1
+#endif
+#ifndef FW_BULK_DMA_WAVES
+#define FW_BULK_DMA_WAVES 4
+#endif
 
 namespace fw {
 namespace {
@@ -49,11 +71,23 @@ diag_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
 //   mode 4: the 2(nb-1)-1 bulk tiles in the last block row or column (the
 //           part of the bulk that bulk_dma_kernel leaves when the last block
 //           is partial).
+// int32 with predecessors takes the keyed form (product_tile_key).
+template <typename T, int S, int BK, bool PRED, class A>
+constexpr bool keyed_tile() {
+    return PRED && std::is_same<T, int32_t>::value && std::is_same<A, Ar<int32_t>>::value &&
+           FW_PRED_KEYS;
+}
+template <typename T, int S, int BK, bool PRED, class A>
+constexpr int tile_smem_bytes() {
+    return keyed_tile<T, S, BK, PRED, A>() ? product_key_smem_bytes<S, BK>()
+                                           : product_smem_bytes<T, S, BK, PRED>();
+}
+
 template <typename T, int S, int BK, int TM, int TN, bool VEC, bool PRED, class A>
 __global__ void __launch_bounds__((S / TM) * (S / TN))
 tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64_t ldp, int b,
             int nb, int mode) {
-    __shared__ __align__(16) char smem[product_smem_bytes<T, S, BK, PRED>()];
+    __shared__ __align__(16) char smem[tile_smem_bytes<T, S, BK, PRED, A>()];
     int bi, bj;
     switch (mode) {
     case 0: panel_coords(blockIdx.x, b, nb - 1, bi, bj); break;
@@ -62,21 +96,12 @@ tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
     case 3: rest_coords(blockIdx.x, b, nb - 1, bi, bj); break;
     default: edge_coords(blockIdx.x, b, nb - 1, bi, bj); break;
     }
-    product_tile<T, S, BK, TM, TN, VEC, PRED, A>(d, P, n, ld, ldp, bi, bj, b, smem);
+    if constexpr (keyed_tile<T, S, BK, PRED, A>())
+        product_tile_key<S, BK, TM, TN, VEC>(d, P, n, ld, ldp, bi, bj, b, smem);
+    else
+        product_tile<T, S, BK, TM, TN, VEC, PRED, A>(d, P, n, ld, ldp, bi, bj, b, smem);
 }
 
-#ifndef FW_BULK_DMA
-#define FW_BULK_DMA 1
-#endif
-#ifndef FW_FUSE_DIAG
-#define FW_FUSE_DIAG 1
-#endif
-#ifndef FW_PANEL_STRIPS
-#define FW_PANEL_STRIPS 1
-#endif
-#ifndef FW_BULK_DMA_WAVES
-#define FW_BULK_DMA_WAVES 4
-#endif
 
 // Phase 3 for 128-wide tiles without predecessors and with 16-byte aligned
 // rows: the bulk tiles among the first nf full blocks (blockIdx.x enumerates

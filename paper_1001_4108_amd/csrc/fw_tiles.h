@@ -573,6 +573,128 @@ __device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int n, int64_t 
 }
 
 // ---------------------------------------------------------------------------
+// product_tile_key: product_tile with predecessors for int32 matrices, the
+// (distance, last hop) pair of a cell held as one 64-bit key, distance in the
+// high word and last hop (>= 0) in the low word.  Compared as signed 64-bit
+// integers, keys order exactly as lex_update orders pairs (shorter first,
+// then smaller last hop), so one compare and two selects replace it.  The
+// candidate through k is B's key plus the A distance shifted into the high
+// word -- one 64-bit shift-and-add; the low word (B's last hop) is unchanged
+// because the added value's low word is zero, and the high word is the int32
+// sum the unkeyed form computes.  Same candidates, same order rule, hence
+// the same distances and predecessors.  B is staged in LDS as keys.
+// ---------------------------------------------------------------------------
+template <int S, int BK>
+constexpr int product_key_smem_bytes() {
+    return 2 * BK * S * 4 + 2 * BK * S * 8;
+}
+
+__device__ __forceinline__ uint64_t make_key(int32_t d, int32_t p) {
+    return ((uint64_t)(uint32_t)d << 32) | (uint32_t)p;
+}
+
+template <int S, int BK, int TM, int TN, bool VEC>
+__device__ __forceinline__ void product_tile_key(int32_t *__restrict__ d, int32_t *__restrict__ P,
+                                                 int n, int64_t ld, int64_t ldp, int bi, int bj,
+                                                 int b, char *smem) {
+    using T = int32_t;
+    constexpr int NT = (S / TM) * (S / TN);
+    constexpr int GX = S / TN;
+    constexpr int EA = S * BK / NT, TPA = BK / EA;
+    constexpr int EB = BK * S / NT, TPB = S / EB;
+    constexpr int NS = S / BK;
+    static_assert(EA * NT == S * BK && EB * NT == S * BK, "slice split");
+    static_assert(TPA * EA == BK && TPB * EB == S, "slice rows");
+    static_assert(!VEC || (EA % 4 == 0 && EB % 4 == 0 && TN % 4 == 0), "vector split");
+    static_assert(BK % 2 == 0, "k-steps are taken in pairs");
+
+    T(*As)[BK][S] = reinterpret_cast<T(*)[BK][S]>(smem);
+    uint64_t(*Bk)[BK][S] = reinterpret_cast<uint64_t(*)[BK][S]>(smem + 2 * BK * S * sizeof(T));
+
+    const int tid = threadIdx.x;
+    const int tx = tid % GX, ty = tid / GX;
+    const int row0 = bi * S, col0 = bj * S, k0 = b * S;
+    const bool full = (row0 + S <= n) && (col0 + S <= n) && (k0 + S <= n);
+    const int ia = tid / TPA, ka = (tid % TPA) * EA;
+    const int kbr = tid / TPB, jb = (tid % TPB) * EB;
+
+    T ra[EA], rb[EB];
+    int32_t rp[EB];
+    auto fetch = [&](int s) {
+        row_load<T, EA, VEC>(ra, d, row0 + ia, k0 + s * BK + ka, n, ld, full, kI32Inf);
+        row_load<T, EB, VEC>(rb, d, k0 + s * BK + kbr, col0 + jb, n, ld, full, kI32Inf);
+        row_load<int32_t, EB, VEC>(rp, P, k0 + s * BK + kbr, col0 + jb, n, ldp, full, kPredNone);
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < EA; ++e) As[buf][ka + e][ia] = ra[e];
+#pragma unroll
+        for (int e = 0; e < EB; ++e) Bk[buf][kbr][jb + e] = make_key(rb[e], rp[e]);
+    };
+
+    uint64_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        T cd[TN];
+        int32_t cp[TN];
+        row_load<T, TN, VEC>(cd, d, row0 + ty * TM + i, col0 + tx * TN, n, ld, full, kI32Inf);
+        row_load<int32_t, TN, VEC>(cp, P, row0 + ty * TM + i, col0 + tx * TN, n, ldp, full,
+                                   kPredNone);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = make_key(cd[j], cp[j]);
+    }
+    fetch(0);
+    stash(0);
+    __syncthreads();
+
+    for (int s = 0; s < NS; ++s) {
+        const int cur = s & 1;
+        if (s + 1 < NS) fetch(s + 1);
+#pragma unroll 1
+        for (int kk = 0; kk < BK; kk += 2) {
+            T a0[TM], a1[TM];
+            uint64_t b0[TN], b1[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                a0[i] = As[cur][kk][ty * TM + i];
+                a1[i] = As[cur][kk + 1][ty * TM + i];
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                b0[j] = Bk[cur][kk][tx * TN + j];
+                b1[j] = Bk[cur][kk + 1][tx * TN + j];
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const uint64_t c0 = ((uint64_t)(uint32_t)a0[i] << 32) + b0[j];
+                    const uint64_t c1 = ((uint64_t)(uint32_t)a1[i] << 32) + b1[j];
+                    uint64_t v = acc[i][j];
+                    v = (int64_t)c0 < (int64_t)v ? c0 : v;
+                    v = (int64_t)c1 < (int64_t)v ? c1 : v;
+                    acc[i][j] = v;
+                }
+        }
+        if (s + 1 < NS) stash(cur ^ 1);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        T cd[TN];
+        int32_t cp[TN];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            cd[j] = (int32_t)(uint32_t)(acc[i][j] >> 32);
+            cp[j] = (int32_t)(uint32_t)acc[i][j];
+        }
+        row_store<T, TN, VEC>(cd, d, row0 + ty * TM + i, col0 + tx * TN, n, ld, full);
+        row_store<int32_t, TN, VEC>(cp, P, row0 + ty * TM + i, col0 + tx * TN, n, ldp, full);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // strip_tile: the panel update of product_tile on one strip of a panel tile,
 // R rows x CW columns with the full k-block of K, so that a stage's 2(nb-1)
 // panel tiles give four times as many workgroups (one 128 x 128 tile per
