@@ -39,7 +39,7 @@ UPDATE_PEAK = VALU_LANE_OPS_PER_S / MIN_INSTR_PER_UPDATE
 ONE_INSTR_64LANE_PEAK = 256 * 64 * 2.4e9
 
 
-PROFILE = os.path.join(ROOT, "profiles", "tile_kernel_bulk_f32_t128_n16384.md")
+PROFILE = os.path.join(ROOT, "profiles", "bulk_dma_kernel_f32_t128_n16384.md")
 KERNEL_SOURCES = ("paper_1001_4108_amd/csrc/fw_tiles.h", "paper_1001_4108_amd/csrc/fw_kernels.hip")
 
 
@@ -404,7 +404,7 @@ def main():
             per_launch_upd = b["updates_per_step"] / b["launches_per_step"]
             per_launch_s = b["ms_per_step"] / b["launches_per_step"] / 1e3
             ach = per_launch_upd / per_launch_s
-            roof = {"bound": "alu", "kernel": "tile_kernel (bulk, mode 1)",
+            roof = {"bound": "alu", "kernel": "bulk_dma_kernel (bulk tiles + next diagonal closure)",
                     "achieved": ach / 1e12, "peak": UPDATE_PEAK / 1e12, "unit": "Tupd/s",
                     "frac": ach / UPDATE_PEAK, "traffic": measured_traffic(),
                     "traffic_unit": "bytes per bulk launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
