@@ -164,8 +164,10 @@ void fw_plan_reset(void);
  * [lo[k], hi[k]] (2 <= lo <= hi <= 65536) it times every tile of
  * fw_plan_tiles() at the bucket's geometric-middle size n and installs the
  * fastest with fw_plan_set.  objective 0 times one single-graph solve,
- * objective 1 one persistent batched launch of `batch` graphs of size n (the
- * batched path reads the same table).  Each (bucket, tile) is run reps + 1
+ * objective 1 one eager launch of a batch plan of `batch` graphs of size n
+ * (persistent or stage-batched, as batch plans run that size; plans read the
+ * same table).  While a candidate is timed it is installed for its bucket, so
+ * concurrent solves may see it.  Each (bucket, tile) is run reps + 1
  * times, the first as a warm-up, and scored by the median.  Writes the chosen
  * tile of bucket k to tile_out[k] and, if ms_out is non-NULL, the median ms of
  * tile t to ms_out[k * ntiles + t].  Synchronous; allocates and frees its own
@@ -176,11 +178,13 @@ int fw_autotune(int dtype, const int64_t *lo, const int64_t *hi, int nbuckets, i
                 int batch, int reps, int *tile_out, double *ms_out);
 
 /*
- * fw_apsp_batched -- many independent graphs in one call, solved together by
- * one persistent kernel launch: every workgroup takes graphs from a device
- * work counter, largest first, and solves each alone (whole-graph closure
- * when n is at most the plan's tile, else the blocked schedule run inside the
- * workgroup).
+ * fw_apsp_batched -- many independent graphs in one call.  Graphs of 33
+ * vertices and more are stage-batched: for each tile size (from the plan
+ * table), stage b of the blocked schedule (section 3.2) is three launches
+ * shared by all such graphs that have a stage b -- their diagonal tiles,
+ * their panel tiles, their bulk tiles.  Smaller graphs go through one
+ * persistent launch whose workgroups take graphs from a device work counter,
+ * largest first, and solve each alone.
  *   d        HOST array of `count` device pointers, one n[g] x n[g] matrix
  *            each (leading dimension ld[g] >= n[g]); graphs must not alias.
  *   n, ld    HOST arrays of `count` sizes and leading dimensions.
@@ -192,8 +196,10 @@ int fw_autotune(int dtype, const int64_t *lo, const int64_t *hi, int nbuckets, i
  * A graph's result is bit-identical to fw_apsp_pred on the same graph alone.
  * Errors: FW_ERR_INVALID if any graph's arguments are invalid (nothing is
  * enqueued), FW_ERR_UNSUPPORTED if a graph exceeds fw_batched_max_n().
- * The call copies its descriptor table to the device asynchronously on
- * `stream` from library-owned pinned memory and may be called again at once.
+ * The call uploads the stage-batched work table (graph, tile) synchronously
+ * on a private stream, then enqueues the descriptor-table copy (from
+ * library-owned pinned memory) and the launches on `stream`; it may be called
+ * again at once.
  */
 int fw_apsp_batched(void *const *d, const int64_t *n, const int64_t *ld,
                     int64_t count, int dtype, int32_t *const *pred,
@@ -204,14 +210,17 @@ int64_t fw_batched_max_n(int dtype, int with_pred);
 
 /*
  * Reusable batch plans.  fw_batch_plan_create validates the graphs exactly as
- * fw_apsp_batched does and builds the descriptor table once (pinned host
- * memory plus a device copy, both owned by the plan); the matrices must stay
- * allocated for the plan's lifetime and are re-solved in place on every
- * launch.  fw_batch_plan_launch enqueues on `stream`, by `mode`:
- *   0  the table refresh (which also resets the device work counter) and the
- *      persistent kernel, as two stream operations;
- *   1  the same two operations captured once into a hipGraph, replayed by
- *      every later launch (one graph launch per batch);
+ * fw_apsp_batched does and builds the descriptor table (pinned host memory
+ * plus a device copy) and the stage-batched work table (device, uploaded at
+ * creation), all owned by the plan; the matrices must stay allocated for the
+ * plan's lifetime and are re-solved in place on every launch.  The tiles are
+ * read from the plan table at creation.  fw_batch_plan_launch enqueues on
+ * `stream`, by `mode`:
+ *   0  the descriptor refresh (which also resets the device work counter),
+ *      the stage-batched launches and the persistent kernel, as plain stream
+ *      operations;
+ *   1  the same operations captured once into a hipGraph, replayed by every
+ *      later launch (one graph launch per batch);
  *   2  no persistent kernel: every graph through the single-graph stage
  *      loop of fw_apsp_pred (the per-graph launch baseline).
  * All modes give bit-identical results.  Launches of one plan must not
