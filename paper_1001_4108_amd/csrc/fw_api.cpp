@@ -255,7 +255,7 @@ int enqueue_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t 
             closed = false;
             if (nb > 1) {
                 if ((e = panels(b, st)) != hipSuccess) return status_of(e);
-                closed = bulk_closes_next_diag(tile, d, pred, n, ld, b);
+                closed = bulk_closes_next_diag(sr, tile, d, pred, n, ld, b);
                 if ((e = bulk(b, kBulkAll, st, closed)) != hipSuccess) return status_of(e);
             }
         }

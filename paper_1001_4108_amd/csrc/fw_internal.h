@@ -35,10 +35,11 @@ hipError_t launch_panels(int dtype, int sr, int tile, void *d, int32_t *p, int n
                          int64_t ldp, int b, int nb, hipStream_t st);
 // With close_next the launch also closes the next stage's diagonal tile
 // (b+1, b+1), which replaces launch_diag(b + 1); allowed exactly when
-// bulk_closes_next_diag(tile, d, p, n, ld, b) holds (and part is kBulkAll).
+// bulk_closes_next_diag(sr, tile, d, p, n, ld, b) holds (and part is kBulkAll).
 hipError_t launch_bulk(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
                        int64_t ldp, int b, int nb, int part, bool close_next, hipStream_t st);
-bool bulk_closes_next_diag(int tile, const void *d, const int32_t *p, int n, int64_t ld, int b);
+bool bulk_closes_next_diag(int sr, int tile, const void *d, const int32_t *p, int n, int64_t ld,
+                           int b);
 hipError_t launch_pred_init(int dtype, const void *d, int32_t *p, int n, int64_t ld,
                             int64_t ldp, hipStream_t st);
 hipError_t launch_pred_fix(int dtype, const void *d, int32_t *p, int n, int64_t ld,

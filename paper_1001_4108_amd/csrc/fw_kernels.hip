@@ -83,23 +83,45 @@ constexpr int tile_smem_bytes() {
                                            : product_smem_bytes<T, S, BK, PRED>();
 }
 
+// The 128-wide predecessor form (4 x 4 sub-tiles over 1024 threads) can also
+// close the next stage's diagonal tile in mode 1, as bulk_dma_kernel does.
+template <int S, int TM, int TN, bool PRED>
+constexpr bool tile_can_close() {
+    return PRED && S == 128 && TM == 4 && TN == 4;
+}
+
 template <typename T, int S, int BK, int TM, int TN, bool VEC, bool PRED, class A>
 __global__ void __launch_bounds__((S / TM) * (S / TN))
 tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64_t ldp, int b,
-            int nb, int mode) {
+            int nb, int mode, int close_next) {
     __shared__ __align__(16) char smem[tile_smem_bytes<T, S, BK, PRED, A>()];
-    int bi, bj;
+    int idx = blockIdx.x, bi, bj;
+    bool close = false;
+    if constexpr (tile_can_close<S, TM, TN, PRED>()) {
+        // the workgroup of tile (b+1, b+1) takes blockIdx 0 (see bulk_dma_kernel)
+        const int dix = b * (nb - 1) + b;
+        if (close_next && mode == 1) {
+            idx = idx == 0 ? dix : idx == dix ? 0 : idx;
+            close = idx == dix;
+        }
+    }
     switch (mode) {
-    case 0: panel_coords(blockIdx.x, b, nb - 1, bi, bj); break;
-    case 1: bulk_coords(blockIdx.x, b, nb - 1, bi, bj); break;
-    case 2: ahead_coords(blockIdx.x, b, nb - 1, bi, bj); break;
-    case 3: rest_coords(blockIdx.x, b, nb - 1, bi, bj); break;
-    default: edge_coords(blockIdx.x, b, nb - 1, bi, bj); break;
+    case 0: panel_coords(idx, b, nb - 1, bi, bj); break;
+    case 1: bulk_coords(idx, b, nb - 1, bi, bj); break;
+    case 2: ahead_coords(idx, b, nb - 1, bi, bj); break;
+    case 3: rest_coords(idx, b, nb - 1, bi, bj); break;
+    default: edge_coords(idx, b, nb - 1, bi, bj); break;
     }
     if constexpr (keyed_tile<T, S, BK, PRED, A>())
         product_tile_key<S, BK, TM, TN, VEC>(d, P, n, ld, ldp, bi, bj, b, smem);
     else
         product_tile<T, S, BK, TM, TN, VEC, PRED, A>(d, P, n, ld, ldp, bi, bj, b, smem);
+    if constexpr (tile_can_close<S, TM, TN, PRED>()) {
+        if (close) {
+            __syncthreads();  // the tile's stores before its reloads
+            closure_tile<T, S, TM, PRED, A>(d, P, n, ld, ldp, (b + 1) * S, smem);
+        }
+    }
 }
 
 
@@ -216,7 +238,7 @@ hipError_t diag_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, in
 
 template <typename T, bool VEC, bool PRED, class A>
 hipError_t tile_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b, int nb,
-                  int mode, unsigned grid, hipStream_t st) {
+                  int mode, unsigned grid, hipStream_t st, int close_next = 0) {
     switch (tile) {
     case 128:
         if constexpr (PRED) {
@@ -224,19 +246,20 @@ hipError_t tile_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, in
             // sub-tiles over 1024 threads keep it at 4 waves per SIMD
             constexpr int TMP = FW_PRED128_TM, TNP = FW_PRED128_TN;
             tile_kernel<T, 128, FW_PRED128_BK, TMP, TNP, VEC, PRED, A>
-                <<<grid, (128 / TMP) * (128 / TNP), 0, st>>>(d, p, n, ld, ldp, b, nb, mode);
+                <<<grid, (128 / TMP) * (128 / TNP), 0, st>>>(d, p, n, ld, ldp, b, nb, mode,
+                                                             close_next);
         } else {
             tile_kernel<T, 128, 16, 8, 8, VEC, PRED, A><<<grid, 256, 0, st>>>(d, p, n, ld, ldp,
-                                                                             b, nb, mode);
+                                                                             b, nb, mode, 0);
         }
         break;
     case 64:
         tile_kernel<T, 64, 16, 4, 4, VEC, PRED, A><<<grid, 256, 0, st>>>(d, p, n, ld, ldp, b, nb,
-                                                                        mode);
+                                                                        mode, 0);
         break;
     case 32:
         tile_kernel<T, 32, 16, 4, 4, VEC, PRED, A><<<grid, 64, 0, st>>>(d, p, n, ld, ldp, b, nb,
-                                                                       mode);
+                                                                       mode, 0);
         break;
     default: return hipErrorInvalidValue;
     }
@@ -264,14 +287,19 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
     if (grid <= 0) return close_next ? hipErrorInvalidValue : hipSuccess;
     if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
     const bool vec = vec_ok(d, ld) && (p == nullptr || vec_ok(p, ldp));
-    if (close_next && (p || mode != 1 || !bulk_copy_path(tile, vec, n, ld, b)))
+    // closing the next diagonal: the copy path without predecessors, the
+    // 128-wide predecessor kernel with them
+    if (close_next &&
+        (mode != 1 || b + 1 >= nb ||
+         (p ? (!ALLOW_PRED || tile != 128) : !bulk_copy_path(tile, vec, n, ld, b))))
         return hipErrorInvalidValue;
     if constexpr (ALLOW_PRED) {
         if (p) {
+            const int c = close_next ? 1 : 0;
             return vec ? tile_t<T, true, true, A>(tile, d, p, n, ld, ldp, b, nb, mode,
-                                                  (unsigned)grid, st)
+                                                  (unsigned)grid, st, c)
                        : tile_t<T, false, true, A>(tile, d, p, n, ld, ldp, b, nb, mode,
-                                                   (unsigned)grid, st);
+                                                   (unsigned)grid, st, c);
         }
     } else {
         if (p) return hipErrorInvalidValue;
@@ -342,12 +370,13 @@ hipError_t launch_panels(int dtype, int sr, int tile, void *d, int32_t *p, int n
     return tile_any<int32_t>(sr, tile, (int32_t *)d, p, n, ld, ldp, b, nb, 0, false, st);
 }
 
-bool bulk_closes_next_diag(int tile, const void *d, const int32_t *p, int n, int64_t ld,
+bool bulk_closes_next_diag(int sr, int tile, const void *d, const int32_t *p, int n, int64_t ld,
                            int b) {
 #if FW_FUSE_DIAG
-    return p == nullptr && bulk_copy_path(tile, vec_ok(d, ld), n, ld, b) && b + 1 < n / 128;
+    if (p) return sr == kMinPlus && tile == 128 && b + 1 < (n + 127) / 128;
+    return bulk_copy_path(tile, vec_ok(d, ld), n, ld, b) && b + 1 < n / 128;
 #else
-    (void)tile, (void)d, (void)p, (void)n, (void)ld, (void)b;
+    (void)sr, (void)tile, (void)d, (void)p, (void)n, (void)ld, (void)b;
     return false;
 #endif
 }
