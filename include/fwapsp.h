@@ -58,7 +58,7 @@ typedef enum {
     FW_ERR_INVALID = 1,     /* bad argument; nothing was enqueued            */
     FW_ERR_HIP = 2,         /* a HIP call failed                             */
     FW_ERR_NOMEM = 3,       /* device or host allocation failed              */
-    FW_ERR_UNSUPPORTED = 4, /* valid request this build cannot serve         */
+    FW_ERR_UNSUPPORTED = 4, /* valid request the library cannot serve         */
     FW_ERR_BUSY = 5,        /* server: admission refused (budget or queue)   */
     FW_ERR_NOT_FOUND = 6    /* server: unknown request id                    */
 } fw_status;
@@ -335,8 +335,8 @@ int64_t fw_path(const int32_t *pred_host, int64_t n, int64_t ld_pred, int64_t i,
                 int64_t j, int64_t *path, int64_t cap);
 
 /*
- * Library options (process-wide).  In this build both are off and cannot be
- * enabled (fw_set_option returns FW_ERR_UNSUPPORTED for a non-zero value):
+ * Library options (process-wide).  Both are off and cannot be enabled
+ * (fw_set_option returns FW_ERR_UNSUPPORTED for a non-zero value):
  * a run that cycled through them ended in a host-side fault whose cause has
  * not been identified.
  *   FW_OPT_LOOKAHEAD: with at least 3 tile rows, split each

@@ -147,7 +147,7 @@ struct StagedWork {
     int32_t local;  // tile number within the phase (panel_coords / bulk_coords)
 };
 
-template <typename T, int S, int BK, int TM, bool VEC, bool PRED>
+template <typename T, int S, int BK, int TM, int TN, bool VEC, bool PRED>
 __device__ void staged_product(const BatchItem &it, int kind, int b, int local, char *smem) {
     T *d = static_cast<T *>(it.d);
     int32_t *p = PRED ? it.p : nullptr;
@@ -157,7 +157,7 @@ __device__ void staged_product(const BatchItem &it, int kind, int b, int local, 
         panel_coords(local, b, m, bi, bj);
     else
         bulk_coords(local, b, m, bi, bj);
-    product_tile<T, S, BK, TM, TM, VEC, PRED>(d, p, it.n, it.ld, it.ldp, bi, bj, b, smem);
+    product_tile<T, S, BK, TM, TN, VEC, PRED>(d, p, it.n, it.ld, it.ldp, bi, bj, b, smem);
 }
 
 // Panels, bulk and predecessor set-up / fix-up of many graphs of tile size S.
@@ -167,6 +167,9 @@ __device__ void staged_product(const BatchItem &it, int kind, int b, int local, 
 // footprint of each form.
 #ifndef FW_STAGED64_TM
 #define FW_STAGED64_TM 4
+#endif
+#ifndef FW_STAGED64_TN
+#define FW_STAGED64_TN 4
 #endif
 #ifndef FW_STAGED64_BK
 #define FW_STAGED64_BK 16
@@ -180,12 +183,19 @@ constexpr int staged_bk() {
     return (PRED && S == 128) ? 32 : (!PRED && S == 64) ? FW_STAGED64_BK : 16;
 }
 template <typename T, int S, bool PRED>
+constexpr int staged_tn() {
+    return (S == 64 && !PRED) ? FW_STAGED64_TN : staged_tm<T, S, PRED>();
+}
+template <typename T, int S, bool PRED>
 constexpr int staged_threads() {
-    return (S / staged_tm<T, S, PRED>()) * (S / staged_tm<T, S, PRED>());
+    return (S / staged_tm<T, S, PRED>()) * (S / staged_tn<T, S, PRED>());
 }
 template <typename T, int S, bool PRED>
 constexpr int staged_waves() {
-    return PRED ? 2 : S == 32 ? 8 : S == 64 ? (staged_tm<T, S, PRED>() == 8 ? 3 : 5) : 3;
+    return PRED ? 2
+                : S == 32 ? 8
+                : S == 64 ? (staged_tm<T, S, PRED>() * staged_tn<T, S, PRED>() >= 32 ? 4 : 5)
+                          : 3;
 }
 template <typename T, int S, bool PRED>
 __global__ void __launch_bounds__((staged_threads<T, S, PRED>()), (staged_waves<T, S, PRED>()))
@@ -211,19 +221,19 @@ staged_kernel(const BatchItem *items, const StagedWork *work, int kind, int b) {
         }
         return;
     }
-    constexpr int TM = staged_tm<T, S, PRED>();
+    constexpr int TM = staged_tm<T, S, PRED>(), TN = staged_tn<T, S, PRED>();
     constexpr bool V = S != 32;  // 2 x 2 sub-tiles at tile 32 are loaded element-wise
     if (PRED && it.p != nullptr) {
         if (V && it.vec)
-            staged_product<T, S, BK, TM, V, PRED>(it, kind, b, w.local, smem);
+            staged_product<T, S, BK, TM, TN, V, PRED>(it, kind, b, w.local, smem);
         else
-            staged_product<T, S, BK, TM, false, PRED>(it, kind, b, w.local, smem);
+            staged_product<T, S, BK, TM, TN, false, PRED>(it, kind, b, w.local, smem);
     } else {
         // a graph without predecessors in a plan with some: same geometry
         if (V && it.vec)
-            staged_product<T, S, BK, TM, V, false>(it, kind, b, w.local, smem);
+            staged_product<T, S, BK, TM, TN, V, false>(it, kind, b, w.local, smem);
         else
-            staged_product<T, S, BK, TM, false, false>(it, kind, b, w.local, smem);
+            staged_product<T, S, BK, TM, TN, false, false>(it, kind, b, w.local, smem);
     }
 }
 
