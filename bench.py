@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-phase HIP events (plain timed region)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-ladder", action="store_true",
+                    help="skip the ablation-ladder leg (rungs 0-4 at n=4096)")
     ap.add_argument("--no-maxmin", action="store_true",
                     help="skip the n=16384 widest-path (max, min) solve")
     ap.add_argument("--no-negative", action="store_true",
@@ -156,6 +158,65 @@ def bench_maxmin(torch, fw, W, dev, reps=3):
                              oracle.widest_rows(Wm, srcs).astype(np.float32).view(np.uint32)))
     return {"workload": f"widest paths, n={n} fp32 (the same edges, absent -INF)", "ms": ms,
             "updates_per_s": float(n) ** 3 / (ms / 1e3), "check": "ok" if ok else "mismatch"}
+
+
+# The paper's Table 1 at n=4096 (Tesla C1060, seconds): per-task threads,
+# 32-wide blocked with tiles in shared memory, its instruction-optimised
+# version, and the staged-load kernel.  Context for the ratios only.
+PAPER_TABLE1_N4096 = {"per_k": 26.05, "blocked_tiles_in_shared": 4.62,
+                      "optimised_blocked": 2.06, "staged_load": 0.934}
+
+
+def bench_ladder(torch, fw, gen, dev, n=4096, reps=3):
+    """The ablation ladder (fw_apsp_ladder rungs 0-4) on one n=4096 fp32 graph
+    (edge prob 0.3, integer weights [1,1000]); every rung's result is
+    compared bit for bit with the library's default path, which is checked on
+    Dijkstra rows."""
+    import numpy as np
+    import oracle
+    W = gen.dense_graph(n, 0.3, 1, 1000, seed=6)
+    pristine = torch.from_numpy(W).to(dev)
+    work = torch.empty_like(pristine)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    out = {"workload": f"single dense directed graph n={n} fp32, edge prob 0.3, integer "
+                       f"weights [1,1000]", "rungs": {}}
+    ref = None
+    ok = True
+    for rung in (4, 3, 2, 1, 0):
+        times = []
+        for r in range(reps + 1):
+            work.copy_(pristine)
+            torch.cuda.synchronize(dev)
+            ev0.record()
+            fw.fw_apsp_ladder(work, rung)
+            ev1.record()
+            torch.cuda.synchronize(dev)
+            if r:
+                times.append(ev0.elapsed_time(ev1))
+        got = work.cpu().numpy()
+        if ref is None:
+            ref = got
+            srcs = np.array([0, n // 3, n - 1])
+            ok &= bool(np.array_equal(got[srcs], oracle.dijkstra_rows(W, srcs).astype(np.float32)))
+        else:
+            ok &= bool(np.array_equal(got.view(np.uint32), ref.view(np.uint32)))
+        ms = float(np.median(times))
+        out["rungs"][str(rung)] = {"what": fw.LADDER_RUNGS[rung], "ms": ms,
+                                   "updates_per_s": float(n) ** 3 / (ms / 1e3)}
+    r = {k: v["ms"] for k, v in out["rungs"].items()}
+    out["ratios"] = {"per_k/blocked_lds": r["0"] / r["1"],
+                     "blocked_lds/registers_whole_tiles": r["1"] / r["2"],
+                     "registers_whole_tiles/staged_slices": r["2"] / r["3"],
+                     "staged_slices/default": r["3"] / r["4"],
+                     "blocked_lds/default": r["1"] / r["4"]}
+    p = PAPER_TABLE1_N4096
+    out["paper_ratios_n4096"] = {
+        "per_task/blocked_in_shared": p["per_k"] / p["blocked_tiles_in_shared"],
+        "blocked_in_shared/optimised": p["blocked_tiles_in_shared"] / p["optimised_blocked"],
+        "optimised/staged_load": p["optimised_blocked"] / p["staged_load"]}
+    out["check"] = "ok" if ok else "mismatch"
+    return out
 
 
 def bench_negative(torch, fw, gen, dev, reps=3):
@@ -419,6 +480,12 @@ def main():
         log("widest paths (max, min) n=16384")
         maxmin = bench_maxmin(torch, fw, W, dev)
 
+    ladder = None
+    if not args.no_ladder:
+        log("ablation ladder n=4096 (rungs 4..0)")
+        ladder = bench_ladder(torch, fw, gen, dev)
+        log("ladder ms: " + ", ".join(f"{k}: {v['ms']:.1f}" for k, v in ladder["rungs"].items()))
+
     negative = None
     if not args.no_negative:
         log("negative-weight int32 n=8192 with predecessors")
@@ -456,7 +523,7 @@ def main():
                    "n": n, "tile": tile, "global_batch": 1, "parallelism": "single-gpu"},
         "frac_of_update_peak": value / UPDATE_PEAK,
         "check": "ok" if ok else "mismatch",
-        "phases": phases, "roofline": roof, "cpu_baseline": cpu, "negative_int32_pred": negative, "maxmin": maxmin,
+        "phases": phases, "roofline": roof, "cpu_baseline": cpu, "negative_int32_pred": negative, "maxmin": maxmin, "ladder": ladder,
         "batched": batched,
         "serving": serving,
         "paper_context": {"tesla_c1060_s_n16384": 53.06,

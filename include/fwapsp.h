@@ -160,6 +160,24 @@ int fw_plan_set(int dtype, int64_t n_lo, int64_t n_hi, int tile);
 void fw_plan_reset(void);
 
 /*
+ * fw_apsp_ladder -- the same solve by one rung of an ablation ladder that
+ * mirrors the columns of the paper's Table 1 with gfx950 kernels (for
+ * measuring what each design step buys; every rung gives the same bits):
+ *   0  one launch per k, one thread per cell (section 3.1's direct form);
+ *   1  blocked (section 3.2), 32 x 32 tiles held in LDS, one cell per thread,
+ *      k-ordered diagonal and panel phases;
+ *   2  blocked, 64 x 64 tiles, 4 x 4 register sub-tiles, two k-steps fused,
+ *      the whole operand tiles in LDS (64 KB per workgroup);
+ *   3  as 2 with the operands staged in 16-deep LDS slices (the tile-64 path
+ *      of fw_apsp_plan);
+ *   4  the default path of fw_apsp / fw_apsp_i32.
+ * d, dtype, n, ld, stream as fw_apsp_pred without predecessors.  Errors:
+ * FW_ERR_INVALID for a bad rung or the argument errors of fw_apsp,
+ * FW_ERR_UNSUPPORTED for n > 65536.
+ */
+int fw_apsp_ladder(void *d, int dtype, int64_t n, int64_t ld, int rung, void *stream);
+
+/*
  * fw_autotune -- the plan table's autotuner.  For each size bucket
  * [lo[k], hi[k]] (2 <= lo <= hi <= 65536) it times every tile of
  * fw_plan_tiles() at the bucket's geometric-middle size n and installs the

@@ -83,6 +83,7 @@ def _declare(L):
         "fw_apsp_plan": ([vp, ci, i64, i64, vp, i64, ci, vp], ci),
         "fw_plan_tiles": ([ctypes.POINTER(ci), ci], ci),
         "fw_apsp_semiring": ([vp, ci, ci, i64, i64, vp], ci),
+        "fw_apsp_ladder": ([vp, ci, i64, i64, ci, vp], ci),
         "fw_plan_tile": ([ci, i64], ci),
         "fw_plan_set": ([ci, i64, i64, ci], ci),
         "fw_plan_reset": ([], None),
@@ -216,6 +217,26 @@ def fw_apsp_semiring(d: torch.Tensor, semiring: str = "maxmin", stream=None) -> 
     with torch.cuda.device(d.device):
         _check(lib().fw_apsp_semiring(p, code, SEMIRINGS[semiring], n, ld, _stream(d, stream)),
                "fw_apsp_semiring")
+    return d
+
+
+LADDER_RUNGS = {
+    0: "one launch per k, one thread per cell",
+    1: "blocked, 32x32 tiles in LDS, one cell per thread",
+    2: "blocked, 64x64 tiles, 4x4 register sub-tiles, whole tiles in LDS",
+    3: "blocked, 64x64 tiles, 4x4 register sub-tiles, staged 16-deep LDS slices",
+    4: "library default (tile 128, direct global->LDS copies)",
+}
+
+
+def fw_apsp_ladder(d: torch.Tensor, rung: int, stream=None) -> torch.Tensor:
+    """In-place shortest paths by one rung of the ablation ladder (see
+    ``LADDER_RUNGS``); every rung gives the same bits as ``fw_apsp``."""
+    code = _dtype_code(d)
+    p, n, ld = _matrix(d, "d")
+    with torch.cuda.device(d.device):
+        _check(lib().fw_apsp_ladder(p, code, n, ld, int(rung), _stream(d, stream)),
+               "fw_apsp_ladder")
     return d
 
 

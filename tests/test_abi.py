@@ -51,6 +51,9 @@ def test_argument_validation_without_gpu():
     assert L.fw_apsp_plan(ctypes.c_void_p(16), 0, 64, 64, null, 0, 48, null) == 1  # tile
     assert L.fw_negative_cycle(ctypes.c_void_p(16), 0, 4, 4, null, null) == 1
     assert L.fw_apsp_batched(None, None, None, 0, 0, None, None, null) == 0
+    assert L.fw_apsp_ladder(ctypes.c_void_p(16), 0, 8, 8, 7, null) == 1   # rung
+    assert L.fw_apsp_ladder(ctypes.c_void_p(16), 0, 8, 4, 0, null) == 1   # ld < n
+    assert L.fw_apsp_ladder(null, 0, 0, 0, 2, null) == 0                  # empty graph
 
 
 def test_plan_table():
