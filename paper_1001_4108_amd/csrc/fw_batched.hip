@@ -246,7 +246,11 @@ constexpr int staged_diag_tm() {
 template <typename T, int S, bool PRED>
 __global__ void __launch_bounds__((S / staged_diag_tm<S>()) * (S / staged_diag_tm<S>()))
 staged_diag_kernel(const BatchItem *items, const StagedWork *work, int b) {
-    __shared__ __align__(16) char smem[closure_smem_bytes<T, S, PRED>()];
+    // a plan with predecessors may hold graphs without: room for both forms
+    constexpr int kSmem = closure_smem_bytes<T, S, PRED>() > closure_smem_bytes<T, S, false>()
+                              ? closure_smem_bytes<T, S, PRED>()
+                              : closure_smem_bytes<T, S, false>();
+    __shared__ __align__(16) char smem[kSmem];
     const BatchItem it = items[work[blockIdx.x].item];
     T *d = static_cast<T *>(it.d);
     if (PRED && it.p != nullptr)
