@@ -1,0 +1,75 @@
+"""Seeded randomized parity sweep: sizes, densities (empty to complete),
+dtypes, negative weights, tiles, leading-dimension padding and misalignment,
+predecessors and the (max, min) semiring, each case bit-exact against the
+oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1001_4108_amd as fw
+from paper_1001_4108_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+CASES = 400
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint32)
+
+
+def draw(rng):
+    n = int(rng.choice([int(rng.integers(1, 70)), int(rng.integers(70, 300)),
+                        int(rng.integers(300, 700))]))
+    p = float(rng.choice([0.0, 0.03, 0.2, 0.6, 1.0]))
+    dtype = str(rng.choice(["f32", "i32"]))
+    negative = dtype == "i32" and bool(rng.integers(0, 2))
+    tile = [None, 32, 64, 128][int(rng.integers(0, 4))]
+    ld_extra = int(rng.choice([0, 0, 1, 4, 7]))
+    pred = bool(rng.integers(0, 3) == 0)
+    maxmin = (not pred) and bool(rng.integers(0, 6) == 0)
+    return n, p, dtype, negative, tile, ld_extra, pred, maxmin
+
+
+def test_randomized_cases():
+    rng = np.random.default_rng(20260101)
+    failures = []
+    for case in range(CASES):
+        n, p, dtype, negative, tile, ld_extra, pred, maxmin = draw(rng)
+        seed = 1000 + case
+        if dtype == "f32":
+            W = gen.dense_graph(n, p, 1, 500, seed)
+        elif negative:
+            W = gen.reweighted_graph(n, p, 1, 500, -200, 200, seed).w
+        else:
+            W = gen.dense_graph(n, p, 1, 500, seed, dtype=np.int32)
+        if maxmin:
+            absent = np.float32(-np.inf) if dtype == "f32" else np.int32(np.iinfo(np.int32).min)
+            present = np.isfinite(W) if dtype == "f32" else W != gen.I32_INF
+            W = np.where(present, W, absent).astype(W.dtype)
+            ref = oracle.fw_maxmin(W)
+        else:
+            ref = oracle.fw(W)
+        fill = W.dtype.type(-3)
+        buf = np.full((n, n + ld_extra), fill, W.dtype)
+        buf[:, :n] = W
+        d = torch.from_numpy(buf).cuda()
+        view = d[:, :n]
+        P = None
+        if pred:
+            P = torch.full((n, n + 3), -9, dtype=torch.int32, device="cuda")[:, :n]
+        if maxmin:
+            fw.fw_apsp_semiring(view, "maxmin")
+        elif tile is None:
+            fw.fw_apsp_pred(view, P)
+        else:
+            fw.fw_apsp_plan(view, tile, P)
+        torch.cuda.synchronize()
+        out = d.cpu().numpy()
+        ok = np.array_equal(bits(out[:, :n]), bits(ref)) and bool((out[:, n:] == fill).all())
+        if ok and pred:
+            ok = np.array_equal(P.cpu().numpy(), oracle.canonical_pred(ref, W))
+        if not ok:
+            failures.append((case, n, p, dtype, negative, tile, ld_extra, pred, maxmin))
+    assert not failures, failures[:5]
