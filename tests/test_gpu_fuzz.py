@@ -73,3 +73,50 @@ def test_randomized_cases():
         if not ok:
             failures.append((case, n, p, dtype, negative, tile, ld_extra, pred, maxmin))
     assert not failures, failures[:5]
+
+
+def test_randomized_batches():
+    """Random batch compositions through batch plans (persistent and
+    stage-batched parts, random tile per size bucket, predecessors on random
+    graphs, padded rows), every graph bit-exact against the oracle."""
+    rng = np.random.default_rng(777)
+    try:
+        for rep in range(6):
+            dtype = [np.float32, np.int32][rep % 2]
+            code = "f32" if dtype == np.float32 else "i32"
+            fw.plan_reset()
+            for lo, hi in ((2, 32), (33, 64), (65, 128), (129, 256), (257, 700)):
+                fw.plan_set(code, lo, hi, int(rng.choice([32, 64, 128])))
+            count = int(rng.integers(20, 120))
+            graphs, bufs, views, preds = [], [], [], []
+            for g in range(count):
+                n = int(rng.choice([int(rng.integers(1, 40)), int(rng.integers(40, 260)),
+                                    int(rng.integers(260, 700))]))
+                if dtype == np.float32:
+                    W = gen.dense_graph(n, float(rng.choice([0.05, 0.3, 0.9])), 1, 300, (rep, g))
+                else:
+                    W = gen.reweighted_graph(n, float(rng.choice([0.05, 0.3, 0.9])), 1, 300,
+                                             -100, 100, (rep, g)).w
+                ld = n + int(rng.choice([0, 3, 4]))
+                host = np.full((n, ld), dtype(-5), dtype)
+                host[:, :n] = W
+                t = torch.from_numpy(host).cuda()
+                graphs.append(W)
+                bufs.append(t)
+                views.append(t[:, :n])
+                preds.append(torch.full((n, n), -9, dtype=torch.int32, device="cuda")
+                             if rng.integers(0, 3) == 0 else None)
+            plan = fw.BatchPlan(views, preds)
+            plan.launch("graph" if rep % 3 else "kernel")
+            torch.cuda.synchronize()
+            for g, (W, t, P) in enumerate(zip(graphs, bufs, preds)):
+                n = W.shape[0]
+                out = t.cpu().numpy()
+                ref = oracle.fw(W)
+                assert np.array_equal(bits(out[:, :n]), bits(ref)), (rep, g, n)
+                assert (out[:, n:] == dtype(-5)).all(), (rep, g, n)
+                if P is not None:
+                    assert np.array_equal(P.cpu().numpy(), oracle.canonical_pred(ref, W)), (rep, g)
+            plan.destroy()
+    finally:
+        fw.plan_reset()
