@@ -83,11 +83,12 @@ constexpr int tile_smem_bytes() {
                                            : product_smem_bytes<T, S, BK, PRED>();
 }
 
-// The 128-wide predecessor form (4 x 4 sub-tiles over 1024 threads) can also
-// close the next stage's diagonal tile in mode 1, as bulk_dma_kernel does.
+// Forms whose geometry is the closure's (4 x 4 cells per thread: tile 64 over
+// 256 threads, the 128-wide predecessor form over 1024) can also close the
+// next stage's diagonal tile in mode 1, as bulk_dma_kernel does.
 template <int S, int TM, int TN, bool PRED>
 constexpr bool tile_can_close() {
-    return PRED && S == 128 && TM == 4 && TN == 4;
+    return TM == 4 && TN == 4 && (S == 64 || (PRED && S == 128));
 }
 
 template <typename T, int S, int BK, int TM, int TN, bool VEC, bool PRED, class A>
@@ -255,7 +256,7 @@ hipError_t tile_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, in
         break;
     case 64:
         tile_kernel<T, 64, 16, 4, 4, VEC, PRED, A><<<grid, 256, 0, st>>>(d, p, n, ld, ldp, b, nb,
-                                                                        mode, 0);
+                                                                        mode, close_next);
         break;
     case 32:
         tile_kernel<T, 32, 16, 4, 4, VEC, PRED, A><<<grid, 64, 0, st>>>(d, p, n, ld, ldp, b, nb,
@@ -287,15 +288,16 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
     if (grid <= 0) return close_next ? hipErrorInvalidValue : hipSuccess;
     if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
     const bool vec = vec_ok(d, ld) && (p == nullptr || vec_ok(p, ldp));
-    // closing the next diagonal: the copy path without predecessors, the
-    // 128-wide predecessor kernel with them
+    // closing the next diagonal: tile 64 in any form, the copy path at 128
+    // without predecessors, the 128-wide predecessor kernel with them
     if (close_next &&
         (mode != 1 || b + 1 >= nb ||
-         (p ? (!ALLOW_PRED || tile != 128) : !bulk_copy_path(tile, vec, n, ld, b))))
+         (tile != 64 &&
+          (p ? (!ALLOW_PRED || tile != 128) : !bulk_copy_path(tile, vec, n, ld, b)))))
         return hipErrorInvalidValue;
+    const int c = close_next ? 1 : 0;
     if constexpr (ALLOW_PRED) {
         if (p) {
-            const int c = close_next ? 1 : 0;
             return vec ? tile_t<T, true, true, A>(tile, d, p, n, ld, ldp, b, nb, mode,
                                                   (unsigned)grid, st, c)
                        : tile_t<T, false, true, A>(tile, d, p, n, ld, ldp, b, nb, mode,
@@ -304,6 +306,11 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
     } else {
         if (p) return hipErrorInvalidValue;
     }
+    if (tile == 64)
+        return vec ? tile_t<T, true, false, A>(tile, d, p, n, ld, ldp, b, nb, mode,
+                                               (unsigned)grid, st, c)
+                   : tile_t<T, false, false, A>(tile, d, p, n, ld, ldp, b, nb, mode,
+                                                (unsigned)grid, st, c);
 #if FW_PANEL_STRIPS
     if (mode == 0 && tile == 128) {
         if (4 * grid > 0x7fffffffLL) return hipErrorInvalidValue;
@@ -373,6 +380,7 @@ hipError_t launch_panels(int dtype, int sr, int tile, void *d, int32_t *p, int n
 bool bulk_closes_next_diag(int sr, int tile, const void *d, const int32_t *p, int n, int64_t ld,
                            int b) {
 #if FW_FUSE_DIAG
+    if (tile == 64) return (!p || sr == kMinPlus) && b + 1 < (n + 63) / 64;
     if (p) return sr == kMinPlus && tile == 128 && b + 1 < (n + 127) / 128;
     return bulk_copy_path(tile, vec_ok(d, ld), n, ld, b) && b + 1 < n / 128;
 #else
