@@ -1,10 +1,12 @@
 // Batched solves: many independent graphs in one batch plan.
 //
 // Graphs of FW_STAGED_MIN_N vertices and more are stage-batched: per tile
-// size, each stage b of the blocked schedule (section 3.2) is three launches
+// size, each stage b of the blocked schedule (section 3.2) is a few launches
 // shared by every graph that has a stage b -- all their diagonal tiles, all
 // their panel tiles, all their bulk tiles -- so a large graph is spread over
-// the whole GPU instead of one workgroup.  The smaller graphs go through one
+// the whole GPU instead of one workgroup.  Where the bulk kernel has the
+// closure's geometry, the workgroup of bulk tile (b+1, b+1) also closes it,
+// and stages after the first need no diagonal launch.  The smaller graphs go through one
 // persistent launch in which each workgroup repeatedly takes the next graph
 // from a device work counter (largest first) and solves it alone:
 //   * n <= tile: closure_tile over the whole graph -- the plain algorithm of
@@ -135,7 +137,9 @@ batched_kernel(BatchHeader *hdr, const BatchItem *items) {
 // workgroup each: their stages run as launches shared by every such graph of
 // one tile size -- for each k-block b, one launch of all diagonal tiles, one
 // of all panel tiles and one of all bulk tiles of the graphs that still have
-// a stage b (kernel boundaries order the phases, as in a single solve).  A
+// a stage b (kernel boundaries order the phases, as in a single solve); the
+// diagonal launch of stage b > 0 is folded into stage b-1's bulk launch where
+// the kernels allow it (staged_can_close).  A
 // launch's workgroups are listed in a table of (graph, tile number) pairs,
 // built on the host when the plan is created.
 // ---------------------------------------------------------------------------
@@ -144,8 +148,16 @@ enum StagedKind { kStagedDiag = 0, kStagedPanel = 1, kStagedBulk = 2, kStagedPre
 
 struct StagedWork {
     int32_t item;   // index into the plan's item array
-    int32_t local;  // tile number within the phase (panel_coords / bulk_coords)
+    int32_t local;  // tile number within the phase (panel_coords / bulk_coords),
+                    // | kStagedClose: after the bulk tile (b+1, b+1), close it
 };
+// Set on the bulk entry of tile (b+1, b+1) when the tile size's kernel has
+// the closure's geometry: that workgroup then closes the next stage's
+// diagonal tile and the graph needs no diagonal launch for stage b+1.
+constexpr int32_t kStagedClose = 0x40000000;
+
+template <typename T, int S, bool PRED>
+constexpr bool staged_can_close();
 
 template <typename T, int S, int BK, int TM, int TN, bool VEC, bool PRED>
 __device__ void staged_product(const BatchItem &it, int kind, int b, int local, char *smem) {
@@ -192,7 +204,7 @@ constexpr int staged_threads() {
 }
 template <typename T, int S, bool PRED>
 constexpr int staged_waves() {
-    return PRED ? 2
+    return PRED ? (S == 64 ? 3 : 2)
                 : S == 32 ? 8
                 : S == 64 ? (staged_tm<T, S, PRED>() * staged_tn<T, S, PRED>() >= 32 ? 4 : 5)
                           : 3;
@@ -223,18 +235,40 @@ staged_kernel(const BatchItem *items, const StagedWork *work, int kind, int b) {
     }
     constexpr int TM = staged_tm<T, S, PRED>(), TN = staged_tn<T, S, PRED>();
     constexpr bool V = S != 32;  // 2 x 2 sub-tiles at tile 32 are loaded element-wise
-    if (PRED && it.p != nullptr) {
+    const int local = w.local & ~kStagedClose;
+    const bool with_pred = PRED && it.p != nullptr;
+    if (with_pred) {
         if (V && it.vec)
-            staged_product<T, S, BK, TM, TN, V, PRED>(it, kind, b, w.local, smem);
+            staged_product<T, S, BK, TM, TN, V, PRED>(it, kind, b, local, smem);
         else
-            staged_product<T, S, BK, TM, TN, false, PRED>(it, kind, b, w.local, smem);
+            staged_product<T, S, BK, TM, TN, false, PRED>(it, kind, b, local, smem);
     } else {
         // a graph without predecessors in a plan with some: same geometry
         if (V && it.vec)
-            staged_product<T, S, BK, TM, TN, V, false>(it, kind, b, w.local, smem);
+            staged_product<T, S, BK, TM, TN, V, false>(it, kind, b, local, smem);
         else
-            staged_product<T, S, BK, TM, TN, false, false>(it, kind, b, w.local, smem);
+            staged_product<T, S, BK, TM, TN, false, false>(it, kind, b, local, smem);
     }
+    if constexpr (staged_can_close<T, S, PRED>()) {
+        static_assert(product_smem_bytes<T, S, BK, PRED>() >= closure_smem_bytes<T, S, PRED>() &&
+                          product_smem_bytes<T, S, BK, PRED>() >= closure_smem_bytes<T, S, false>(),
+                      "closure scratch must fit the product's LDS");
+        if (w.local & kStagedClose) {
+            __syncthreads();  // the tile's stores before its reloads
+            T *d = static_cast<T *>(it.d);
+            if (with_pred)
+                closure_tile<T, S, TM, PRED>(d, it.p, it.n, it.ld, it.ldp, (b + 1) * S, smem);
+            else
+                closure_tile<T, S, TM, false>(d, nullptr, it.n, it.ld, 0, (b + 1) * S, smem);
+        }
+    }
+}
+
+// Tile sizes whose panel/bulk kernel has the closure's geometry (TM x TM
+// cells over (S/TM)^2 threads): 32 and 64, and 128 with predecessors.
+template <typename T, int S, bool PRED>
+constexpr bool staged_can_close() {
+    return staged_tm<T, S, PRED>() == staged_tn<T, S, PRED>() && (S <= 64 || PRED);
 }
 
 // Diagonal tiles of stage b of many graphs: (S / TMC)^2 threads, the
@@ -497,10 +531,12 @@ int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t coun
             if (items[(size_t)g].p) work.push_back({g, 0});
         add_launch(kStagedPredInit, tile, 0, first);
         const int nb_max = blocks(gs.front());
+        // the bulk launch of stage b closes each graph's tile (b+1, b+1)
+        const bool fuse = tile <= 64 || (tile == 128 && any_pred);
         for (int b = 0; b < nb_max; ++b) {
             first = (int64_t)work.size();
             for (int32_t g : gs)
-                if (blocks(g) > b) work.push_back({g, 0});
+                if (blocks(g) > b && !(fuse && b > 0)) work.push_back({g, 0});
             add_launch(kStagedDiag, tile, b, first);
             first = (int64_t)work.size();
             for (int32_t g : gs) {
@@ -510,10 +546,18 @@ int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t coun
             }
             add_launch(kStagedPanel, tile, b, first);
             first = (int64_t)work.size();
+            if (fuse)  // the closing workgroups first: they run longest
+                for (int32_t g : gs)
+                    if (blocks(g) > b + 1) {
+                        const int m = blocks(g) - 1;
+                        work.push_back({g, (b * m + b) | kStagedClose});
+                    }
             for (int32_t g : gs) {
                 const int m = blocks(g) - 1;
                 if (blocks(g) > b)
-                    for (int t = 0; t < m * m; ++t) work.push_back({g, t});
+                    for (int t = 0; t < m * m; ++t)
+                        if (!(fuse && blocks(g) > b + 1 && t == b * m + b))
+                            work.push_back({g, t});
             }
             add_launch(kStagedBulk, tile, b, first);
         }
