@@ -458,6 +458,42 @@ struct fw_batch_plan_s {
 
 namespace {
 
+// The workgroups of a launch go to the GPU's XCDs in turn (workgroup w to
+// XCD w mod 8) and every XCD has its own L2.  A launch's entries are
+// reordered so that all tiles of one graph sit at indices congruent modulo
+// the XCD count: the graph's panel tiles, which each of its bulk tiles reads,
+// are then fetched into one L2 instead of all eight.  Graphs go to the group
+// with the fewest entries so far, largest first; each group keeps the
+// launch's order (closing entries first), and the groups are interleaved
+// until the shortest runs out, the rest then following in turn.
+#ifndef FW_STAGED_XCD_GROUPS
+#define FW_STAGED_XCD_GROUPS 8
+#endif
+void xcd_group(std::vector<StagedWork> &work, int64_t first, int groups) {
+    const int64_t end = (int64_t)work.size();
+    std::map<int32_t, int64_t> count;  // graph -> entries in this launch
+    std::vector<int32_t> graphs;       // in order of first appearance
+    for (int64_t e = first; e < end; ++e)
+        if (count[work[(size_t)e].item]++ == 0) graphs.push_back(work[(size_t)e].item);
+    std::stable_sort(graphs.begin(), graphs.end(),
+                     [&](int32_t a, int32_t b) { return count[a] > count[b]; });
+    std::vector<int64_t> load((size_t)groups, 0);
+    std::map<int32_t, int> group_of;
+    for (int32_t g : graphs) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        group_of[g] = x;
+        load[(size_t)x] += count[g];
+    }
+    std::vector<std::vector<StagedWork>> lists((size_t)groups);
+    for (int64_t e = first; e < end; ++e)
+        lists[(size_t)group_of[work[(size_t)e].item]].push_back(work[(size_t)e]);
+    std::vector<size_t> pos((size_t)groups, 0);
+    int64_t out = first;
+    while (out < end)
+        for (size_t x = 0; x < lists.size(); ++x)
+            if (pos[x] < lists[x].size()) work[(size_t)out++] = lists[x][pos[x]++];
+}
+
 int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t count, int dtype,
                int32_t *const *pred, const int64_t *ld_pred, fw_batch_plan_s *pl) {
     if (count < 0 || count > 0x7fffffffLL) return FW_ERR_INVALID;
@@ -519,8 +555,10 @@ int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t coun
     std::map<int, std::vector<int32_t>> groups;
     for (int64_t g = 0; g < n_staged; ++g) groups[items[(size_t)g].tile].push_back((int32_t)g);
     auto add_launch = [&](int kind, int tile, int b, int64_t first) {
-        if ((int64_t)work.size() > first)
+        if ((int64_t)work.size() > first) {
+            if (FW_STAGED_XCD_GROUPS > 1) xcd_group(work, first, FW_STAGED_XCD_GROUPS);
             pl->staged.push_back({kind, tile, b, first, (int64_t)work.size() - first});
+        }
     };
     for (auto &kv : groups) {
         const int tile = kv.first;
