@@ -231,7 +231,8 @@ def bench_negative(torch, fw, gen, dev, reps=3):
     P = torch.empty((n, n), dtype=torch.int32, device=dev)
     out = {"workload": "single graph n=8192 int32, edge prob 0.2, base weights [1,1000] "
                        "reweighted by potentials in [-500,500], INT32_MAX/2 absent",
-           "n": n, "tile": fw.plan_tile(torch.int32, n)}
+           "n": n, "tile": {"with_pred": fw.plan_tile(torch.int32, n, pred=True),
+                            "distances_only": fw.plan_tile(torch.int32, n)}}
     for mode, pp in (("with_pred", P), ("distances_only", None)):
         work.copy_(pristine)
         fw.fw_apsp_pred(work, pp)

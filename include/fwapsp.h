@@ -144,17 +144,27 @@ int fw_apsp_semiring(void *d, int dtype, int semiring, int64_t n, int64_t ld, vo
 int fw_plan_tiles(int *tiles, int cap);
 
 /*
- * Tile size the library picks for (dtype, n), from its tuned plan table.
- * Returns the tile, or 0 for n <= 1, or -1 for a bad dtype / n < 0.
+ * Plan keys.  The plan table has one part per key: a fw_dtype, or'd with
+ * FW_PLAN_PRED for the solves that also compute predecessors (fw_apsp_pred
+ * with a non-NULL pred, batched graphs with a predecessor matrix), whose
+ * kernels favour other tiles.  The fw_plan_tile / fw_plan_set / fw_autotune
+ * calls take a key where they take a dtype.
  */
-int fw_plan_tile(int dtype, int64_t n);
+#define FW_PLAN_PRED 2
 
 /*
- * fw_plan_set -- replace the plan table entry for a size bucket: graphs of
- * dtype `dtype` with n_lo <= n <= n_hi use `tile`.  Used by the autotuner to
- * install measured choices.  Returns FW_OK or FW_ERR_INVALID.
+ * Tile size the library picks for (key, n), from its tuned plan table.
+ * Returns the tile, or 0 for n <= 1, or -1 for a bad key / n < 0.
  */
-int fw_plan_set(int dtype, int64_t n_lo, int64_t n_hi, int tile);
+int fw_plan_tile(int key, int64_t n);
+
+/*
+ * fw_plan_set -- replace the plan table entry for a size bucket: solves of
+ * plan key `key` (dtype [| FW_PLAN_PRED]) with n_lo <= n <= n_hi use `tile`.
+ * Used by the autotuner to install measured choices.  Returns FW_OK or
+ * FW_ERR_INVALID.
+ */
+int fw_plan_set(int key, int64_t n_lo, int64_t n_hi, int tile);
 
 /* Restore the built-in plan table. */
 void fw_plan_reset(void);
@@ -178,7 +188,8 @@ void fw_plan_reset(void);
 int fw_apsp_ladder(void *d, int dtype, int64_t n, int64_t ld, int rung, void *stream);
 
 /*
- * fw_autotune -- the plan table's autotuner.  For each size bucket
+ * fw_autotune -- the plan table's autotuner (dtype: a plan key; with
+ * FW_PLAN_PRED the timed solves compute predecessors).  For each size bucket
  * [lo[k], hi[k]] (2 <= lo <= hi <= 65536) it times every tile of
  * fw_plan_tiles() at the bucket's geometric-middle size n and installs the
  * fastest with fw_plan_set.  objective 0 times one single-graph solve,

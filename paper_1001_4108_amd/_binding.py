@@ -255,14 +255,23 @@ def plan_tiles() -> list[int]:
     return [buf[i] for i in range(k)]
 
 
-def plan_tile(dtype, n: int) -> int:
-    code = FW_F32 if dtype in (torch.float32, "f32", FW_F32) else FW_I32
-    return int(lib().fw_plan_tile(code, int(n)))
+FW_PLAN_PRED = 2
 
 
-def plan_set(dtype, n_lo: int, n_hi: int, tile: int) -> None:
+def _plan_key(dtype, pred: bool) -> int:
     code = FW_F32 if dtype in (torch.float32, "f32", FW_F32) else FW_I32
-    _check(lib().fw_plan_set(code, int(n_lo), int(n_hi), int(tile)), "fw_plan_set")
+    return code | (FW_PLAN_PRED if pred else 0)
+
+
+def plan_tile(dtype, n: int, pred: bool = False) -> int:
+    """Tile of the plan table for (dtype, n); ``pred``: the table of solves
+    that also compute predecessors."""
+    return int(lib().fw_plan_tile(_plan_key(dtype, pred), int(n)))
+
+
+def plan_set(dtype, n_lo: int, n_hi: int, tile: int, pred: bool = False) -> None:
+    _check(lib().fw_plan_set(_plan_key(dtype, pred), int(n_lo), int(n_hi), int(tile)),
+           "fw_plan_set")
 
 
 def plan_reset() -> None:
@@ -270,14 +279,15 @@ def plan_reset() -> None:
 
 
 def autotune(dtype, buckets, objective: str = "single", batch: int = 256, reps: int = 3,
-             device=None) -> dict:
+             device=None, pred: bool = False) -> dict:
     """Time every tile per size bucket on the device and install the fastest.
 
     ``buckets`` is a list of (lo, hi) sizes; ``objective`` is "single" (one
-    solve) or "batched" (one persistent launch of ``batch`` graphs).  Returns
-    {(lo, hi): {"tile": t, "ms": {tile: median_ms}}}.
+    solve) or "batched" (one persistent launch of ``batch`` graphs); with
+    ``pred`` the solves compute predecessors and that table is tuned.
+    Returns {(lo, hi): {"tile": t, "ms": {tile: median_ms}}}.
     """
-    code = FW_F32 if dtype in (torch.float32, "f32", FW_F32) else FW_I32
+    code = _plan_key(dtype, pred)
     k = len(buckets)
     lo = (ctypes.c_int64 * k)(*[int(b[0]) for b in buckets])
     hi = (ctypes.c_int64 * k)(*[int(b[1]) for b in buckets])
@@ -293,13 +303,14 @@ def autotune(dtype, buckets, objective: str = "single", batch: int = 256, reps: 
             for i in range(k)}
 
 
-def save_plan(result: dict, path: str, dtype="f32", objective="single") -> None:
+def save_plan(result: dict, path: str, dtype="f32", objective="single", pred: bool = False) -> None:
     """Persist an autotune result as JSON."""
     import json
     rows = [{"lo": lo, "hi": hi, "tile": v["tile"], "ms": {str(t): m for t, m in v["ms"].items()}}
             for (lo, hi), v in result.items()]
     with open(path, "w") as f:
-        json.dump({"dtype": str(dtype), "objective": objective, "buckets": rows}, f, indent=1)
+        json.dump({"dtype": str(dtype), "pred": bool(pred), "objective": objective,
+                   "buckets": rows}, f, indent=1)
 
 
 def load_plan(path: str) -> None:
@@ -308,7 +319,7 @@ def load_plan(path: str) -> None:
     spec = json.load(open(path))
     dt = "i32" if "int32" in spec["dtype"] or spec["dtype"] == "i32" else "f32"
     for row in spec["buckets"]:
-        plan_set(dt, row["lo"], row["hi"], row["tile"])
+        plan_set(dt, row["lo"], row["hi"], row["tile"], pred=bool(spec.get("pred", False)))
 
 
 def fw_apsp_batched(mats, preds=None, stream=None) -> None:

@@ -31,30 +31,44 @@ struct PlanEntry {
 const int kTiles[] = {32, 64, 128};
 
 std::mutex g_plan_mu;
-std::vector<PlanEntry> g_plan[2];
+// one table per plan key: dtype, | FW_PLAN_PRED for solves with predecessors
+std::vector<PlanEntry> g_plan[4];
 
 void default_plan_locked() {
-    for (int dt = 0; dt < 2; ++dt) {
-        g_plan[dt].clear();
+    for (int key = 0; key < 4; ++key) {
+        std::vector<PlanEntry> &t = g_plan[key];
+        t.clear();
         // n <= tile: one closure over the whole graph (the plain algorithm)
-        g_plan[dt].push_back({0, 32, 32});
-        g_plan[dt].push_back({33, 64, 64});
-        g_plan[dt].push_back({65, 128, 128});
-        // blocked: below about 3k vertices a stage's 128-wide bulk fills the
-        // GPU less than once and the 128-step diagonal closure dominates;
-        // tile 64 then solves 1.5-2x faster (measured by fw_autotune)
-        g_plan[dt].push_back({129, 3072, 64});
-        g_plan[dt].push_back({3073, INT64_MAX, 128});
+        t.push_back({0, 32, 32});
+        t.push_back({33, 64, 64});
+        t.push_back({65, 128, 128});
+        // blocked (measured with fw_apsp_plan on one MI355X): below ~4.6k
+        // (fp32) / ~4.1k (int32) vertices a stage's 128-wide bulk fills the
+        // GPU too few times and the 128-step diagonal closure weighs more,
+        // and tile 64 solves faster (n=1024: 1.7x, n=4096: 1.15x); above,
+        // tile 128's lower traffic per update wins (n=12288: 1.4x).  With
+        // predecessors tile 64 won at every size measured up to 16384
+        // (int32 n=8192: 69 vs 82 ms).
+        const int64_t hi64 = (key & FW_PLAN_PRED) ? INT64_MAX : (key & 1) == FW_F32 ? 4608 : 4096;
+        t.push_back({129, hi64, 64});
+        if (hi64 != INT64_MAX) t.push_back({hi64 + 1, INT64_MAX, 128});
     }
 }
 
-int plan_tile(int dtype, int64_t n) {
+int plan_tile(int key, int64_t n) {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     if (g_plan[0].empty()) default_plan_locked();
     // the most recently installed entry covering n wins
-    for (auto it = g_plan[dtype].rbegin(); it != g_plan[dtype].rend(); ++it)
+    for (auto it = g_plan[key].rbegin(); it != g_plan[key].rend(); ++it)
         if (n >= it->n_lo && n <= it->n_hi) return it->tile;
     return 128;
+}
+
+int plan_key(int dtype, const int32_t *pred) { return dtype | (pred ? FW_PLAN_PRED : 0); }
+
+bool plan_key_ok(int key) {
+    const int dt = key & ~FW_PLAN_PRED;
+    return dt == FW_F32 || dt == FW_I32;
 }
 
 bool tile_supported(int tile) {
@@ -419,17 +433,20 @@ int solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int
 
 }  // namespace
 
-int plan_tile_for(int dtype, int64_t n) { return plan_tile(dtype, n); }
+int plan_tile_for(int dtype, int64_t n, bool pred) {
+    return plan_tile(dtype | (pred ? FW_PLAN_PRED : 0), n);
+}
 
 int solve_single(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64_t ldp,
                  hipStream_t st) {
     // eager launches: callers (the per-graph batch baseline, the server) solve
     // many different matrices, which a graph cache would only churn
-    return solve(d, dtype, (int)n, ld, pred, ldp, plan_tile(dtype, n), st, false);
+    return solve(d, dtype, (int)n, ld, pred, ldp, plan_tile(plan_key(dtype, pred), n), st, false);
 }
 
-int solve_with_tile(void *d, int dtype, int n, int64_t ld, int tile, hipStream_t st) {
-    return solve(d, dtype, n, ld, nullptr, 0, tile, st, false);
+int solve_with_tile(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
+                    hipStream_t st) {
+    return solve(d, dtype, n, ld, pred, ldp, tile, st, false);
 }
 
 int validate_matrix(const void *d, int dtype, int64_t n, int64_t ld, const int32_t *pred,
@@ -480,7 +497,8 @@ int fw_apsp_pred(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64
                  void *stream) {
     int s = validate(d, dtype, n, ld, pred, ld_pred);
     if (s != FW_OK) return s;
-    return solve(d, dtype, (int)n, ld, pred, ld_pred, plan_tile(dtype, n), (hipStream_t)stream);
+    return solve(d, dtype, (int)n, ld, pred, ld_pred, plan_tile(plan_key(dtype, pred), n),
+                 (hipStream_t)stream);
 }
 
 int fw_apsp_plan(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64_t ld_pred,
@@ -506,18 +524,18 @@ int fw_plan_tiles(int *tiles, int cap) {
     return cnt;
 }
 
-int fw_plan_tile(int dtype, int64_t n) {
-    if ((dtype != FW_F32 && dtype != FW_I32) || n < 0) return -1;
+int fw_plan_tile(int key, int64_t n) {
+    if (!plan_key_ok(key) || n < 0) return -1;
     if (n <= 1) return 0;
-    return plan_tile(dtype, n);
+    return plan_tile(key, n);
 }
 
-int fw_plan_set(int dtype, int64_t n_lo, int64_t n_hi, int tile) {
-    if ((dtype != FW_F32 && dtype != FW_I32) || n_lo < 0 || n_hi < n_lo || !tile_supported(tile))
+int fw_plan_set(int key, int64_t n_lo, int64_t n_hi, int tile) {
+    if (!plan_key_ok(key) || n_lo < 0 || n_hi < n_lo || !tile_supported(tile))
         return FW_ERR_INVALID;
     std::lock_guard<std::mutex> lk(g_plan_mu);
     if (g_plan[0].empty()) default_plan_locked();
-    g_plan[dtype].push_back({n_lo, n_hi, tile});
+    g_plan[key].push_back({n_lo, n_hi, tile});
     return FW_OK;
 }
 

@@ -186,6 +186,9 @@ __device__ void staged_product(const BatchItem &it, int kind, int b, int local, 
 #ifndef FW_STAGED64_BK
 #define FW_STAGED64_BK 16
 #endif
+#ifndef FW_STAGED64_WAVES
+#define FW_STAGED64_WAVES 6
+#endif
 template <typename T, int S, bool PRED>
 constexpr int staged_tm() {
     return S == 32 ? 2 : S == 64 ? (PRED ? 4 : FW_STAGED64_TM) : (PRED ? 4 : 8);
@@ -206,7 +209,8 @@ template <typename T, int S, bool PRED>
 constexpr int staged_waves() {
     return PRED ? (S == 64 ? 3 : 2)
                 : S == 32 ? 8
-                : S == 64 ? (staged_tm<T, S, PRED>() * staged_tn<T, S, PRED>() >= 32 ? 4 : 5)
+                : S == 64 ? (staged_tm<T, S, PRED>() * staged_tn<T, S, PRED>() >= 32 ? 4
+                                                                                     : FW_STAGED64_WAVES)
                           : 3;
 }
 template <typename T, int S, bool PRED>
@@ -386,7 +390,7 @@ void fill_batch_item(BatchItem &it, void *d, int dtype, int64_t n, int64_t ld, i
     it.ld = ld;
     it.ldp = p ? ldp : 0;
     it.n = (int32_t)n;
-    it.tile = n > 1 ? plan_tile_for(dtype, n) : 32;
+    it.tile = n > 1 ? plan_tile_for(dtype, n, p != nullptr) : 32;
     it.vec = vec_ok(d, ld) && (!p || vec_ok(p, ldp)) ? 1 : 0;
     it.pad = 0;
 }

@@ -72,7 +72,12 @@ hipError_t launch_batched_raw(int dtype, bool pred, BatchHeader *hdr, const Batc
 int batched_resident_grid(int dtype, bool pred);
 void fill_batch_item(BatchItem &it, void *d, int dtype, int64_t n, int64_t ld, int32_t *p,
                      int64_t ldp);
-int plan_tile_for(int dtype, int64_t n);
+// The plan table's tile for (dtype, n), from the table of solves with
+// predecessors when `pred`.
+int plan_tile_for(int dtype, int64_t n, bool pred);
+// One solve with the given tile, eager launches (pred may be NULL).
+int solve_with_tile(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
+                    hipStream_t st);
 int validate_matrix(const void *d, int dtype, int64_t n, int64_t ld, const int32_t *pred,
                     int64_t ldp);
 int solve_single(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64_t ldp,

@@ -22,7 +22,8 @@
 #include "fw_tiles.h"
 
 namespace fw {
-int solve_with_tile(void *d, int dtype, int n, int64_t ld, int tile, hipStream_t st);
+int solve_with_tile(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
+                    hipStream_t st);
 
 namespace {
 
@@ -207,7 +208,7 @@ extern "C" int fw_apsp_ladder(void *d, int dtype, int64_t n, int64_t ld, int run
     if (n > 65536 || (int64_t)(n + 255) / 256 > 0x7fffffffLL) return FW_ERR_UNSUPPORTED;
     if (n <= 1) return FW_OK;
     hipStream_t st = (hipStream_t)stream;
-    if (rung == 3) return solve_with_tile(d, dtype, (int)n, ld, 64, st);
+    if (rung == 3) return solve_with_tile(d, dtype, (int)n, ld, nullptr, 0, 64, st);
     if (rung == 4) return solve_single(d, dtype, n, ld, nullptr, 0, st);
     if (dtype == FW_F32) return status_of(run_rung<float>(rung, (float *)d, (int)n, ld, st));
     return status_of(run_rung<int32_t>(rung, (int32_t *)d, (int)n, ld, st));

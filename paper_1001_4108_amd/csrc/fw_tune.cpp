@@ -3,7 +3,9 @@
 //
 // Timing uses a matrix of zeros: the sweep is data-oblivious (section 1: the
 // run time of Floyd-Warshall does not depend on the graph), so the timings
-// hold for every input of that size.  Two objectives:
+// hold for every input of that size.  With FW_PLAN_PRED in the dtype argument
+// the solves compute predecessors too and the table of such solves is tuned.
+// Two objectives:
 //   0  one single-graph solve of the bucket's representative size;
 //   1  one batch-plan launch of `batch` graphs of that size (persistent or
 //      stage-batched, whichever the plan uses for that size; batch plans read
@@ -17,10 +19,6 @@
 
 #include "../../include/fwapsp.h"
 #include "fw_internal.h"
-
-namespace fw {
-int solve_with_tile(void *d, int dtype, int n, int64_t ld, int tile, hipStream_t st);
-}
 
 using namespace fw;
 
@@ -54,7 +52,9 @@ double median(std::vector<double> v) {
 
 extern "C" int fw_autotune(int dtype, const int64_t *lo, const int64_t *hi, int nbuckets,
                            int objective, int batch, int reps, int *tile_out, double *ms_out) {
-    if ((dtype != FW_F32 && dtype != FW_I32) || !lo || !hi || nbuckets < 1 || !tile_out ||
+    const int base = dtype & ~FW_PLAN_PRED;
+    const bool pred = (dtype & FW_PLAN_PRED) != 0;
+    if ((base != FW_F32 && base != FW_I32) || !lo || !hi || nbuckets < 1 || !tile_out ||
         (objective != 0 && objective != 1) || reps < 1 || (objective == 1 && batch < 1))
         return FW_ERR_INVALID;
     for (int k = 0; k < nbuckets; ++k)
@@ -71,14 +71,20 @@ extern "C" int fw_autotune(int dtype, const int64_t *lo, const int64_t *hi, int 
         const int64_t ld = (n + 3) / 4 * 4;
         const int count = objective == 1 ? batch : 1;
         const size_t per = (size_t)n * (size_t)ld * 4;
+        const size_t total = per * (size_t)count * (pred ? 2 : 1);  // distances [, predecessors]
         if (sc.mat) hipFree(sc.mat);
         sc.mat = nullptr;
-        if ((e = hipMalloc(&sc.mat, per * (size_t)count)) != hipSuccess) return status_of(e);
-        if ((e = hipMemsetAsync(sc.mat, 0, per * (size_t)count, sc.st)) != hipSuccess)
-            return status_of(e);
+        if ((e = hipMalloc(&sc.mat, total)) != hipSuccess) return status_of(e);
+        if ((e = hipMemsetAsync(sc.mat, 0, total, sc.st)) != hipSuccess) return status_of(e);
         std::vector<void *> ptrs((size_t)count);
+        std::vector<int32_t *> preds((size_t)count, nullptr);
         std::vector<int64_t> ns((size_t)count, n), lds((size_t)count, ld);
-        for (int g = 0; g < count; ++g) ptrs[(size_t)g] = static_cast<char *>(sc.mat) + per * (size_t)g;
+        for (int g = 0; g < count; ++g) {
+            ptrs[(size_t)g] = static_cast<char *>(sc.mat) + per * (size_t)g;
+            if (pred)
+                preds[(size_t)g] = reinterpret_cast<int32_t *>(static_cast<char *>(sc.mat) +
+                                                               per * (size_t)(count + g));
+        }
         double best = 1e300;
         int best_tile = tiles[0];
         for (int t = 0; t < ntiles; ++t) {
@@ -89,15 +95,17 @@ extern "C" int fw_autotune(int dtype, const int64_t *lo, const int64_t *hi, int 
             if (s != FW_OK) return s;
             fw_batch_plan plan = nullptr;
             if (objective == 1) {
-                s = fw_batch_plan_create(ptrs.data(), ns.data(), lds.data(), count, dtype, nullptr,
-                                         nullptr, &plan);
+                s = fw_batch_plan_create(ptrs.data(), ns.data(), lds.data(), count, base,
+                                         pred ? preds.data() : nullptr,
+                                         pred ? lds.data() : nullptr, &plan);
                 if (s != FW_OK) return s;
             }
             std::vector<double> times;
             for (int r = 0; r <= reps && s == FW_OK; ++r) {  // the first run is a warm-up
                 if ((e = hipEventRecord(sc.e0, sc.st)) != hipSuccess) s = status_of(e);
                 if (s == FW_OK)
-                    s = objective == 0 ? solve_with_tile(sc.mat, dtype, n, ld, tile, sc.st)
+                    s = objective == 0 ? solve_with_tile(sc.mat, base, n, ld, preds[0], ld, tile,
+                                                         sc.st)
                                        : fw_batch_plan_launch(plan, 0, sc.st);
                 if (s == FW_OK && (e = hipEventRecord(sc.e1, sc.st)) != hipSuccess)
                     s = status_of(e);

@@ -29,9 +29,10 @@ def graph(n, dtype, seed):
 @pytest.fixture(autouse=True)
 def mixed_tiles():
     for dt in ("f32", "i32"):
-        fw.plan_set(dt, 257, 400, 32)
-        fw.plan_set(dt, 401, 700, 64)
-        fw.plan_set(dt, 701, 4096, 128)
+        for pred in (False, True):
+            fw.plan_set(dt, 257, 400, 32, pred=pred)
+            fw.plan_set(dt, 401, 700, 64, pred=pred)
+            fw.plan_set(dt, 701, 4096, 128, pred=pred)
     yield
     fw.plan_reset()
 

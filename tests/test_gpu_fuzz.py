@@ -86,7 +86,9 @@ def test_randomized_batches():
             code = "f32" if dtype == np.float32 else "i32"
             fw.plan_reset()
             for lo, hi in ((2, 32), (33, 64), (65, 128), (129, 256), (257, 700)):
-                fw.plan_set(code, lo, hi, int(rng.choice([32, 64, 128])))
+                tile = int(rng.choice([32, 64, 128]))
+                fw.plan_set(code, lo, hi, tile)
+                fw.plan_set(code, lo, hi, tile, pred=True)
             count = int(rng.integers(20, 120))
             graphs, bufs, views, preds = [], [], [], []
             for g in range(count):
