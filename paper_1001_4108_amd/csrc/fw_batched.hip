@@ -36,6 +36,18 @@ namespace {
 
 constexpr int kBatchThreads = 256;
 
+// The graphs' matrices are reached through pointers read from the plan's
+// tables, which the compiler must treat as generic (flat) addresses; flat
+// loads also count against the LDS wait counter, so a wait for an LDS read
+// also waits for the global prefetch in flight.  Converting through an
+// integer to the global address space lets the compiler emit global loads
+// (a plain cast pair would be folded away).
+template <typename T>
+__device__ __forceinline__ T *as_global(T *p) {
+    auto *g = (__attribute__((address_space(1))) T *)(uintptr_t)p;
+    return (T *)g;
+}
+
 // LDS of the persistent kernel whose largest tile is MAXS.
 template <typename T, bool PRED, int MAXS>
 constexpr int batch_smem_bytes() {
@@ -44,6 +56,8 @@ constexpr int batch_smem_bytes() {
 
 template <typename T, int S, int TMC, int TM, bool VEC, bool PRED>
 __device__ void blocked_in_wg(T *d, int32_t *p, int n, int64_t ld, int64_t ldp, char *smem) {
+    d = as_global(d);
+    p = as_global(p);
     const int nb = (n + S - 1) / S;
     const int m = nb - 1;
     for (int b = 0; b < nb; ++b) {
@@ -66,8 +80,8 @@ __device__ void blocked_in_wg(T *d, int32_t *p, int n, int64_t ld, int64_t ldp, 
 
 template <typename T, bool PRED, int MAXS>
 __device__ void solve_graph(const BatchItem &it, char *smem) {
-    T *d = static_cast<T *>(it.d);
-    int32_t *p = PRED ? it.p : nullptr;
+    T *d = as_global(static_cast<T *>(it.d));
+    int32_t *p = PRED ? as_global(it.p) : nullptr;
     const int n = it.n;
     const int64_t ld = it.ld, ldp = it.ldp;
     if constexpr (PRED) {
@@ -161,8 +175,8 @@ constexpr bool staged_can_close();
 
 template <typename T, int S, int BK, int TM, int TN, bool VEC, bool PRED>
 __device__ void staged_product(const BatchItem &it, int kind, int b, int local, char *smem) {
-    T *d = static_cast<T *>(it.d);
-    int32_t *p = PRED ? it.p : nullptr;
+    T *d = as_global(static_cast<T *>(it.d));
+    int32_t *p = PRED ? as_global(it.p) : nullptr;
     const int m = (it.n + S - 1) / S - 1;
     int bi, bj;
     if (kind == kStagedPanel)
@@ -223,12 +237,12 @@ staged_kernel(const BatchItem *items, const StagedWork *work, int kind, int b) {
     const BatchItem it = items[w.item];
     if (kind == kStagedPredInit || kind == kStagedPredFix) {
         if constexpr (PRED) {
-            T *d = static_cast<T *>(it.d);
+            T *d = as_global(static_cast<T *>(it.d));
             const int n = it.n;
             for (int64_t c = threadIdx.x; c < (int64_t)n * n; c += NT) {
                 const int i = (int)(c / n), j = (int)(c - (int64_t)i * n);
                 const T v = d[(int64_t)i * it.ld + j];
-                int32_t &q = it.p[(int64_t)i * it.ldp + j];
+                int32_t &q = as_global(it.p)[(int64_t)i * it.ldp + j];
                 if (kind == kStagedPredInit)
                     q = (i != j && !Ar<T>::absent(v)) ? i : kPredNone;
                 else if (i == j || q == kPredNone || Ar<T>::unreachable(v))
@@ -259,9 +273,9 @@ staged_kernel(const BatchItem *items, const StagedWork *work, int kind, int b) {
                       "closure scratch must fit the product's LDS");
         if (w.local & kStagedClose) {
             __syncthreads();  // the tile's stores before its reloads
-            T *d = static_cast<T *>(it.d);
+            T *d = as_global(static_cast<T *>(it.d));
             if (with_pred)
-                closure_tile<T, S, TM, PRED>(d, it.p, it.n, it.ld, it.ldp, (b + 1) * S, smem);
+                closure_tile<T, S, TM, PRED>(d, as_global(it.p), it.n, it.ld, it.ldp, (b + 1) * S, smem);
             else
                 closure_tile<T, S, TM, false>(d, nullptr, it.n, it.ld, 0, (b + 1) * S, smem);
         }
@@ -290,9 +304,9 @@ staged_diag_kernel(const BatchItem *items, const StagedWork *work, int b) {
                               : closure_smem_bytes<T, S, false>();
     __shared__ __align__(16) char smem[kSmem];
     const BatchItem it = items[work[blockIdx.x].item];
-    T *d = static_cast<T *>(it.d);
+    T *d = as_global(static_cast<T *>(it.d));
     if (PRED && it.p != nullptr)
-        closure_tile<T, S, staged_diag_tm<S>(), PRED>(d, it.p, it.n, it.ld, it.ldp, b * S, smem);
+        closure_tile<T, S, staged_diag_tm<S>(), PRED>(d, as_global(it.p), it.n, it.ld, it.ldp, b * S, smem);
     else
         closure_tile<T, S, staged_diag_tm<S>(), false>(d, nullptr, it.n, it.ld, 0, b * S, smem);
 }
