@@ -180,7 +180,10 @@ void fw_plan_reset(void);
  *      the whole operand tiles in LDS (64 KB per workgroup);
  *   3  as 2 with the operands staged in 16-deep LDS slices (the tile-64 path
  *      of fw_apsp_plan);
- *   4  the default path of fw_apsp / fw_apsp_i32.
+ *   4  tile 128: direct global->LDS slice copies, 8 x 8 register sub-tiles,
+ *      strip panels, the next diagonal tile closed in the bulk launch (the
+ *      path the plan table picks for large solves; rung 3 is its pick for
+ *      mid sizes).
  * d, dtype, n, ld, stream as fw_apsp_pred without predecessors.  Errors:
  * FW_ERR_INVALID for a bad rung or the argument errors of fw_apsp,
  * FW_ERR_UNSUPPORTED for n > 65536.

@@ -225,7 +225,7 @@ LADDER_RUNGS = {
     1: "blocked, 32x32 tiles in LDS, one cell per thread",
     2: "blocked, 64x64 tiles, 4x4 register sub-tiles, whole tiles in LDS",
     3: "blocked, 64x64 tiles, 4x4 register sub-tiles, staged 16-deep LDS slices",
-    4: "library default (tile 128, direct global->LDS copies)",
+    4: "tile 128, direct global->LDS copies, 8x8 register sub-tiles (the large-n path)",
 }
 
 

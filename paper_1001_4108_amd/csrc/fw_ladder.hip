@@ -14,8 +14,9 @@
 //           in LDS (64 KB per workgroup);
 //   rung 3  the same with the operands staged through LDS in 16-deep k-slices
 //           (16 KB per workgroup): the library's tile-64 path;
-//   rung 4  the library's default path (tile 128, direct global->LDS slice
-//           copies, strip panels, the next diagonal closed in the bulk).
+//   rung 4  the library's 128-wide path (direct global->LDS slice copies,
+//           8 x 8 cells per thread, strip panels, the next diagonal closed in
+//           the bulk), which the plan table picks for large solves.
 #include <hip/hip_runtime.h>
 
 #include "../../include/fwapsp.h"
@@ -209,7 +210,7 @@ extern "C" int fw_apsp_ladder(void *d, int dtype, int64_t n, int64_t ld, int run
     if (n <= 1) return FW_OK;
     hipStream_t st = (hipStream_t)stream;
     if (rung == 3) return solve_with_tile(d, dtype, (int)n, ld, nullptr, 0, 64, st);
-    if (rung == 4) return solve_single(d, dtype, n, ld, nullptr, 0, st);
+    if (rung == 4) return solve_with_tile(d, dtype, (int)n, ld, nullptr, 0, 128, st);
     if (dtype == FW_F32) return status_of(run_rung<float>(rung, (float *)d, (int)n, ld, st));
     return status_of(run_rung<int32_t>(rung, (int32_t *)d, (int)n, ld, st));
 }
