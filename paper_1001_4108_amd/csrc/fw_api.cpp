@@ -1,9 +1,11 @@
 // C ABI and host driver of libfwapsp (declared in include/fwapsp.h).
 //
 // The driver runs the stage loop of the blocked algorithm (section 3.2,
-// Fig. BFW-Alg): for every k-block b, three stream-ordered launches (diagonal
-// tile, panels, bulk).  It validates every argument before enqueueing
-// anything, picks the tile size from a plan table keyed by (dtype, n), and can
+// Fig. BFW-Alg): for every k-block b, stream-ordered launches of the diagonal
+// tile, the panels and the bulk -- where the bulk kernel can, it also closes
+// the next stage's diagonal tile, and stages after the first are two launches.
+// It validates every argument before enqueueing anything, picks the tile size
+// from a plan table keyed by (dtype, with predecessors or not, n), and can
 // bracket each launch with HIP events for per-phase timing.
 #include <hip/hip_runtime.h>
 
