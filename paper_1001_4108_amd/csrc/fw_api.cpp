@@ -44,16 +44,23 @@ void default_plan_locked() {
         t.push_back({0, 32, 32});
         t.push_back({33, 64, 64});
         t.push_back({65, 128, 128});
-        // blocked (measured with fw_apsp_plan on one MI355X): below ~4.6k
-        // (fp32) / ~4.1k (int32) vertices a stage's 128-wide bulk fills the
-        // GPU too few times and the 128-step diagonal closure weighs more,
-        // and tile 64 solves faster (n=1024: 1.7x, n=4096: 1.15x); above,
-        // tile 128's lower traffic per update wins (n=12288: 1.4x).  With
-        // predecessors tile 64 won at every size measured up to 16384
-        // (int32 n=8192: 69 vs 82 ms).
-        const int64_t hi64 = (key & FW_PLAN_PRED) ? INT64_MAX : (key & 1) == FW_F32 ? 4608 : 4096;
-        t.push_back({129, hi64, 64});
-        if (hi64 != INT64_MAX) t.push_back({hi64 + 1, INT64_MAX, 128});
+        // blocked (measured with fw_apsp_plan / fw_autotune on one MI355X):
+        // below ~4.6k (fp32) / ~4.1k (int32) vertices a stage's 128-wide bulk
+        // fills the GPU too few times and the 128-step diagonal closure
+        // weighs more, and tile 64 solves faster (n=1024: 1.7x, n=4096:
+        // 1.15x); above, tile 128's lower traffic per update wins (n=12288:
+        // 1.4x).  With predecessors tile 128 never won (int32 n=8192: 69 vs
+        // 82 ms at tile 64), and tile 32 wins below ~2k (fp32) / ~1k (int32)
+        // vertices (fp32 n~1448: 4.0 vs 4.6 ms; int32 n~724: 0.78 vs 0.83).
+        if (key & FW_PLAN_PRED) {
+            const int64_t hi32 = (key & 1) == FW_F32 ? 2048 : 1024;
+            t.push_back({129, hi32, 32});
+            t.push_back({hi32 + 1, INT64_MAX, 64});
+        } else {
+            const int64_t hi64 = (key & 1) == FW_F32 ? 4608 : 4096;
+            t.push_back({129, hi64, 64});
+            t.push_back({hi64 + 1, INT64_MAX, 128});
+        }
     }
 }
 

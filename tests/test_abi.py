@@ -82,14 +82,15 @@ def test_plan_table_predecessor_key():
         for n in (2, 100, 512, 5000, 16384):
             assert B.plan_tile(dt, n, pred=True) == B.lib().fw_plan_tile(code | 2, n)
             assert B.plan_tile(dt, n, pred=True) in B.plan_tiles()
-    # built-in defaults: tile 64 above 128 vertices with predecessors, 128 for
-    # large solves without
+    # built-in defaults: with predecessors tile 32 for small blocked solves and
+    # 64 above, without 64 then 128 for large solves
     assert B.plan_tile("i32", 8192, pred=True) == 64
+    assert B.plan_tile("i32", 500, pred=True) == 32 and B.plan_tile("f32", 1500, pred=True) == 32
     assert B.plan_tile("f32", 16384) == 128 and B.plan_tile("i32", 8192) == 128
     assert B.plan_tile("f32", 1024) == 64
     B.plan_set("i32", 1000, 2000, 32, pred=True)
     assert B.plan_tile("i32", 1500, pred=True) == 32
-    assert B.plan_tile("i32", 1500) == 64 and B.plan_tile("f32", 1500, pred=True) == 64
+    assert B.plan_tile("i32", 1500) == 64 and B.plan_tile("i32", 2500, pred=True) == 64
     assert B.lib().fw_plan_tile(4, 10) == -1 and B.lib().fw_plan_tile(-1, 10) == -1
     assert B.lib().fw_plan_set(6, 1, 2, 64) == 1
     B.plan_reset()
