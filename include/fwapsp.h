@@ -212,12 +212,13 @@ int fw_autotune(int dtype, const int64_t *lo, const int64_t *hi, int nbuckets, i
 /*
  * fw_apsp_batched -- many independent graphs in one call.  Graphs of 33
  * vertices and more are stage-batched: for each tile size (from the plan
- * table), stage b of the blocked schedule (section 3.2) is at most three
- * launches shared by all such graphs that have a stage b -- their diagonal
- * tiles, their panel tiles, their bulk tiles (the bulk launch also closes
- * each graph's next diagonal tile where the tile size allows).  Smaller graphs go through one
- * persistent launch whose workgroups take graphs from a device work counter,
- * largest first, and solve each alone.
+ * table: a graph with a predecessor matrix reads the FW_PLAN_PRED part),
+ * stage b of the blocked schedule (section 3.2) is at most three launches
+ * shared by all such graphs that have a stage b -- their diagonal tiles,
+ * their panel tiles, their bulk tiles (the bulk launch also closes each
+ * graph's next diagonal tile where the tile size allows).  Smaller graphs go
+ * through one persistent launch whose workgroups take graphs from a device
+ * work counter, largest first, and solve each alone.
  *   d        HOST array of `count` device pointers, one n[g] x n[g] matrix
  *            each (leading dimension ld[g] >= n[g]); graphs must not alias.
  *   n, ld    HOST arrays of `count` sizes and leading dimensions.
