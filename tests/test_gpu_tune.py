@@ -34,3 +34,31 @@ def test_autotune_installs_fastest_tile(objective, tmp_path):
     torch.cuda.synchronize()
     assert np.array_equal(d.cpu().numpy().view(np.uint32), oracle.fw(W).view(np.uint32))
     fw.plan_reset()
+
+
+@pytest.mark.parametrize("objective", ["single", "batched"])
+def test_autotune_predecessor_table(objective, tmp_path):
+    """Tuning with predecessors writes the FW_PLAN_PRED part only, and a
+    solve with predecessors at the tuned tile is still bit-exact."""
+    fw.plan_reset()
+    before = {n: fw.plan_tile(torch.int32, n) for n in (150, 250)}
+    res = fw.autotune(torch.int32, [(129, 300)], objective=objective, batch=16, reps=2, pred=True)
+    v = res[(129, 300)]
+    assert v["tile"] in fw.plan_tiles() and v["ms"][v["tile"]] == min(v["ms"].values())
+    for n in (150, 250):
+        assert fw.plan_tile(torch.int32, n, pred=True) == v["tile"]
+        assert fw.plan_tile(torch.int32, n) == before[n]
+    path = tmp_path / "plan_pred.json"
+    fw.save_plan(res, str(path), dtype="i32", objective=objective, pred=True)
+    fw.plan_reset()
+    fw.load_plan(str(path))
+    assert fw.plan_tile(torch.int32, 200, pred=True) == v["tile"]
+    g = gen.reweighted_graph(211, 0.2, 1, 40, -10, 10, seed=8)
+    d = torch.from_numpy(g.w).cuda()
+    P = torch.empty((211, 211), dtype=torch.int32, device="cuda")
+    fw.fw_apsp_pred(d, P)
+    torch.cuda.synchronize()
+    ref = oracle.fw(g.w)
+    assert np.array_equal(d.cpu().numpy(), ref)
+    assert np.array_equal(P.cpu().numpy(), oracle.canonical_pred(ref, g.w))
+    fw.plan_reset()
