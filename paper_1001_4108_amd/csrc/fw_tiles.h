@@ -23,12 +23,37 @@ namespace fw {
 
 template <typename T> struct Ar;
 
+// fp32 minimum and maximum.  With FW_MINIMUM the IEEE 754-2019 forms
+// (gfx950's v_minimum3_f32 / v_maximum3_f32): IEEE-mode v_min_f32 needs its
+// operands quieted first, and wherever the compiler cannot prove a value is
+// already canonical (a load, a value pinned across a barrier) it spends a
+// v_max_f32 x, x, x on it; the 2019 forms need none.  The two agree except
+// on NaN (excluded by the contract) and on which zero of +0 / -0 is
+// returned (left open by the contract).
+#ifndef FW_MINIMUM
+#define FW_MINIMUM 1
+#endif
+__device__ __forceinline__ float fmin32(float a, float b) {
+#if FW_MINIMUM
+    return __builtin_elementwise_minimum(a, b);
+#else
+    return __builtin_fminf(a, b);
+#endif
+}
+__device__ __forceinline__ float fmax32(float a, float b) {
+#if FW_MINIMUM
+    return __builtin_elementwise_maximum(a, b);
+#else
+    return __builtin_fmaxf(a, b);
+#endif
+}
+
 template <> struct Ar<float> {
     __device__ __forceinline__ static float inf() { return __builtin_inff(); }
     __device__ __forceinline__ static float add(float a, float b) { return a + b; }
-    __device__ __forceinline__ static float min2(float a, float b) { return __builtin_fminf(a, b); }
+    __device__ __forceinline__ static float min2(float a, float b) { return fmin32(a, b); }
     __device__ __forceinline__ static float min3(float a, float b, float c) {
-        return __builtin_fminf(__builtin_fminf(a, b), c);
+        return fmin32(fmin32(a, b), c);
     }
     __device__ __forceinline__ static bool absent(float v) { return v == __builtin_inff(); }
     __device__ __forceinline__ static bool unreachable(float v) { return v == __builtin_inff(); }
@@ -56,10 +81,10 @@ template <typename T> struct ArMaxMin;
 
 template <> struct ArMaxMin<float> {
     __device__ __forceinline__ static float inf() { return -__builtin_inff(); }
-    __device__ __forceinline__ static float add(float a, float b) { return __builtin_fminf(a, b); }
-    __device__ __forceinline__ static float min2(float a, float b) { return __builtin_fmaxf(a, b); }
+    __device__ __forceinline__ static float add(float a, float b) { return fmin32(a, b); }
+    __device__ __forceinline__ static float min2(float a, float b) { return fmax32(a, b); }
     __device__ __forceinline__ static float min3(float a, float b, float c) {
-        return __builtin_fmaxf(__builtin_fmaxf(a, b), c);
+        return fmax32(fmax32(a, b), c);
     }
 };
 
