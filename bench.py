@@ -279,16 +279,19 @@ def bench_batched(torch, fw, gen, dev, reps):
                                for (lo, hi), v in tuned.items()}}
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    for mode, nrep in (("graph", reps), ("kernel", reps), ("per_graph", max(1, reps // 2))):
+    # warm-up launches per mode: the first replays of a fresh graph run a few
+    # percent slower than the steady state (3.30 vs 3.21 ms measured)
+    for mode, nrep, warm in (("graph", reps, 3), ("kernel", reps, 3),
+                             ("per_graph", max(1, reps // 2), 1)):
         times = []
-        for r in range(nrep + 1):
+        for r in range(nrep + warm):
             pool.copy_(pristine)
             torch.cuda.synchronize(dev)
             ev0.record()
             plan.launch(mode)
             ev1.record()
             torch.cuda.synchronize(dev)
-            if r:  # the first launch of each mode is a warm-up
+            if r >= warm:
                 times.append(ev0.elapsed_time(ev1))
         ms = float(np.median(times))
         out[mode] = {"ms": ms, "graphs_per_s": len(graphs) / (ms / 1e3),

@@ -48,6 +48,11 @@ __device__ __forceinline__ T *as_global(T *p) {
     return (T *)g;
 }
 
+// Sets a persistent launch's work counter to 0 before the launch.
+__global__ void batch_reset_kernel(BatchHeader *hdr) {
+    if (threadIdx.x == 0) hdr->next = 0;
+}
+
 // LDS of the persistent kernel whose largest tile is MAXS.
 template <typename T, bool PRED, int MAXS>
 constexpr int batch_smem_bytes() {
@@ -564,6 +569,16 @@ int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t coun
     if (count)
         std::copy(items.begin(), items.end(),
                   reinterpret_cast<BatchItem *>(static_cast<char *>(pl->host) + sizeof(BatchHeader)));
+    // the descriptor table never changes either (only the persistent part's
+    // work counter, which each launch resets with a kernel): uploaded once
+    {
+        hipStream_t up = nullptr;
+        if (hipStreamCreateWithFlags(&up, hipStreamNonBlocking) != hipSuccess) return FW_ERR_HIP;
+        hipError_t e = hipMemcpyAsync(pl->dev, pl->host, pl->bytes, hipMemcpyHostToDevice, up);
+        if (e == hipSuccess) e = hipStreamSynchronize(up);
+        hipStreamDestroy(up);
+        if (e != hipSuccess) return status_of(e);
+    }
     if (n_staged == 0) return FW_OK;
 
     // Stage-batched part: per tile size, the launch sequence and its work
@@ -635,13 +650,13 @@ int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t coun
     return status_of(e);
 }
 
-// Enqueue: refresh the device table (which also resets the work counter) and
-// launch the persistent kernel.  Both are plain stream operations, so the
-// same sequence can be captured into a graph.
+// Enqueue: the stage-batched launches, then (if the plan has a persistent
+// part) the reset of its work counter and the persistent kernel.  All are
+// kernel launches (no copy or memset node), so the same sequence can be
+// captured into a graph and replayed.
 int enqueue_plan(fw_batch_plan_s *pl, hipStream_t st, bool capturing) {
     if (pl->count == 0) return FW_OK;
-    hipError_t e = hipMemcpyAsync(pl->dev, pl->host, pl->bytes, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return status_of(e);
+    hipError_t e = hipSuccess;
     auto *hdr = static_cast<BatchHeader *>(pl->dev);
     auto *items =
         reinterpret_cast<const BatchItem *>(static_cast<char *>(pl->dev) + sizeof(BatchHeader));
@@ -651,6 +666,8 @@ int enqueue_plan(fw_batch_plan_s *pl, hipStream_t st, bool capturing) {
         if (e != hipSuccess) return status_of(e);
     }
     if (pl->count == pl->n_staged) return FW_OK;
+    batch_reset_kernel<<<1, 64, 0, st>>>(hdr);
+    if ((e = hipGetLastError()) != hipSuccess) return status_of(e);
     const BatchItem *rest = items + pl->n_staged;
     if (capturing)
         return status_of(
