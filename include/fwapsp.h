@@ -230,10 +230,9 @@ int fw_autotune(int dtype, const int64_t *lo, const int64_t *hi, int nbuckets, i
  * A graph's result is bit-identical to fw_apsp_pred on the same graph alone.
  * Errors: FW_ERR_INVALID if any graph's arguments are invalid (nothing is
  * enqueued), FW_ERR_UNSUPPORTED if a graph exceeds fw_batched_max_n().
- * The call uploads the stage-batched work table (graph, tile) synchronously
- * on a private stream, then enqueues the descriptor-table copy (from
- * library-owned pinned memory) and the launches on `stream`; it may be called
- * again at once.
+ * The call uploads the descriptor table and the stage-batched work table
+ * (graph, tile) synchronously on a private stream, then enqueues the launches
+ * on `stream`; it may be called again at once.
  */
 int fw_apsp_batched(void *const *d, const int64_t *n, const int64_t *ld,
                     int64_t count, int dtype, int32_t *const *pred,
@@ -245,20 +244,19 @@ int64_t fw_batched_max_n(int dtype, int with_pred);
 /*
  * Reusable batch plans.  fw_batch_plan_create validates the graphs exactly as
  * fw_apsp_batched does and builds the descriptor table (pinned host memory
- * plus a device copy) and the stage-batched work table (device, uploaded at
- * creation), all owned by the plan; the matrices must stay allocated for the
+ * plus a device copy) and the stage-batched work table (device), both
+ * uploaded at creation and owned by the plan; the matrices must stay allocated for the
  * plan's lifetime and are re-solved in place on every launch.  The tiles are
  * read from the plan table at creation.  fw_batch_plan_launch enqueues on
  * `stream`, by `mode`:
- *   0  the descriptor refresh (which also resets the device work counter),
- *      the stage-batched launches and the persistent kernel, as plain stream
- *      operations;
+ *   0  the stage-batched launches, the reset of the device work counter (a
+ *      kernel) and the persistent kernel, as plain stream operations;
  *   1  the same operations captured once into a hipGraph, replayed by every
  *      later launch (one graph launch per batch);
  *   2  no persistent kernel: every graph through the single-graph stage
  *      loop of fw_apsp_pred (the per-graph launch baseline).
  * All modes give bit-identical results.  Launches of one plan must not
- * overlap in time (they share the table).  fw_batch_plan_destroy synchronises
+ * overlap in time (they share the work counter).  fw_batch_plan_destroy synchronises
  * the device and frees the plan.  fw_batch_plan_grid returns the persistent
  * grid size (workgroups), or -1 for a NULL plan.
  */
