@@ -85,7 +85,9 @@ constexpr int tile_smem_bytes() {
 
 // Forms whose geometry is the closure's (4 x 4 cells per thread: tile 64 over
 // 256 threads, the 128-wide predecessor form over 1024) can also close the
-// next stage's diagonal tile in mode 1, as bulk_dma_kernel does.
+// next stage's diagonal tile in mode 1, as bulk_dma_kernel does.  (Tile 32
+// over 64 threads has it too, but one wave's 32-wide closure is slower than
+// the separate four-wave diagonal launch.)
 template <int S, int TM, int TN, bool PRED>
 constexpr bool tile_can_close() {
     return TM == 4 && TN == 4 && (S == 64 || (PRED && S == 128));
@@ -338,6 +340,7 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
                                              (unsigned)(2 * m - 1), st);
         return hipSuccess;
     }
+    if (close_next) return hipErrorInvalidValue;  // every closing form is handled above
     return vec ? tile_t<T, true, false, A>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid, st)
                : tile_t<T, false, false, A>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid,
                                             st);
