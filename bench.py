@@ -306,6 +306,10 @@ def bench_batched(torch, fw, gen, dev, reps):
     return out
 
 
+FW_ERR_BUSY = 5
+QUEUE_CAP = 256
+
+
 def run_trace(torch, fw, srv, bases, tr, limit_s):
     """Open-loop replay: submit each request at its arrival time, then drain."""
     import threading
@@ -313,6 +317,7 @@ def run_trace(torch, fw, srv, bases, tr, limit_s):
     ids = {}
     t0 = time.perf_counter_ns()
     sub_err = []
+    refused = [0]  # requests the server refused at submission (queue cap)
 
     def submitter():
         try:
@@ -325,7 +330,12 @@ def run_trace(torch, fw, srv, bases, tr, limit_s):
                     if due - now > 200_000:
                         time.sleep((due - now - 100_000) / 1e9)
                 n, o, b = int(tr.n[r]), int(tr.o[r]), int(tr.b[r])
-                ids[srv.submit(bases[b][o:o + n, o:o + n])] = r
+                try:
+                    ids[srv.submit(bases[b][o:o + n, o:o + n])] = r
+                except fw.FwError as e:
+                    if e.status != FW_ERR_BUSY:
+                        raise
+                    refused[0] += 1
         except Exception as e:  # surfaced after the join
             sub_err.append(e)
 
@@ -338,7 +348,7 @@ def run_trace(torch, fw, srv, bases, tr, limit_s):
     if sub_err:
         raise sub_err[0]
     srv.drain(timeout_s=limit_s)
-    while len(recs) < len(tr.t):
+    while len(recs) < len(tr.t) - refused[0]:
         got = srv.poll(timeout_us=100000)
         if not got:
             break
@@ -349,7 +359,8 @@ def run_trace(torch, fw, srv, bases, tr, limit_s):
     span = (last - first) / 1e9
     upd = float(sum(float(c[1]) ** 3 for c in recs if c[2] == 0))
     st = srv.stats()
-    return {"requests": len(tr.t), "completed": int((np.array([c[2] for c in recs]) == 0).sum()),
+    return {"requests": len(tr.t), "refused": refused[0],
+            "completed": int((np.array([c[2] for c in recs]) == 0).sum()),
             "offered_per_s": len(tr.t) / float(tr.t[-1]) if len(tr.t) > 1 else 0.0,
             "solves_per_s": len(lat) / span, "updates_per_s": upd / span, "span_s": span,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
@@ -380,6 +391,15 @@ def bench_serving(torch, fw, gen, dev, seconds, rate):
         for frac in (0.5, 0.9):
             tr = gen.serving_trace(rate=cap * frac, duration=min(seconds, 3.0), seed=50 + int(frac * 10))
             out[f"at_{frac:.1f}x_capacity"] = run_trace(torch, fw, srv, bases, tr, 600)
+    # the same overload with admission control: at most QUEUE_CAP requests may
+    # wait, later ones are refused at submission (FW_ERR_BUSY); latency of the
+    # accepted ones
+    with fw.Server(torch.float32, queue_cap=QUEUE_CAP, **cfg) as srv:
+        for n in (64, 300, 700, 2000):
+            srv.submit(bases[0][:n, :n])
+        srv.drain(timeout_s=60)
+        srv.poll()
+        out[f"at_rate_queue_cap_{QUEUE_CAP}"] = run_trace(torch, fw, srv, bases, tr_full, 600)
     # correctness: a few requests of the trace solved through the server with
     # copy-back, compared with the oracle
     import oracle
@@ -510,6 +530,10 @@ def main():
         a = serving["at_rate"]
         log(f"serving: {a['solves_per_s']:.0f} solves/s, p50 {a['p50_ms']:.1f} ms, "
             f"p99 {a['p99_ms']:.1f} ms at {args.serve_rate:.0f} req/s offered")
+        c = serving[f"at_rate_queue_cap_{QUEUE_CAP}"]
+        log(f"serving, queue cap {QUEUE_CAP}: {c['solves_per_s']:.0f} solves/s, "
+            f"{c['refused']} of {c['requests']} refused, p50 {c['p50_ms']:.1f} ms, "
+            f"p99 {c['p99_ms']:.1f} ms")
 
     cpu = None
     if not args.no_cpu:
