@@ -1,6 +1,6 @@
 // C ABI and host driver of libfwapsp (declared in include/fwapsp.h).
 //
-// The driver runs the stage loop of the blocked algorithm (section 3.2,
+// The host side runs the stage loop of the blocked algorithm (section 3.2,
 // Fig. BFW-Alg): for every k-block b, stream-ordered launches of the diagonal
 // tile, the panels and the bulk -- where the bulk kernel can, it also closes
 // the next stage's diagonal tile, and stages after the first are two launches.
