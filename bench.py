@@ -86,6 +86,8 @@ def parse():
                     help="skip the ablation-ladder leg (rungs 0-4 at n=4096)")
     ap.add_argument("--no-maxmin", action="store_true",
                     help="skip the n=16384 widest-path (max, min) solve")
+    ap.add_argument("--no-closure", action="store_true",
+                    help="skip the n=16384 bit-packed reachability leg")
     ap.add_argument("--no-negative", action="store_true",
                     help="skip the n=8192 int32 negative-weight solve with predecessors")
     ap.add_argument("--no-serving", action="store_true")
@@ -158,6 +160,51 @@ def bench_maxmin(torch, fw, W, dev, reps=3):
                              oracle.widest_rows(Wm, srcs).astype(np.float32).view(np.uint32)))
     return {"workload": f"widest paths, n={n} fp32 (the same edges, absent -INF)", "ms": ms,
             "updates_per_s": float(n) ** 3 / (ms / 1e3), "check": "ok" if ok else "mismatch"}
+
+
+def bench_closure(torch, fw, gen, dev, n=16384, reps=5):
+    """Reachability (reflexive transitive closure) of an n=16384 digraph with
+    edge probability 1.2/n (long paths, many unreachable pairs), bit-packed:
+    the closure timed on resident packed words; the int32 (max, min) closure
+    of the same 0/1 matrix timed once beside it; rows checked against BFS."""
+    import numpy as np
+    import oracle
+    W = gen.dense_graph(n, 1.2 / n, 1, 1, seed=19, dtype=np.int32)
+    A = np.where(W == gen.I32_INF, 0, 1).astype(np.int32)
+    adj = torch.from_numpy(A).to(dev)
+    del A
+    pristine = fw.pack_bits(adj)
+    bits = pristine.clone()
+    fw.fw_transitive_closure_bits(bits, n)
+    torch.cuda.synchronize(dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(reps):
+        bits.copy_(pristine)
+        ev0.record()
+        fw.fw_transitive_closure_bits(bits, n)
+        ev1.record()
+        torch.cuda.synchronize(dev)
+        times.append(ev0.elapsed_time(ev1))
+    ms = float(np.median(times))
+    srcs = [0, n // 3, n - 1]
+    rows = fw.unpack_bits(bits, n)[torch.tensor(srcs, device=dev)].cpu().numpy()
+    ok = all(np.array_equal(rows[q].astype(bool), oracle.reach_row(W, s)) for q, s in enumerate(srcs))
+    # the same closure through the int32 (max, min) semiring, one cell per int
+    adj.fill_diagonal_(1)
+    ev0.record()
+    fw.fw_apsp_semiring(adj, "maxmin")
+    ev1.record()
+    torch.cuda.synchronize(dev)
+    ms_int = ev0.elapsed_time(ev1)
+    ok &= bool(np.array_equal(adj[torch.tensor(srcs, device=dev)].cpu().numpy(), rows))
+    del adj
+    return {"workload": f"reachability, n={n} digraph, edge prob 1.2/n, bit-packed "
+                        f"({n} x {fw.words_per_row(n)} words)",
+            "ms": ms, "cell_updates_per_s": float(n) ** 3 / (ms / 1e3),
+            "int32_maxmin_ms": ms_int, "speedup_vs_int32_maxmin": ms_int / ms,
+            "check": "ok" if ok else "mismatch"}
 
 
 # The paper's Table 1 at n=4096 (Tesla C1060, seconds): per-task threads,
@@ -503,6 +550,12 @@ def main():
         log("widest paths (max, min) n=16384")
         maxmin = bench_maxmin(torch, fw, W, dev)
 
+    closure = None
+    if not args.no_closure:
+        log("reachability (bit-packed) n=16384")
+        closure = bench_closure(torch, fw, gen, dev)
+        log(f"reachability: {closure['ms']:.2f} ms (int32 max-min {closure['int32_maxmin_ms']:.0f} ms)")
+
     ladder = None
     if not args.no_ladder:
         log("ablation ladder n=4096 (rungs 4..0)")
@@ -550,7 +603,8 @@ def main():
                    "n": n, "tile": tile, "global_batch": 1, "parallelism": "single-gpu"},
         "frac_of_update_peak": value / UPDATE_PEAK,
         "check": "ok" if ok else "mismatch",
-        "phases": phases, "roofline": roof, "cpu_baseline": cpu, "negative_int32_pred": negative, "maxmin": maxmin, "ladder": ladder,
+        "phases": phases, "roofline": roof, "cpu_baseline": cpu, "negative_int32_pred": negative, "maxmin": maxmin,
+        "transitive_closure": closure, "ladder": ladder,
         "batched": batched,
         "serving": serving,
         "paper_context": {"tesla_c1060_s_n16384": 53.06,

@@ -138,6 +138,35 @@ int fw_apsp_plan(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred,
 int fw_apsp_semiring(void *d, int dtype, int semiring, int64_t n, int64_t ld, void *stream);
 
 /*
+ * fw_transitive_closure_bits -- reachability on a bit-packed adjacency matrix:
+ * the blocked schedule (section 3.2) over the boolean semiring, in place.
+ * Row i is ceil(n / 32) 32-bit words; bit j % 32 of word j / 32 is the edge
+ * i -> j on input and "j is reachable from i" on output.
+ *   bits       device, n rows of ldw words (ldw >= ceil(n / 32)); bits of
+ *              columns >= n must be 0 (they stay 0); words past ceil(n / 32)
+ *              are neither read nor written.
+ *   reflexive  non-zero: every vertex reaches itself (the diagonal is set
+ *              first); zero: paths of one edge or more only (i reaches i iff
+ *              i lies on a cycle).
+ * Stream-ordered.  Errors: FW_ERR_INVALID for bits == NULL with n > 0, n < 0
+ * or ldw too small; FW_ERR_UNSUPPORTED for n > 2^30.
+ */
+int fw_transitive_closure_bits(uint32_t *bits, int64_t n, int64_t ldw, int reflexive,
+                               void *stream);
+
+/*
+ * fw_pack_bits / fw_unpack_bits -- convert between an n x n int32 matrix (ld
+ * >= n; non-zero = edge) and the bit layout above (ldw >= ceil(n / 32); the
+ * pack writes words 0 .. ceil(n / 32) - 1 of each row, column bits >= n as 0;
+ * the unpack writes 0 / 1).  Stream-ordered; the same errors as
+ * fw_transitive_closure_bits.
+ */
+int fw_pack_bits(const int32_t *adj, int64_t n, int64_t ld, uint32_t *bits, int64_t ldw,
+                 void *stream);
+int fw_unpack_bits(const uint32_t *bits, int64_t n, int64_t ldw, int32_t *adj, int64_t ld,
+                   void *stream);
+
+/*
  * Tile sizes fw_apsp_plan accepts: writes up to `cap` of them to `tiles`
  * (host memory) and returns how many exist.
  */

@@ -84,6 +84,9 @@ def _declare(L):
         "fw_plan_tiles": ([ctypes.POINTER(ci), ci], ci),
         "fw_apsp_semiring": ([vp, ci, ci, i64, i64, vp], ci),
         "fw_apsp_ladder": ([vp, ci, i64, i64, ci, vp], ci),
+        "fw_transitive_closure_bits": ([vp, i64, i64, ci, vp], ci),
+        "fw_pack_bits": ([vp, i64, i64, vp, i64, vp], ci),
+        "fw_unpack_bits": ([vp, i64, i64, vp, i64, vp], ci),
         "fw_plan_tile": ([ci, i64], ci),
         "fw_plan_set": ([ci, i64, i64, ci], ci),
         "fw_plan_reset": ([], None),
@@ -240,13 +243,73 @@ def fw_apsp_ladder(d: torch.Tensor, rung: int, stream=None) -> torch.Tensor:
     return d
 
 
+def words_per_row(n: int) -> int:
+    """32-bit words per row of the bit-packed adjacency layout."""
+    return (int(n) + 31) // 32
+
+
+def _bits(bits: torch.Tensor, n: int, name: str):
+    """(pointer, ldw) of an n x >= ceil(n/32) int32 device tensor holding the
+    packed words (int32 is uint32 reinterpreted)."""
+    if not isinstance(bits, torch.Tensor) or not bits.is_cuda or bits.dtype != torch.int32:
+        raise ValueError(f"{name} must be an int32 device tensor of packed words")
+    if bits.dim() != 2 or bits.shape[0] != n or bits.shape[1] < words_per_row(n):
+        raise ValueError(f"{name} must be {n} x >= {words_per_row(n)} words")
+    if n > 1 and bits.stride(1) != 1:
+        raise ValueError(f"{name} needs unit column stride")
+    return bits.data_ptr(), max(bits.stride(0), words_per_row(n)) if n else 0
+
+
+def pack_bits(adj: torch.Tensor, stream=None) -> torch.Tensor:
+    """Bit-packed copy (n x ceil(n/32) int32 words) of an int32 matrix whose
+    non-zero entries are edges."""
+    if adj.dtype != torch.int32:
+        raise TypeError("pack_bits takes an int32 0/1 matrix")
+    p, n, ld = _matrix(adj, "adj")
+    out = torch.empty((n, words_per_row(n)), dtype=torch.int32, device=adj.device)
+    with torch.cuda.device(adj.device):
+        _check(lib().fw_pack_bits(p, n, ld, out.data_ptr(), words_per_row(n),
+                                  _stream(adj, stream)), "fw_pack_bits")
+    return out
+
+
+def unpack_bits(bits: torch.Tensor, n: int, out: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+    """The n x n int32 0/1 matrix of a bit-packed one (into ``out`` if given)."""
+    bp, ldw = _bits(bits, n, "bits")
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.int32, device=bits.device)
+    if out.dtype != torch.int32:
+        raise TypeError("unpack_bits writes an int32 matrix")
+    p, m, ld = _matrix(out, "out")
+    if m != n:
+        raise ValueError("out must be n x n")
+    with torch.cuda.device(bits.device):
+        _check(lib().fw_unpack_bits(bp, n, ldw, p, ld, _stream(bits, stream)), "fw_unpack_bits")
+    return out
+
+
+def fw_transitive_closure_bits(bits: torch.Tensor, n: int, reflexive: bool = True,
+                               stream=None) -> torch.Tensor:
+    """Reachability in place on a bit-packed adjacency matrix (see pack_bits)."""
+    bp, ldw = _bits(bits, n, "bits")
+    with torch.cuda.device(bits.device):
+        _check(lib().fw_transitive_closure_bits(bp, int(n), ldw, 1 if reflexive else 0,
+                                                _stream(bits, stream)),
+               "fw_transitive_closure_bits")
+    return bits
+
+
 def fw_transitive_closure(adj: torch.Tensor, stream=None) -> torch.Tensor:
-    """Reachability in place on an int32 0/1 adjacency matrix (1 = edge; the
-    diagonal is set to 1 first)."""
+    """Reachability in place on an int32 0/1 adjacency matrix (non-zero =
+    edge; every vertex reaches itself): packed to bits, closed by the
+    bit-packed kernels, unpacked into ``adj``."""
     if adj.dtype != torch.int32:
         raise TypeError("transitive closure takes an int32 0/1 matrix")
-    adj.fill_diagonal_(1)
-    return fw_apsp_semiring(adj, "maxmin", stream)
+    n = adj.shape[0]
+    bits = pack_bits(adj, stream)
+    fw_transitive_closure_bits(bits, n, True, stream)
+    return unpack_bits(bits, n, adj, stream)
 
 
 def plan_tiles() -> list[int]:

@@ -1,0 +1,340 @@
+// Reachability (transitive closure) on bit-packed adjacency matrices: the
+// blocked schedule of section 3.2 over the boolean semiring (OR for min, AND
+// for +).  Row i of the n x n matrix is ceil(n / 32) 32-bit words; bit j % 32
+// of word j / 32 is the edge (or, after the solve, the path) i -> j.  A cell
+// update of the bulk ("row i gains row k if i reaches k") is one
+// v_and_or_b32 per 32 cells: the bit of i -> k, sign-extended to a full-word
+// mask, ANDed with word w of row k and ORed into word w of row i.
+//
+// k-blocks are 256 bits (8 words) wide; stage b runs
+//   bits_diag_kernel       the 256 x 256 diagonal block, closed by one wave
+//                          (Warshall's k-ordered steps, row k broadcast from
+//                          its owner lane with v_readlane);
+//   bits_row_panel_kernel  rows of block b, every other 8-word column block:
+//                          P <- P | D* x P (D* the closed diagonal block);
+//   bits_col_panel_kernel  columns of block b, every other 256-row block:
+//                          C <- C | C x D*;
+//   bits_bulk_kernel       the rest: X <- X | C x P.
+// As for distances, the panel and bulk steps are products with closed
+// blocks, so the result is exact reachability; OR is idempotent, so nothing
+// depends on the order of the updates.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/fwapsp.h"
+
+namespace fw {
+namespace {
+
+constexpr int kBW = 8;          // words per k-block
+constexpr int kBK = 32 * kBW;   // bits (vertices) per k-block
+
+// all ones where bit t of x is set, else 0
+__device__ __forceinline__ uint32_t bitmask(uint32_t x, int t) {
+    return (uint32_t)(-(int32_t)((x >> t) & 1u));
+}
+
+// Sets bit (i, i) for every vertex: the reflexive closure.
+__global__ void __launch_bounds__(256)
+bits_reflexive_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) bits[(int64_t)i * ldw + (i >> 5)] |= 1u << (i & 31);
+}
+
+// Stage b's diagonal block by one wave: lane l keeps rows k0 + l + 64 g
+// (g = 0..3), 8 words each, in registers.  Step k: the owner lane's row k is
+// read into scalar registers (v_readlane), and every row whose bit k is set
+// ORs it in.  Row k itself does not change in step k.
+__global__ void __launch_bounds__(64)
+bits_diag_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b) {
+    const int l = threadIdx.x;
+    const int k0 = b * kBK, w0 = b * kBW;
+    uint32_t r[4][kBW];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int i = k0 + l + 64 * g;
+#pragma unroll
+        for (int c = 0; c < kBW; ++c)
+            r[g][c] = (i < n && w0 + c < nw) ? bits[(int64_t)i * ldw + w0 + c] : 0u;
+    }
+    const int kreal = n - k0 < kBK ? n - k0 : kBK;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+        for (int cw = 0; cw < 2; ++cw) {
+            const int c = 2 * g + cw;  // the word holding bit k of every row
+#pragma unroll 1
+            for (int t = 0; t < 32; ++t) {
+                if (64 * g + 32 * cw + t >= kreal) break;  // uniform
+                const int owner = 32 * cw + t;
+                uint32_t rk[kBW];
+#pragma unroll
+                for (int q = 0; q < kBW; ++q)
+                    rk[q] = (uint32_t)__builtin_amdgcn_readlane((int)r[g][q], owner);
+#pragma unroll
+                for (int gg = 0; gg < 4; ++gg) {
+                    const uint32_t m = bitmask(r[gg][c], t);
+#pragma unroll
+                    for (int q = 0; q < kBW; ++q) r[gg][q] |= m & rk[q];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int i = k0 + l + 64 * g;
+#pragma unroll
+        for (int c = 0; c < kBW; ++c)
+            if (i < n && w0 + c < nw) bits[(int64_t)i * ldw + w0 + c] = r[g][c];
+    }
+}
+
+// Row panel: the rows of block b, word block wb != b (blockIdx.x enumerates
+// the other word blocks).  Thread t owns row k0 + t; every row of the block
+// is staged in LDS (old values) before any is written.
+__global__ void __launch_bounds__(256)
+bits_row_panel_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b) {
+    __shared__ uint32_t P[kBK][kBW];
+    const int t = threadIdx.x;
+    const int wb = (int)blockIdx.x < b ? (int)blockIdx.x : (int)blockIdx.x + 1;
+    const int k0 = b * kBK, w0 = wb * kBW;
+    const int i = k0 + t;
+    const bool row_ok = i < n;
+    uint32_t dk[kBW], acc[kBW];
+#pragma unroll
+    for (int c = 0; c < kBW; ++c) {
+        // the thread's row of the closed diagonal block (its masks)
+        dk[c] = (row_ok && b * kBW + c < nw) ? bits[(int64_t)i * ldw + b * kBW + c] : 0u;
+        acc[c] = (row_ok && w0 + c < nw) ? bits[(int64_t)i * ldw + w0 + c] : 0u;
+        P[t][c] = acc[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cw = 0; cw < kBW; ++cw) {
+        // a full unroll would hoist all 256 rows' LDS reads and spill
+#pragma unroll 4
+        for (int s = 0; s < 32; ++s) {
+            const uint32_t m = bitmask(dk[cw], s);
+            const int k = 32 * cw + s;
+#pragma unroll
+            for (int c = 0; c < kBW; ++c) acc[c] |= m & P[k][c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kBW; ++c)
+        if (row_ok && w0 + c < nw) bits[(int64_t)i * ldw + w0 + c] = acc[c];
+}
+
+// Column panel: word block b of the rows of row block rb != b (blockIdx.x
+// enumerates the other row blocks).  Thread t owns row 256 rb + t; the
+// closed diagonal block is staged in LDS.
+__global__ void __launch_bounds__(256)
+bits_col_panel_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b) {
+    __shared__ uint32_t D[kBK][kBW];
+    const int t = threadIdx.x;
+    const int rb = (int)blockIdx.x < b ? (int)blockIdx.x : (int)blockIdx.x + 1;
+    const int k0 = b * kBK, w0 = b * kBW;
+    {
+        const int k = k0 + t;
+#pragma unroll
+        for (int c = 0; c < kBW; ++c)
+            D[t][c] = (k < n && w0 + c < nw) ? bits[(int64_t)k * ldw + w0 + c] : 0u;
+    }
+    const int i = rb * kBK + t;
+    const bool row_ok = i < n;
+    uint32_t y[kBW], acc[kBW];
+#pragma unroll
+    for (int c = 0; c < kBW; ++c) {
+        y[c] = (row_ok && w0 + c < nw) ? bits[(int64_t)i * ldw + w0 + c] : 0u;
+        acc[c] = y[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cw = 0; cw < kBW; ++cw) {
+#pragma unroll 4
+        for (int s = 0; s < 32; ++s) {
+            const uint32_t m = bitmask(y[cw], s);
+            const int k = 32 * cw + s;
+#pragma unroll
+            for (int c = 0; c < kBW; ++c) acc[c] |= m & D[k][c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kBW; ++c)
+        if (row_ok && w0 + c < nw) bits[(int64_t)i * ldw + w0 + c] = acc[c];
+}
+
+// Bulk: 64 rows x 64 words per workgroup (rows outside block b; the words of
+// block b, the column panel, are not written).  Thread (tx, ty) owns rows
+// 4 ty .. 4 ty + 3 and words 4 tx .. 4 tx + 3 of the tile.  The rows of the
+// row panel are staged in LDS 32 k at a time.
+constexpr int kTR = 64, kTW = 64;
+
+__global__ void __launch_bounds__(256)
+bits_bulk_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b, int nrt) {
+    __shared__ uint32_t P[32][kTW];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int k0 = b * kBK, wk0 = b * kBW;
+    // row tiles of block b (rows k0 .. k0 + 255) are skipped
+    const int skip0 = k0 / kTR, nskip = (nrt - skip0) < 4 ? (nrt - skip0) : 4;
+    const int rt = (int)blockIdx.y < skip0 ? (int)blockIdx.y : (int)blockIdx.y + nskip;
+    const int row0 = rt * kTR, col0 = blockIdx.x * kTW;
+
+    uint32_t y[4][kBW], acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = row0 + 4 * ty + r;
+#pragma unroll
+        for (int c = 0; c < kBW; ++c)
+            y[r][c] = (i < n && wk0 + c < nw) ? bits[(int64_t)i * ldw + wk0 + c] : 0u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int w = col0 + 4 * tx + j;
+            acc[r][j] = (i < n && w < nw) ? bits[(int64_t)i * ldw + w] : 0u;
+        }
+    }
+    for (int cw = 0; cw < kBW; ++cw) {
+        // rows k0 + 32 cw .. + 31 of the row panel, the tile's 64 words
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = e * 256 + tid;  // 32 x 64 words
+            const int kr = idx >> 6, wc = idx & 63;
+            const int k = k0 + 32 * cw + kr, w = col0 + wc;
+            P[kr][wc] = (k < n && w < nw) ? bits[(int64_t)k * ldw + w] : 0u;
+        }
+        __syncthreads();
+        uint32_t yw[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            // the word of y holding bits 32 cw .. 32 cw + 31 (register index
+            // chosen by a select chain, not a dynamic index)
+            uint32_t v = y[r][0];
+#pragma unroll
+            for (int c = 1; c < kBW; ++c) v = cw == c ? y[r][c] : v;
+            yw[r] = v;
+        }
+#pragma unroll 4
+        for (int s = 0; s < 32; ++s) {
+            uint32_t p[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) p[j] = P[s][4 * tx + j];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t m = bitmask(yw[r], s);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[r][j] |= m & p[j];
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = row0 + 4 * ty + r;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int w = col0 + 4 * tx + j;
+            if (i < n && w < nw && (w < wk0 || w >= wk0 + kBW)) bits[(int64_t)i * ldw + w] = acc[r][j];
+        }
+    }
+}
+
+// Pack / unpack between an int32 0/1 matrix and the bit layout.
+__global__ void __launch_bounds__(256)
+bits_pack_kernel(const int32_t *__restrict__ adj, int n, int64_t ld, uint32_t *__restrict__ bits,
+                 int64_t ldw, int nw) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)n * nw) return;
+    const int i = (int)(idx / nw), w = (int)(idx - (int64_t)i * nw);
+    uint32_t v = 0;
+    for (int s = 0; s < 32; ++s) {
+        const int j = 32 * w + s;
+        if (j < n && adj[(int64_t)i * ld + j] != 0) v |= 1u << s;
+    }
+    bits[(int64_t)i * ldw + w] = v;
+}
+
+__global__ void __launch_bounds__(256)
+bits_unpack_kernel(const uint32_t *__restrict__ bits, int n, int64_t ldw, int32_t *__restrict__ adj,
+                   int64_t ld) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)n * n) return;
+    const int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
+    adj[(int64_t)i * ld + j] = (int32_t)((bits[(int64_t)i * ldw + (j >> 5)] >> (j & 31)) & 1u);
+}
+
+int status_of(hipError_t e) {
+    if (e == hipSuccess) return FW_OK;
+    if (e == hipErrorOutOfMemory) return FW_ERR_NOMEM;
+    return FW_ERR_HIP;
+}
+
+int64_t words_of(int64_t n) { return (n + 31) / 32; }
+
+// ceil(a / b) blocks of a 1-D launch over `count` items, or -1 if too many
+int64_t blocks_for(int64_t count) {
+    const int64_t g = (count + 255) / 256;
+    return g > 0x7fffffffLL ? -1 : g;
+}
+
+}  // namespace
+}  // namespace fw
+
+using namespace fw;
+
+extern "C" {
+
+int fw_transitive_closure_bits(uint32_t *bits, int64_t n, int64_t ldw, int reflexive,
+                               void *stream) {
+    if (n < 0 || (n > 0 && !bits) || ldw < words_of(n)) return FW_ERR_INVALID;
+    if (n > (1LL << 30) || ldw > (1LL << 40) / (n > 0 ? n : 1)) return FW_ERR_UNSUPPORTED;
+    if (n == 0) return FW_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const int nn = (int)n, nw = (int)words_of(n);
+    if (reflexive) {
+        bits_reflexive_kernel<<<(unsigned)blocks_for(n), 256, 0, st>>>(bits, nn, ldw);
+        if (hipGetLastError() != hipSuccess) return FW_ERR_HIP;
+    }
+    const int nb = (nn + kBK - 1) / kBK;          // k-blocks = row blocks = word blocks
+    const int nrt = (nn + kTR - 1) / kTR;         // bulk row tiles
+    const int nwt = (nw + kTW - 1) / kTW;         // bulk word tiles
+    for (int b = 0; b < nb; ++b) {
+        bits_diag_kernel<<<1, 64, 0, st>>>(bits, nn, ldw, nw, b);
+        if (nb > 1) {
+            bits_row_panel_kernel<<<(unsigned)(nb - 1), 256, 0, st>>>(bits, nn, ldw, nw, b);
+            bits_col_panel_kernel<<<(unsigned)(nb - 1), 256, 0, st>>>(bits, nn, ldw, nw, b);
+            const int skip0 = b * kBK / kTR;
+            const int nskip = (nrt - skip0) < 4 ? (nrt - skip0) : 4;
+            const dim3 grid((unsigned)nwt, (unsigned)(nrt - nskip));
+            bits_bulk_kernel<<<grid, 256, 0, st>>>(bits, nn, ldw, nw, b, nrt);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return status_of(e);
+    }
+    return FW_OK;
+}
+
+int fw_pack_bits(const int32_t *adj, int64_t n, int64_t ld, uint32_t *bits, int64_t ldw,
+                 void *stream) {
+    if (n < 0 || (n > 0 && (!adj || !bits)) || ld < n || ldw < words_of(n))
+        return FW_ERR_INVALID;
+    if (n == 0) return FW_OK;
+    const int64_t g = blocks_for(n * words_of(n));
+    if (n > (1LL << 30) || g < 0) return FW_ERR_UNSUPPORTED;
+    bits_pack_kernel<<<(unsigned)g, 256, 0, (hipStream_t)stream>>>(adj, (int)n, ld, bits, ldw,
+                                                                    (int)words_of(n));
+    return status_of(hipGetLastError());
+}
+
+int fw_unpack_bits(const uint32_t *bits, int64_t n, int64_t ldw, int32_t *adj, int64_t ld,
+                   void *stream) {
+    if (n < 0 || (n > 0 && (!adj || !bits)) || ld < n || ldw < words_of(n))
+        return FW_ERR_INVALID;
+    if (n == 0) return FW_OK;
+    const int64_t g = blocks_for(n * n);
+    if (n > (1LL << 30) || g < 0) return FW_ERR_UNSUPPORTED;
+    bits_unpack_kernel<<<(unsigned)g, 256, 0, (hipStream_t)stream>>>(bits, (int)n, ldw, adj, ld);
+    return status_of(hipGetLastError());
+}
+
+}  // extern "C"

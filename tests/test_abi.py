@@ -56,6 +56,21 @@ def test_argument_validation_without_gpu():
     assert L.fw_apsp_ladder(null, 0, 0, 0, 2, null) == 0                  # empty graph
 
 
+def test_bit_packed_closure_argument_validation():
+    L = B.lib()
+    null = ctypes.c_void_p(0)
+    some = ctypes.c_void_p(16)
+    assert L.fw_transitive_closure_bits(null, 5, 1, 1, null) == 1      # NULL bits
+    assert L.fw_transitive_closure_bits(some, -1, 1, 1, null) == 1     # n < 0
+    assert L.fw_transitive_closure_bits(some, 33, 1, 1, null) == 1     # ldw < 2 words
+    assert L.fw_transitive_closure_bits(null, 0, 0, 1, null) == 0      # empty graph
+    assert L.fw_pack_bits(some, 40, 39, some, 2, null) == 1            # ld < n
+    assert L.fw_pack_bits(some, 40, 40, some, 1, null) == 1            # ldw < 2
+    assert L.fw_unpack_bits(null, 40, 2, some, 40, null) == 1          # NULL bits
+    assert L.fw_unpack_bits(some, 0, 0, null, 0, null) == 0
+    assert B.words_per_row(0) == 0 and B.words_per_row(32) == 1 and B.words_per_row(33) == 2
+
+
 def test_plan_table():
     tiles = B.plan_tiles()
     assert tiles == sorted(tiles) and set(tiles) <= {32, 64, 128, 256}

@@ -1,0 +1,101 @@
+"""Bit-packed reachability (boolean semiring) against the oracle's max-min
+closure over {0, 1}, bit for bit, across block and word boundaries."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1001_4108_amd as fw
+from paper_1001_4108_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def adjacency(n, p, seed):
+    """int32 0/1 adjacency (diagonal 0) of a seeded Bernoulli digraph."""
+    W = gen.dense_graph(n, p, 1, 1, seed=seed, dtype=np.int32)
+    A = np.where(W == gen.I32_INF, 0, 1).astype(np.int32)
+    np.fill_diagonal(A, 0)
+    return A
+
+
+def reference(A, reflexive):
+    B = A.copy()
+    if reflexive:
+        np.fill_diagonal(B, 1)
+    # max-min over {0, 1}: 1 iff a path of edges exists (with diagonal 0: iff
+    # the vertex lies on a cycle)
+    return oracle.fw_maxmin(B)
+
+
+def pack_host(A, ldw):
+    n = A.shape[0]
+    out = np.zeros((n, ldw), dtype=np.uint32)
+    for j in range(n):
+        out[:, j >> 5] |= (A[:, j].astype(np.uint32) & 1) << np.uint32(j & 31)
+    return out.view(np.int32)
+
+
+SIZES = [1, 2, 31, 32, 33, 64, 255, 256, 257, 300, 511, 512, 513, 700, 1025]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("reflexive", [True, False])
+def test_closure_matches_oracle(n, reflexive):
+    # edge probability near the connectivity threshold: long paths, many
+    # unreachable pairs
+    p = min(1.0, 1.5 / max(n, 1))
+    A = adjacency(n, p, seed=n)
+    bits = fw.pack_bits(torch.from_numpy(A).cuda())
+    fw.fw_transitive_closure_bits(bits, n, reflexive=reflexive)
+    got = fw.unpack_bits(bits, n).cpu().numpy()
+    assert np.array_equal(got, reference(A, reflexive)), n
+
+
+@pytest.mark.parametrize("n,p", [(600, 0.002), (1300, 0.001), (2100, 0.0008), (300, 0.05)])
+def test_closure_dense_and_sparse_mixes(n, p):
+    A = adjacency(n, p, seed=7 * n)
+    bits = fw.pack_bits(torch.from_numpy(A).cuda())
+    fw.fw_transitive_closure_bits(bits, n)
+    got = fw.unpack_bits(bits, n).cpu().numpy()
+    assert np.array_equal(got, reference(A, True))
+
+
+def test_padded_rows_and_host_packing():
+    """ldw beyond ceil(n/32): the extra words are neither read nor written;
+    the device packing equals a host packing of the same matrix."""
+    n, extra = 333, 5
+    nw = fw.words_per_row(n)
+    A = adjacency(n, 0.006, seed=3)
+    host = pack_host(A, nw + extra)
+    host[:, nw:] = -12345
+    dev = torch.from_numpy(host).cuda()
+    assert np.array_equal(fw.pack_bits(torch.from_numpy(A).cuda()).cpu().numpy(), host[:, :nw])
+    fw.fw_transitive_closure_bits(dev, n)
+    out = dev.cpu().numpy()
+    assert (out[:, nw:] == -12345).all()
+    R = reference(A, True)
+    assert np.array_equal(out[:, :nw], pack_host(R, nw))
+
+
+def test_int32_entry_point_unchanged_semantics():
+    n = 400
+    W = gen.dense_graph(n, 0.004, 1, 1, seed=5, dtype=np.int32)
+    A = np.where(W == gen.I32_INF, 0, 1).astype(np.int32)
+    d = torch.from_numpy(A).cuda()
+    fw.fw_transitive_closure(d)
+    got = d.cpu().numpy()
+    for s in range(0, n, 9):
+        assert np.array_equal(got[s].astype(bool), oracle.reach_row(W, s))
+    assert set(np.unique(got)) <= {0, 1} and (np.diag(got) == 1).all()
+
+
+def test_large_sampled_rows_against_bfs():
+    n = 8192
+    W = gen.dense_graph(n, 1.2 / n, 1, 1, seed=17, dtype=np.int32)
+    A = np.where(W == gen.I32_INF, 0, 1).astype(np.int32)
+    bits = fw.pack_bits(torch.from_numpy(A).cuda())
+    fw.fw_transitive_closure_bits(bits, n)
+    got = fw.unpack_bits(bits, n).cpu().numpy()
+    for s in (0, 1, 777, 4095, 4096, 8191):
+        assert np.array_equal(got[s].astype(bool), oracle.reach_row(W, s)), s
