@@ -30,9 +30,25 @@ namespace {
 constexpr int kBW = 8;          // words per k-block
 constexpr int kBK = 32 * kBW;   // bits (vertices) per k-block
 
-// all ones where bit t of x is set, else 0
+// all ones where bit t of x is set, else 0 (v_bfe_i32)
 __device__ __forceinline__ uint32_t bitmask(uint32_t x, int t) {
-    return (uint32_t)(-(int32_t)((x >> t) & 1u));
+    return (uint32_t)__builtin_amdgcn_sbfe((int)x, t, 1);
+}
+
+// (m & p) | acc.  With m from v_bfe_i32 the compiler selects one
+// v_and_or_b32 per 32 cells.
+__device__ __forceinline__ uint32_t and_or(uint32_t m, uint32_t p, uint32_t acc) {
+    return (m & p) | acc;
+}
+
+// The same, written out as the instruction for the bulk kernel's unrolled
+// k loop, where the compiler otherwise merges the ORs of two k steps into a
+// v_or3_b32 fed by two v_and_b32 (1.5 instructions per 32 cells instead of
+// 1).  Pure vector ALU on vector registers, no memory access.
+__device__ __forceinline__ uint32_t and_or_v(uint32_t m, uint32_t p, uint32_t acc) {
+    uint32_t d;
+    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(d) : "v"(m), "v"(p), "v"(acc));
+    return d;
 }
 
 // Sets bit (i, i) for every vertex: the reflexive closure.
@@ -76,7 +92,7 @@ bits_diag_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b)
                 for (int gg = 0; gg < 4; ++gg) {
                     const uint32_t m = bitmask(r[gg][c], t);
 #pragma unroll
-                    for (int q = 0; q < kBW; ++q) r[gg][q] |= m & rk[q];
+                    for (int q = 0; q < kBW; ++q) r[gg][q] = and_or(m, rk[q], r[gg][q]);
                 }
             }
         }
@@ -118,7 +134,7 @@ bits_row_panel_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, i
             const uint32_t m = bitmask(dk[cw], s);
             const int k = 32 * cw + s;
 #pragma unroll
-            for (int c = 0; c < kBW; ++c) acc[c] |= m & P[k][c];
+            for (int c = 0; c < kBW; ++c) acc[c] = and_or(m, P[k][c], acc[c]);
         }
     }
 #pragma unroll
@@ -157,7 +173,7 @@ bits_col_panel_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, i
             const uint32_t m = bitmask(y[cw], s);
             const int k = 32 * cw + s;
 #pragma unroll
-            for (int c = 0; c < kBW; ++c) acc[c] |= m & D[k][c];
+            for (int c = 0; c < kBW; ++c) acc[c] = and_or(m, D[k][c], acc[c]);
         }
     }
 #pragma unroll
@@ -165,66 +181,82 @@ bits_col_panel_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, i
         if (row_ok && w0 + c < nw) bits[(int64_t)i * ldw + w0 + c] = acc[c];
 }
 
-// Bulk: 64 rows x 64 words per workgroup (rows outside block b; the words of
-// block b, the column panel, are not written).  Thread (tx, ty) owns rows
-// 4 ty .. 4 ty + 3 and words 4 tx .. 4 tx + 3 of the tile.  The rows of the
-// row panel are staged in LDS 32 k at a time.
-constexpr int kTR = 64, kTW = 64;
+// Bulk: 64 rows x 128 words per workgroup (rows outside block b; the words
+// of block b, the column panel, are not written).  Thread (tx, ty) owns rows
+// 4 ty .. 4 ty + 3 and words 4 tx .. 4 tx + 3 and 64 + 4 tx .. 64 + 4 tx + 3
+// of the tile (two 16-byte LDS reads per k, each contiguous across tx).  The
+// rows of the row panel are staged in LDS 32 k at a time; the next 32 are
+// loaded into registers while the current ones are applied.
+//
+// Loads are unconditional from clamped addresses: a row past n or a word
+// past the last one reads some valid word instead.  Such values only reach
+// accumulators that are never stored (rows past n, words past the last), or
+// row-panel rows past n, whose masks are cleared (bits of vertices >= n are
+// dropped from the column-panel words before use).
+constexpr int kTR = 64, kTW = 128;
 
 __global__ void __launch_bounds__(256)
 bits_bulk_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b, int nrt) {
-    __shared__ uint32_t P[32][kTW];
+    __shared__ __attribute__((aligned(16))) uint32_t P[32][kTW];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     const int k0 = b * kBK, wk0 = b * kBW;
     // row tiles of block b (rows k0 .. k0 + 255) are skipped
     const int skip0 = k0 / kTR, nskip = (nrt - skip0) < 4 ? (nrt - skip0) : 4;
     const int rt = (int)blockIdx.y < skip0 ? (int)blockIdx.y : (int)blockIdx.y + nskip;
     const int row0 = rt * kTR, col0 = blockIdx.x * kTW;
+    auto word_of = [&](int j) { return col0 + (j < 4 ? 4 * tx + j : 64 + 4 * tx + j - 4); };
+    auto clampi = [](int v, int hi) { return v < hi ? v : hi; };
 
-    uint32_t y[4][kBW], acc[4][4];
+    // this thread's rows, clamped
+    const uint32_t *rowp[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = row0 + 4 * ty + r;
+    for (int r = 0; r < 4; ++r) rowp[r] = bits + (int64_t)clampi(row0 + 4 * ty + r, n - 1) * ldw;
+    uint32_t acc[4][8];
 #pragma unroll
-        for (int c = 0; c < kBW; ++c)
-            y[r][c] = (i < n && wk0 + c < nw) ? bits[(int64_t)i * ldw + wk0 + c] : 0u;
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int w = col0 + 4 * tx + j;
-            acc[r][j] = (i < n && w < nw) ? bits[(int64_t)i * ldw + w] : 0u;
-        }
-    }
+        for (int j = 0; j < 8; ++j) acc[r][j] = rowp[r][clampi(word_of(j), nw - 1)];
+
+    // row-panel staging: thread loads word (tid & 127) of rows 2 e + (tid >> 7);
+    // the row is the same across a wave, so its address is scalar work
+    const int wl = tid & (kTW - 1);
+    const int kl = __builtin_amdgcn_readfirstlane(tid >> 7);
+    const int wcl = clampi(col0 + wl, nw - 1);
+    const int klast = n - 1 - k0;  // last valid row of the block, relative
+    uint32_t pf[16], yn[4];
+    auto fetch = [&](int cw) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            pf[e] = bits[(int64_t)(k0 + clampi(32 * cw + 2 * e + kl, klast)) * ldw + wcl];
+        const int wy = clampi(wk0 + cw, nw - 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) yn[r] = rowp[r][wy];
+    };
+    fetch(0);
     for (int cw = 0; cw < kBW; ++cw) {
-        // rows k0 + 32 cw .. + 31 of the row panel, the tile's 64 words
-        __syncthreads();
+        __syncthreads();  // every wave is done with the previous slice
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int idx = e * 256 + tid;  // 32 x 64 words
-            const int kr = idx >> 6, wc = idx & 63;
-            const int k = k0 + 32 * cw + kr, w = col0 + wc;
-            P[kr][wc] = (k < n && w < nw) ? bits[(int64_t)k * ldw + w] : 0u;
-        }
-        __syncthreads();
+        for (int e = 0; e < 16; ++e) P[2 * e + kl][wl] = pf[e];
+        // bits 32 cw .. 32 cw + 31 of block b in the thread's rows (the
+        // column panel, final since the column-panel launch), vertices >= n
+        // dropped
+        const int valid = n - (k0 + 32 * cw);
+        const uint32_t vmask = valid >= 32 ? ~0u : valid <= 0 ? 0u : (1u << valid) - 1u;
         uint32_t yw[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            // the word of y holding bits 32 cw .. 32 cw + 31 (register index
-            // chosen by a select chain, not a dynamic index)
-            uint32_t v = y[r][0];
-#pragma unroll
-            for (int c = 1; c < kBW; ++c) v = cw == c ? y[r][c] : v;
-            yw[r] = v;
-        }
+        for (int r = 0; r < 4; ++r) yw[r] = yn[r] & vmask;
+        __syncthreads();
+        if (cw + 1 < kBW) fetch(cw + 1);
 #pragma unroll 4
         for (int s = 0; s < 32; ++s) {
-            uint32_t p[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) p[j] = P[s][4 * tx + j];
+            const uint4 pa = *reinterpret_cast<const uint4 *>(&P[s][4 * tx]);
+            const uint4 pb = *reinterpret_cast<const uint4 *>(&P[s][64 + 4 * tx]);
+            const uint32_t p[8] = {pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w};
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const uint32_t m = bitmask(yw[r], s);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[r][j] |= m & p[j];
+                for (int j = 0; j < 8; ++j) acc[r][j] = and_or_v(m, p[j], acc[r][j]);
             }
         }
     }
@@ -232,8 +264,8 @@ bits_bulk_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b,
     for (int r = 0; r < 4; ++r) {
         const int i = row0 + 4 * ty + r;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int w = col0 + 4 * tx + j;
+        for (int j = 0; j < 8; ++j) {
+            const int w = word_of(j);
             if (i < n && w < nw && (w < wk0 || w >= wk0 + kBW)) bits[(int64_t)i * ldw + w] = acc[r][j];
         }
     }
