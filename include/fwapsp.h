@@ -149,7 +149,7 @@ int fw_apsp_semiring(void *d, int dtype, int semiring, int64_t n, int64_t ld, vo
  *              first); zero: paths of one edge or more only (i reaches i iff
  *              i lies on a cycle).
  * Stream-ordered.  Errors: FW_ERR_INVALID for bits == NULL with n > 0, n < 0
- * or ldw too small; FW_ERR_UNSUPPORTED for n > 2^30.
+ * or ldw too small; FW_ERR_UNSUPPORTED for n > 2^21 (a 512 GiB matrix).
  */
 int fw_transitive_closure_bits(uint32_t *bits, int64_t n, int64_t ldw, int reflexive,
                                void *stream);

@@ -58,10 +58,62 @@ bits_reflexive_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw) {
     if (i < n) bits[(int64_t)i * ldw + (i >> 5)] |= 1u << (i & 31);
 }
 
-// Stage b's diagonal block by one wave: lane l keeps rows k0 + l + 64 g
-// (g = 0..3), 8 words each, in registers.  Step k: the owner lane's row k is
-// read into scalar registers (v_readlane), and every row whose bit k is set
-// ORs it in.  Row k itself does not change in step k.
+// Warshall's k-ordered steps on a 256 x 256 block held by one wave: lane l
+// keeps rows l + 64 g (g = 0..3), 8 words each, in registers.  Step k: the
+// owner lane's row k is read into scalar registers (v_readlane), and every
+// row whose bit k is set ORs it in.  Row k itself does not change in step k.
+// The steps form one dependent chain, so each step first updates the owner
+// group (the rows that include row k + 1), reads row k + 1 for the next step,
+// and only then updates the other three groups, which hides the readlane
+// latency.  kreal is the number of the block's vertices below n.
+__device__ __forceinline__ void close_block_wave(uint32_t (&r)[4][kBW], int kreal) {
+    uint32_t rk[kBW];
+#pragma unroll
+    for (int q = 0; q < kBW; ++q) rk[q] = (uint32_t)__builtin_amdgcn_readlane((int)r[0][q], 0);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+        for (int cw = 0; cw < 2; ++cw) {
+            const int c = 2 * g + cw;  // the word holding bit k of every row
+            // two steps per iteration, so rk and rn trade registers
+            // instead of being copied
+#pragma unroll 2
+            for (int t = 0; t < 32; ++t) {
+                if (64 * g + 32 * cw + t >= kreal) break;  // uniform
+                {
+                    const uint32_t m = bitmask(r[g][c], t);
+#pragma unroll
+                    for (int q = 0; q < kBW; ++q) r[g][q] = and_or(m, rk[q], r[g][q]);
+                }
+                // row k + 1 while it is in group g (lane 63 is read
+                // harmlessly at the group's last step)
+                const int next = 32 * cw + t + 1 < 63 ? 32 * cw + t + 1 : 63;
+                uint32_t rn[kBW];
+#pragma unroll
+                for (int q = 0; q < kBW; ++q)
+                    rn[q] = (uint32_t)__builtin_amdgcn_readlane((int)r[g][q], next);
+#pragma unroll
+                for (int gg = 0; gg < 4; ++gg) {
+                    if (gg == g) continue;
+                    const uint32_t m = bitmask(r[gg][c], t);
+#pragma unroll
+                    for (int q = 0; q < kBW; ++q) r[gg][q] = and_or(m, rk[q], r[gg][q]);
+                }
+#pragma unroll
+                for (int q = 0; q < kBW; ++q) rk[q] = rn[q];
+            }
+        }
+        // the next group's first row (lane 0), now final for its step
+        if (g + 1 < 4) {
+#pragma unroll
+            for (int q = 0; q < kBW; ++q)
+                rk[q] = (uint32_t)__builtin_amdgcn_readlane((int)r[g + 1][q], 0);
+        }
+    }
+}
+
+// Stage b's diagonal block by one wave (stage 0 only: every later diagonal
+// block is closed inside the previous stage's bulk launch).
 __global__ void __launch_bounds__(64)
 bits_diag_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b) {
     const int l = threadIdx.x;
@@ -74,29 +126,7 @@ bits_diag_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b)
         for (int c = 0; c < kBW; ++c)
             r[g][c] = (i < n && w0 + c < nw) ? bits[(int64_t)i * ldw + w0 + c] : 0u;
     }
-    const int kreal = n - k0 < kBK ? n - k0 : kBK;
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-#pragma unroll
-        for (int cw = 0; cw < 2; ++cw) {
-            const int c = 2 * g + cw;  // the word holding bit k of every row
-#pragma unroll 1
-            for (int t = 0; t < 32; ++t) {
-                if (64 * g + 32 * cw + t >= kreal) break;  // uniform
-                const int owner = 32 * cw + t;
-                uint32_t rk[kBW];
-#pragma unroll
-                for (int q = 0; q < kBW; ++q)
-                    rk[q] = (uint32_t)__builtin_amdgcn_readlane((int)r[g][q], owner);
-#pragma unroll
-                for (int gg = 0; gg < 4; ++gg) {
-                    const uint32_t m = bitmask(r[gg][c], t);
-#pragma unroll
-                    for (int q = 0; q < kBW; ++q) r[gg][q] = and_or(m, rk[q], r[gg][q]);
-                }
-            }
-        }
-    }
+    close_block_wave(r, n - k0 < kBK ? n - k0 : kBK);
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int i = k0 + l + 64 * g;
@@ -106,14 +136,12 @@ bits_diag_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b)
     }
 }
 
-// Row panel: the rows of block b, word block wb != b (blockIdx.x enumerates
-// the other word blocks).  Thread t owns row k0 + t; every row of the block
-// is staged in LDS (old values) before any is written.
-__global__ void __launch_bounds__(256)
-bits_row_panel_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b) {
-    __shared__ uint32_t P[kBK][kBW];
+// Row panel of stage b: the rows of block b, word block wb != b.  Thread t
+// owns row k0 + t; every row of the block is staged in S (old values) before
+// any is written.
+__device__ __forceinline__ void row_panel(uint32_t (*S)[kBW], uint32_t *__restrict__ bits, int n,
+                                          int64_t ldw, int nw, int b, int wb) {
     const int t = threadIdx.x;
-    const int wb = (int)blockIdx.x < b ? (int)blockIdx.x : (int)blockIdx.x + 1;
     const int k0 = b * kBK, w0 = wb * kBW;
     const int i = k0 + t;
     const bool row_ok = i < n;
@@ -123,7 +151,7 @@ bits_row_panel_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, i
         // the thread's row of the closed diagonal block (its masks)
         dk[c] = (row_ok && b * kBW + c < nw) ? bits[(int64_t)i * ldw + b * kBW + c] : 0u;
         acc[c] = (row_ok && w0 + c < nw) ? bits[(int64_t)i * ldw + w0 + c] : 0u;
-        P[t][c] = acc[c];
+        S[t][c] = acc[c];
     }
     __syncthreads();
 #pragma unroll
@@ -134,7 +162,7 @@ bits_row_panel_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, i
             const uint32_t m = bitmask(dk[cw], s);
             const int k = 32 * cw + s;
 #pragma unroll
-            for (int c = 0; c < kBW; ++c) acc[c] = and_or(m, P[k][c], acc[c]);
+            for (int c = 0; c < kBW; ++c) acc[c] = and_or(m, S[k][c], acc[c]);
         }
     }
 #pragma unroll
@@ -142,20 +170,17 @@ bits_row_panel_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, i
         if (row_ok && w0 + c < nw) bits[(int64_t)i * ldw + w0 + c] = acc[c];
 }
 
-// Column panel: word block b of the rows of row block rb != b (blockIdx.x
-// enumerates the other row blocks).  Thread t owns row 256 rb + t; the
-// closed diagonal block is staged in LDS.
-__global__ void __launch_bounds__(256)
-bits_col_panel_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b) {
-    __shared__ uint32_t D[kBK][kBW];
+// Column panel of stage b: word block b of the rows of row block rb != b.
+// Thread t owns row 256 rb + t; the closed diagonal block is staged in S.
+__device__ __forceinline__ void col_panel(uint32_t (*S)[kBW], uint32_t *__restrict__ bits, int n,
+                                          int64_t ldw, int nw, int b, int rb) {
     const int t = threadIdx.x;
-    const int rb = (int)blockIdx.x < b ? (int)blockIdx.x : (int)blockIdx.x + 1;
     const int k0 = b * kBK, w0 = b * kBW;
     {
         const int k = k0 + t;
 #pragma unroll
         for (int c = 0; c < kBW; ++c)
-            D[t][c] = (k < n && w0 + c < nw) ? bits[(int64_t)k * ldw + w0 + c] : 0u;
+            S[t][c] = (k < n && w0 + c < nw) ? bits[(int64_t)k * ldw + w0 + c] : 0u;
     }
     const int i = rb * kBK + t;
     const bool row_ok = i < n;
@@ -173,12 +198,82 @@ bits_col_panel_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, i
             const uint32_t m = bitmask(y[cw], s);
             const int k = 32 * cw + s;
 #pragma unroll
-            for (int c = 0; c < kBW; ++c) acc[c] = and_or(m, D[k][c], acc[c]);
+            for (int c = 0; c < kBW; ++c) acc[c] = and_or(m, S[k][c], acc[c]);
         }
     }
 #pragma unroll
     for (int c = 0; c < kBW; ++c)
         if (row_ok && w0 + c < nw) bits[(int64_t)i * ldw + w0 + c] = acc[c];
+}
+
+// Both panels of stage b in one launch of 2 (nb - 1) workgroups: the first
+// nb - 1 take the row panel's word blocks, the rest the column panel's row
+// blocks.  The two write disjoint words and read only their own words and
+// the closed diagonal block.
+__global__ void __launch_bounds__(256)
+bits_panel_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b, int nb) {
+    __shared__ uint32_t S[kBK][kBW];
+    const int x = (int)blockIdx.x;
+    if (x < nb - 1)
+        row_panel(S, bits, n, ldw, nw, b, x < b ? x : x + 1);
+    else {
+        const int y = x - (nb - 1);
+        col_panel(S, bits, n, ldw, nw, b, y < b ? y : y + 1);
+    }
+}
+
+// Inside the bulk launch of stage b: applies stage b to diagonal block b + 1
+// (X <- X | C x P over the 256 vertices of block b, as every bulk tile does)
+// and closes it, so stage b + 1 needs no diagonal launch.  Block b is full
+// here (it is not the last block).  The bulk tiles leave block b + 1's
+// diagonal words to this workgroup.
+__device__ __forceinline__ void bulk_close_next(uint32_t *L, uint32_t *__restrict__ bits, int n,
+                                                int64_t ldw, int nw, int b) {
+    // This workgroup's waves share their SIMDs with bulk waves, and the
+    // closure is a chain of 256 dependent steps: let them issue first
+    // whenever they are ready.
+    __builtin_amdgcn_s_setprio(3);
+    const int t = threadIdx.x;
+    const int k0 = b * kBK, k1 = k0 + kBK, w0 = b * kBW, w1 = w0 + kBW;
+    const int i = k1 + t;
+    const bool row_ok = i < n;
+    uint32_t(*Pn)[kBW] = reinterpret_cast<uint32_t(*)[kBW]>(L);        // row panel, words of block b+1
+    uint32_t(*X)[kBW] = reinterpret_cast<uint32_t(*)[kBW]>(L + kBK * kBW);  // block b+1 after stage b
+    uint32_t y[kBW], acc[kBW];
+#pragma unroll
+    for (int c = 0; c < kBW; ++c) {
+        Pn[t][c] = (w1 + c < nw) ? bits[(int64_t)(k0 + t) * ldw + w1 + c] : 0u;
+        y[c] = row_ok ? bits[(int64_t)i * ldw + w0 + c] : 0u;
+        acc[c] = (row_ok && w1 + c < nw) ? bits[(int64_t)i * ldw + w1 + c] : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cw = 0; cw < kBW; ++cw) {
+#pragma unroll 4
+        for (int s = 0; s < 32; ++s) {
+            const uint32_t m = bitmask(y[cw], s);
+            const int k = 32 * cw + s;
+#pragma unroll
+            for (int c = 0; c < kBW; ++c) acc[c] = and_or(m, Pn[k][c], acc[c]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kBW; ++c) X[t][c] = acc[c];
+    __syncthreads();
+    if (t >= 64) return;
+    uint32_t r[4][kBW];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int c = 0; c < kBW; ++c) r[g][c] = X[t + 64 * g][c];
+    close_block_wave(r, n - k1 < kBK ? n - k1 : kBK);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int ii = k1 + t + 64 * g;
+#pragma unroll
+        for (int c = 0; c < kBW; ++c)
+            if (ii < n && w1 + c < nw) bits[(int64_t)ii * ldw + w1 + c] = r[g][c];
+    }
 }
 
 // Bulk: 64 rows x 128 words per workgroup (rows outside block b; the words
@@ -196,14 +291,23 @@ bits_col_panel_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, i
 constexpr int kTR = 64, kTW = 128;
 
 __global__ void __launch_bounds__(256)
-bits_bulk_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b, int nrt) {
+bits_bulk_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b, int nrt, int nwt,
+                 int close_next) {
     __shared__ __attribute__((aligned(16))) uint32_t P[32][kTW];
+    if (close_next && blockIdx.x == 0) {  // first, so it starts at once
+        bulk_close_next(&P[0][0], bits, n, ldw, nw, b);
+        return;
+    }
+    const int tile = (int)blockIdx.x - close_next;
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     const int k0 = b * kBK, wk0 = b * kBW;
     // row tiles of block b (rows k0 .. k0 + 255) are skipped
     const int skip0 = k0 / kTR, nskip = (nrt - skip0) < 4 ? (nrt - skip0) : 4;
-    const int rt = (int)blockIdx.y < skip0 ? (int)blockIdx.y : (int)blockIdx.y + nskip;
-    const int row0 = rt * kTR, col0 = blockIdx.x * kTW;
+    const int ty_tile = tile / nwt;
+    const int rt = ty_tile < skip0 ? ty_tile : ty_tile + nskip;
+    const int row0 = rt * kTR, col0 = (tile - ty_tile * nwt) * kTW;
+    // block b + 1's diagonal words, written by the closing workgroup
+    const int k1 = k0 + kBK, wk1 = wk0 + kBW;
     auto word_of = [&](int j) { return col0 + (j < 4 ? 4 * tx + j : 64 + 4 * tx + j - 4); };
     auto clampi = [](int v, int hi) { return v < hi ? v : hi; };
 
@@ -266,7 +370,9 @@ bits_bulk_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b,
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int w = word_of(j);
-            if (i < n && w < nw && (w < wk0 || w >= wk0 + kBW)) bits[(int64_t)i * ldw + w] = acc[r][j];
+            const bool diag1 = close_next && i >= k1 && i < k1 + kBK && w >= wk1 && w < wk1 + kBW;
+            if (i < n && w < nw && (w < wk0 || w >= wk0 + kBW) && !diag1)
+                bits[(int64_t)i * ldw + w] = acc[r][j];
         }
     }
 }
@@ -303,6 +409,8 @@ int status_of(hipError_t e) {
 
 int64_t words_of(int64_t n) { return (n + 31) / 32; }
 
+constexpr int64_t kMaxBitsN = 1LL << 21;
+
 // ceil(a / b) blocks of a 1-D launch over `count` items, or -1 if too many
 int64_t blocks_for(int64_t count) {
     const int64_t g = (count + 255) / 256;
@@ -319,7 +427,8 @@ extern "C" {
 int fw_transitive_closure_bits(uint32_t *bits, int64_t n, int64_t ldw, int reflexive,
                                void *stream) {
     if (n < 0 || (n > 0 && !bits) || ldw < words_of(n)) return FW_ERR_INVALID;
-    if (n > (1LL << 30) || ldw > (1LL << 40) / (n > 0 ? n : 1)) return FW_ERR_UNSUPPORTED;
+    // past 2^21 vertices (a 512 GiB matrix) the bulk grid would overflow
+    if (n > kMaxBitsN || ldw > (1LL << 40) / (n > 0 ? n : 1)) return FW_ERR_UNSUPPORTED;
     if (n == 0) return FW_OK;
     hipStream_t st = (hipStream_t)stream;
     const int nn = (int)n, nw = (int)words_of(n);
@@ -331,14 +440,16 @@ int fw_transitive_closure_bits(uint32_t *bits, int64_t n, int64_t ldw, int refle
     const int nrt = (nn + kTR - 1) / kTR;         // bulk row tiles
     const int nwt = (nw + kTW - 1) / kTW;         // bulk word tiles
     for (int b = 0; b < nb; ++b) {
-        bits_diag_kernel<<<1, 64, 0, st>>>(bits, nn, ldw, nw, b);
+        // later diagonal blocks are closed by the previous bulk launch
+        if (b == 0) bits_diag_kernel<<<1, 64, 0, st>>>(bits, nn, ldw, nw, b);
         if (nb > 1) {
-            bits_row_panel_kernel<<<(unsigned)(nb - 1), 256, 0, st>>>(bits, nn, ldw, nw, b);
-            bits_col_panel_kernel<<<(unsigned)(nb - 1), 256, 0, st>>>(bits, nn, ldw, nw, b);
+            bits_panel_kernel<<<(unsigned)(2 * (nb - 1)), 256, 0, st>>>(bits, nn, ldw, nw, b, nb);
             const int skip0 = b * kBK / kTR;
             const int nskip = (nrt - skip0) < 4 ? (nrt - skip0) : 4;
-            const dim3 grid((unsigned)nwt, (unsigned)(nrt - nskip));
-            bits_bulk_kernel<<<grid, 256, 0, st>>>(bits, nn, ldw, nw, b, nrt);
+            const int close_next = b + 1 < nb ? 1 : 0;
+            const int64_t groups = (int64_t)nwt * (nrt - nskip) + close_next;
+            bits_bulk_kernel<<<(unsigned)groups, 256, 0, st>>>(bits, nn, ldw, nw, b, nrt, nwt,
+                                                               close_next);
         }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return status_of(e);
@@ -352,7 +463,7 @@ int fw_pack_bits(const int32_t *adj, int64_t n, int64_t ld, uint32_t *bits, int6
         return FW_ERR_INVALID;
     if (n == 0) return FW_OK;
     const int64_t g = blocks_for(n * words_of(n));
-    if (n > (1LL << 30) || g < 0) return FW_ERR_UNSUPPORTED;
+    if (n > kMaxBitsN || g < 0) return FW_ERR_UNSUPPORTED;
     bits_pack_kernel<<<(unsigned)g, 256, 0, (hipStream_t)stream>>>(adj, (int)n, ld, bits, ldw,
                                                                     (int)words_of(n));
     return status_of(hipGetLastError());
@@ -364,7 +475,7 @@ int fw_unpack_bits(const uint32_t *bits, int64_t n, int64_t ldw, int32_t *adj, i
         return FW_ERR_INVALID;
     if (n == 0) return FW_OK;
     const int64_t g = blocks_for(n * n);
-    if (n > (1LL << 30) || g < 0) return FW_ERR_UNSUPPORTED;
+    if (n > kMaxBitsN || g < 0) return FW_ERR_UNSUPPORTED;
     bits_unpack_kernel<<<(unsigned)g, 256, 0, (hipStream_t)stream>>>(bits, (int)n, ldw, adj, ld);
     return status_of(hipGetLastError());
 }

@@ -64,6 +64,7 @@ def test_bit_packed_closure_argument_validation():
     assert L.fw_transitive_closure_bits(some, -1, 1, 1, null) == 1     # n < 0
     assert L.fw_transitive_closure_bits(some, 33, 1, 1, null) == 1     # ldw < 2 words
     assert L.fw_transitive_closure_bits(null, 0, 0, 1, null) == 0      # empty graph
+    assert L.fw_transitive_closure_bits(some, (1 << 21) + 1, 1 << 17, 1, null) == 4  # too large
     assert L.fw_pack_bits(some, 40, 39, some, 2, null) == 1            # ld < n
     assert L.fw_pack_bits(some, 40, 40, some, 1, null) == 1            # ldw < 2
     assert L.fw_unpack_bits(null, 40, 2, some, 40, null) == 1          # NULL bits
