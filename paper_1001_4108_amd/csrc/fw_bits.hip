@@ -58,82 +58,91 @@ bits_reflexive_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw) {
     if (i < n) bits[(int64_t)i * ldw + (i >> 5)] |= 1u << (i & 31);
 }
 
-// Warshall's k-ordered steps on a 256 x 256 block held by one wave: lane l
-// keeps rows l + 64 g (g = 0..3), 8 words each, in registers.  Step k: the
-// owner lane's row k is read into scalar registers (v_readlane), and every
-// row whose bit k is set ORs it in.  Row k itself does not change in step k.
-// The steps form one dependent chain, so each step first updates the owner
-// group (the rows that include row k + 1), reads row k + 1 for the next step,
-// and only then updates the other three groups, which hides the readlane
-// latency.  kreal is the number of the block's vertices below n.
-__device__ __forceinline__ void close_block_wave(uint32_t (&r)[4][kBW], int kreal) {
-    uint32_t rk[kBW];
+// Closure of a 256 x 256 diagonal block by a workgroup of 256 threads,
+// thread t holding row t (8 words) in x.  The block is cut into eight
+// 32-vertex sub-blocks K, taken in order (the blocked schedule once more,
+// one level down).  For each K:
+//   1. the wave holding K's 32 rows closes their word of K alone (32
+//      k-ordered steps on one word, row k broadcast by v_readlane): D*;
+//   2. every row i closes its own word of K through D*:
+//      y' = y | OR over k in y of D*[k];
+//   3. every row ORs in the old rows k (all 8 words, staged in LDS before
+//      step 1) selected by y'.
+// Steps 2-3 give exactly the result of the 32 Warshall steps over K: a
+// vertex reached from i through K is reached by a first hop into K followed
+// by a path inside K, whose last vertex's old row holds the target.  (For a
+// row of K, y' is its closed row D*.)  Rows past n hold 0 and stay 0.
+// lds: 32 x 8 + 32 words.  kreal is the number of the block's vertices below n.
+__device__ __forceinline__ void close_block_wg(uint32_t (&x)[kBW], uint32_t *lds, int kreal) {
+    const int t = threadIdx.x, wave = t >> 6;
+    uint32_t(*R)[kBW] = reinterpret_cast<uint32_t(*)[kBW]>(lds);  // old rows of K
+    uint32_t *Dk = lds + 32 * kBW;                                 // D*, word K of K's rows
 #pragma unroll
-    for (int q = 0; q < kBW; ++q) rk[q] = (uint32_t)__builtin_amdgcn_readlane((int)r[0][q], 0);
+    for (int kb = 0; kb < kBW; ++kb) {
+        if (32 * kb >= kreal) break;  // uniform
+        const bool in_k = (t >> 5) == kb;
+        if (in_k) {
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
+            for (int c = 0; c < kBW; ++c) R[t & 31][c] = x[c];
+        }
+        if (wave == (kb >> 1)) {
+            // lanes of the other half compute nothing that is kept
+            const int base = 32 * (kb & 1);
+            const int steps = kreal - 32 * kb;
+            uint32_t d = x[kb];
+            if (steps >= 32) {
 #pragma unroll
-        for (int cw = 0; cw < 2; ++cw) {
-            const int c = 2 * g + cw;  // the word holding bit k of every row
-            // two steps per iteration, so rk and rn trade registers
-            // instead of being copied
-#pragma unroll 2
-            for (int t = 0; t < 32; ++t) {
-                if (64 * g + 32 * cw + t >= kreal) break;  // uniform
-                {
-                    const uint32_t m = bitmask(r[g][c], t);
-#pragma unroll
-                    for (int q = 0; q < kBW; ++q) r[g][q] = and_or(m, rk[q], r[g][q]);
+                for (int s = 0; s < 32; ++s) {
+                    const uint32_t rk = (uint32_t)__builtin_amdgcn_readlane((int)d, base + s);
+                    d = and_or(bitmask(d, s), rk, d);
                 }
-                // row k + 1 while it is in group g (lane 63 is read
-                // harmlessly at the group's last step)
-                const int next = 32 * cw + t + 1 < 63 ? 32 * cw + t + 1 : 63;
-                uint32_t rn[kBW];
-#pragma unroll
-                for (int q = 0; q < kBW; ++q)
-                    rn[q] = (uint32_t)__builtin_amdgcn_readlane((int)r[g][q], next);
-#pragma unroll
-                for (int gg = 0; gg < 4; ++gg) {
-                    if (gg == g) continue;
-                    const uint32_t m = bitmask(r[gg][c], t);
-#pragma unroll
-                    for (int q = 0; q < kBW; ++q) r[gg][q] = and_or(m, rk[q], r[gg][q]);
+            } else {  // the last block's last vertices
+#pragma unroll 1
+                for (int s = 0; s < steps; ++s) {
+                    const uint32_t rk = (uint32_t)__builtin_amdgcn_readlane((int)d, base + s);
+                    d = and_or(bitmask(d, s), rk, d);
                 }
-#pragma unroll
-                for (int q = 0; q < kBW; ++q) rk[q] = rn[q];
             }
+            if (in_k) Dk[t & 31] = d;
         }
-        // the next group's first row (lane 0), now final for its step
-        if (g + 1 < 4) {
-#pragma unroll
-            for (int q = 0; q < kBW; ++q)
-                rk[q] = (uint32_t)__builtin_amdgcn_readlane((int)r[g + 1][q], 0);
+        __syncthreads();
+        const uint32_t y0 = x[kb];
+        uint32_t y = y0;
+#pragma unroll 8
+        for (int s = 0; s < 32; ++s) y = and_or(bitmask(y0, s), Dk[s], y);
+#pragma unroll 4
+        for (int s = 0; s < 32; ++s) {
+            const uint32_t m = bitmask(y, s);
+            const uint4 ra = *reinterpret_cast<const uint4 *>(&R[s][0]);
+            const uint4 rb = *reinterpret_cast<const uint4 *>(&R[s][4]);
+            x[0] = and_or(m, ra.x, x[0]);
+            x[1] = and_or(m, ra.y, x[1]);
+            x[2] = and_or(m, ra.z, x[2]);
+            x[3] = and_or(m, ra.w, x[3]);
+            x[4] = and_or(m, rb.x, x[4]);
+            x[5] = and_or(m, rb.y, x[5]);
+            x[6] = and_or(m, rb.z, x[6]);
+            x[7] = and_or(m, rb.w, x[7]);
         }
+        __syncthreads();  // R and Dk are rewritten for the next K
     }
 }
 
-// Stage b's diagonal block by one wave (stage 0 only: every later diagonal
-// block is closed inside the previous stage's bulk launch).
-__global__ void __launch_bounds__(64)
+// Stage b's diagonal block (stage 0 only: every later diagonal block is
+// closed inside the previous stage's bulk launch).  Thread t owns row k0 + t.
+__global__ void __launch_bounds__(256)
 bits_diag_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b) {
-    const int l = threadIdx.x;
+    __shared__ __attribute__((aligned(16))) uint32_t lds[32 * kBW + 32];
+    const int t = threadIdx.x;
     const int k0 = b * kBK, w0 = b * kBW;
-    uint32_t r[4][kBW];
+    const int i = k0 + t;
+    uint32_t x[kBW];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const int i = k0 + l + 64 * g;
+    for (int c = 0; c < kBW; ++c) x[c] = (i < n && w0 + c < nw) ? bits[(int64_t)i * ldw + w0 + c] : 0u;
+    close_block_wg(x, lds, n - k0 < kBK ? n - k0 : kBK);
 #pragma unroll
-        for (int c = 0; c < kBW; ++c)
-            r[g][c] = (i < n && w0 + c < nw) ? bits[(int64_t)i * ldw + w0 + c] : 0u;
-    }
-    close_block_wave(r, n - k0 < kBK ? n - k0 : kBK);
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const int i = k0 + l + 64 * g;
-#pragma unroll
-        for (int c = 0; c < kBW; ++c)
-            if (i < n && w0 + c < nw) bits[(int64_t)i * ldw + w0 + c] = r[g][c];
-    }
+    for (int c = 0; c < kBW; ++c)
+        if (i < n && w0 + c < nw) bits[(int64_t)i * ldw + w0 + c] = x[c];
 }
 
 // Row panel of stage b: the rows of block b, word block wb != b.  Thread t
@@ -229,16 +238,15 @@ bits_panel_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b
 // diagonal words to this workgroup.
 __device__ __forceinline__ void bulk_close_next(uint32_t *L, uint32_t *__restrict__ bits, int n,
                                                 int64_t ldw, int nw, int b) {
-    // This workgroup's waves share their SIMDs with bulk waves, and the
-    // closure is a chain of 256 dependent steps: let them issue first
-    // whenever they are ready.
+    // This workgroup's waves share their SIMDs with bulk waves, and the next
+    // stage waits for its result: let them issue first whenever they are
+    // ready.
     __builtin_amdgcn_s_setprio(3);
     const int t = threadIdx.x;
     const int k0 = b * kBK, k1 = k0 + kBK, w0 = b * kBW, w1 = w0 + kBW;
     const int i = k1 + t;
     const bool row_ok = i < n;
-    uint32_t(*Pn)[kBW] = reinterpret_cast<uint32_t(*)[kBW]>(L);        // row panel, words of block b+1
-    uint32_t(*X)[kBW] = reinterpret_cast<uint32_t(*)[kBW]>(L + kBK * kBW);  // block b+1 after stage b
+    uint32_t(*Pn)[kBW] = reinterpret_cast<uint32_t(*)[kBW]>(L);  // row panel, words of block b+1
     uint32_t y[kBW], acc[kBW];
 #pragma unroll
     for (int c = 0; c < kBW; ++c) {
@@ -257,23 +265,11 @@ __device__ __forceinline__ void bulk_close_next(uint32_t *L, uint32_t *__restric
             for (int c = 0; c < kBW; ++c) acc[c] = and_or(m, Pn[k][c], acc[c]);
         }
     }
+    __syncthreads();  // Pn is read no more; its space is reused
+    close_block_wg(acc, L, n - k1 < kBK ? n - k1 : kBK);
 #pragma unroll
-    for (int c = 0; c < kBW; ++c) X[t][c] = acc[c];
-    __syncthreads();
-    if (t >= 64) return;
-    uint32_t r[4][kBW];
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-        for (int c = 0; c < kBW; ++c) r[g][c] = X[t + 64 * g][c];
-    close_block_wave(r, n - k1 < kBK ? n - k1 : kBK);
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const int ii = k1 + t + 64 * g;
-#pragma unroll
-        for (int c = 0; c < kBW; ++c)
-            if (ii < n && w1 + c < nw) bits[(int64_t)ii * ldw + w1 + c] = r[g][c];
-    }
+    for (int c = 0; c < kBW; ++c)
+        if (row_ok && w1 + c < nw) bits[(int64_t)i * ldw + w1 + c] = acc[c];
 }
 
 // Bulk: 64 rows x 128 words per workgroup (rows outside block b; the words
@@ -441,7 +437,7 @@ int fw_transitive_closure_bits(uint32_t *bits, int64_t n, int64_t ldw, int refle
     const int nwt = (nw + kTW - 1) / kTW;         // bulk word tiles
     for (int b = 0; b < nb; ++b) {
         // later diagonal blocks are closed by the previous bulk launch
-        if (b == 0) bits_diag_kernel<<<1, 64, 0, st>>>(bits, nn, ldw, nw, b);
+        if (b == 0) bits_diag_kernel<<<1, 256, 0, st>>>(bits, nn, ldw, nw, b);
         if (nb > 1) {
             bits_panel_kernel<<<(unsigned)(2 * (nb - 1)), 256, 0, st>>>(bits, nn, ldw, nw, b, nb);
             const int skip0 = b * kBK / kTR;
