@@ -286,7 +286,7 @@ __device__ __forceinline__ void bulk_close_next(uint32_t *L, uint32_t *__restric
 // dropped from the column-panel words before use).
 constexpr int kTR = 64, kTW = 128;
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 bits_bulk_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b, int nrt, int nwt,
                  int close_next) {
     __shared__ __attribute__((aligned(16))) uint32_t P[32][kTW];
@@ -347,10 +347,17 @@ bits_bulk_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b,
         for (int r = 0; r < 4; ++r) yw[r] = yn[r] & vmask;
         __syncthreads();
         if (cw + 1 < kBW) fetch(cw + 1);
-#pragma unroll 4
+        // the LDS words of step s + 1 are read before step s is applied (the
+        // compiler keeps the written order around the and_or statements)
+        uint4 pa = *reinterpret_cast<const uint4 *>(&P[0][4 * tx]);
+        uint4 pb = *reinterpret_cast<const uint4 *>(&P[0][64 + 4 * tx]);
+#pragma unroll
         for (int s = 0; s < 32; ++s) {
-            const uint4 pa = *reinterpret_cast<const uint4 *>(&P[s][4 * tx]);
-            const uint4 pb = *reinterpret_cast<const uint4 *>(&P[s][64 + 4 * tx]);
+            uint4 na = pa, nb = pb;
+            if (s + 1 < 32) {
+                na = *reinterpret_cast<const uint4 *>(&P[s + 1][4 * tx]);
+                nb = *reinterpret_cast<const uint4 *>(&P[s + 1][64 + 4 * tx]);
+            }
             const uint32_t p[8] = {pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w};
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -358,6 +365,8 @@ bits_bulk_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b,
 #pragma unroll
                 for (int j = 0; j < 8; ++j) acc[r][j] = and_or_v(m, p[j], acc[r][j]);
             }
+            pa = na;
+            pb = nb;
         }
     }
 #pragma unroll
