@@ -165,7 +165,8 @@ def bench_maxmin(torch, fw, W, dev, reps=3):
 def bench_closure(torch, fw, gen, dev, n=16384, reps=5):
     """Reachability (reflexive transitive closure) of an n=16384 digraph with
     edge probability 1.2/n (long paths, many unreachable pairs), bit-packed:
-    the closure timed on resident packed words; the int32 (max, min) closure
+    the closure timed on resident packed words; packing the int32 0/1 matrix
+    and unpacking the result timed once each; the int32 (max, min) closure
     of the same 0/1 matrix timed once beside it; rows checked against BFS."""
     import numpy as np
     import oracle
@@ -174,6 +175,14 @@ def bench_closure(torch, fw, gen, dev, n=16384, reps=5):
     adj = torch.from_numpy(A).to(dev)
     del A
     pristine = fw.pack_bits(adj)
+    torch.cuda.synchronize(dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    pristine = fw.pack_bits(adj)
+    ev1.record()
+    torch.cuda.synchronize(dev)
+    ms_pack = ev0.elapsed_time(ev1)
     bits = pristine.clone()
     fw.fw_transitive_closure_bits(bits, n)
     torch.cuda.synchronize(dev)
@@ -189,7 +198,14 @@ def bench_closure(torch, fw, gen, dev, n=16384, reps=5):
         times.append(ev0.elapsed_time(ev1))
     ms = float(np.median(times))
     srcs = [0, n // 3, n - 1]
-    rows = fw.unpack_bits(bits, n)[torch.tensor(srcs, device=dev)].cpu().numpy()
+    full = torch.empty((n, n), dtype=torch.int32, device=dev)
+    ev0.record()
+    fw.unpack_bits(bits, n, out=full)
+    ev1.record()
+    torch.cuda.synchronize(dev)
+    ms_unpack = ev0.elapsed_time(ev1)
+    rows = full[torch.tensor(srcs, device=dev)].cpu().numpy()
+    del full
     ok = all(np.array_equal(rows[q].astype(bool), oracle.reach_row(W, s)) for q, s in enumerate(srcs))
     # the same closure through the int32 (max, min) semiring, one cell per int
     adj.fill_diagonal_(1)
@@ -204,6 +220,7 @@ def bench_closure(torch, fw, gen, dev, n=16384, reps=5):
                         f"({n} x {fw.words_per_row(n)} words)",
             "ms": ms, "cell_updates_per_s": float(n) ** 3 / (ms / 1e3),
             "int32_maxmin_ms": ms_int, "speedup_vs_int32_maxmin": ms_int / ms,
+            "pack_ms": ms_pack, "unpack_ms": ms_unpack,
             "check": "ok" if ok else "mismatch"}
 
 

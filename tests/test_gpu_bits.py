@@ -99,3 +99,20 @@ def test_large_sampled_rows_against_bfs():
     got = fw.unpack_bits(bits, n).cpu().numpy()
     for s in (0, 1, 777, 4095, 4096, 8191):
         assert np.array_equal(got[s].astype(bool), oracle.reach_row(W, s)), s
+
+
+@pytest.mark.parametrize("n", [1, 31, 32, 33, 63, 64, 65, 100, 333, 1000])
+def test_pack_unpack_against_host(n):
+    """Any non-zero int is an edge; a padded ld is honoured; unpacking gives
+    0 / 1 back; column bits >= n stay 0."""
+    rng = np.random.default_rng(n)
+    ld = n + 3
+    M = np.zeros((n, ld), dtype=np.int32)
+    M[:, :n] = rng.integers(-3, 4, size=(n, n), dtype=np.int32) * (rng.random((n, n)) < 0.3)
+    M[:, n:] = 99  # beyond the row: never read
+    nw = fw.words_per_row(n)
+    dev = torch.from_numpy(M).cuda()
+    bits = fw.pack_bits(dev[:, :n])
+    A01 = (M[:, :n] != 0).astype(np.int32)
+    assert np.array_equal(bits.cpu().numpy(), pack_host(A01, nw))
+    assert np.array_equal(fw.unpack_bits(bits, n).cpu().numpy(), A01)
