@@ -383,40 +383,40 @@ bits_bulk_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b,
 }
 
 // Pack / unpack between an int32 0/1 matrix and the bit layout, one wave per
-// 512 columns of a row (8 coalesced 256-byte accesses per wave).  Pack: each
-// lane reads one int per 64-column chunk and the wave's ballot is the chunk's
-// two words (lanes 0 and 1 store them).  Unpack: each lane writes one int
-// per chunk from the word holding its bit.
+// 512 columns of a row (8 coalesced 256-byte accesses per wave); waves stride
+// over the groups, so the grid stays bounded for any n.  Pack: each lane
+// reads one int per 64-column chunk and the wave's ballot is the chunk's two
+// words (lanes 0 and 1 store them).  Unpack: each lane writes one int per
+// chunk from the word holding its bit.
 constexpr int kPackCols = 512;
+constexpr int64_t kPackMaxBlocks = 1 << 20;
 
-__device__ __forceinline__ bool pack_group(int64_t grp, int n, int &i, int &g) {
-    const int ng = (n + kPackCols - 1) / kPackCols;
-    if (grp >= (int64_t)n * ng) return false;
-    i = (int)(grp / ng);
-    g = (int)(grp - (int64_t)i * ng);
-    return true;
+// the first group of the calling wave (wave-uniform: scalar arithmetic)
+__device__ __forceinline__ int64_t first_group() {
+    return (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
 __global__ void __launch_bounds__(256)
 bits_pack_kernel(const int32_t *__restrict__ adj, int n, int64_t ld, uint32_t *__restrict__ bits,
                  int64_t ldw, int nw) {
     const int lane = threadIdx.x & 63;
-    // the wave's group (wave-uniform: scalar arithmetic)
-    const int64_t grp = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    int i, g;
-    if (!pack_group(grp, n, i, g)) return;  // whole waves
-    const int32_t *row = adj + (int64_t)i * ld;
-    bool e[8];
+    const int ng = (n + kPackCols - 1) / kPackCols;
+    const int64_t groups = (int64_t)n * ng, stride = (int64_t)gridDim.x * 4;
+    for (int64_t grp = first_group(); grp < groups; grp += stride) {
+        const int i = (int)(grp / ng), g = (int)(grp - (int64_t)(grp / ng) * ng);
+        const int32_t *row = adj + (int64_t)i * ld;
+        bool e[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int j = kPackCols * g + 64 * q + lane;
-        e[q] = j < n && row[j] != 0;
-    }
+        for (int q = 0; q < 8; ++q) {
+            const int j = kPackCols * g + 64 * q + lane;
+            e[q] = j < n && row[j] != 0;
+        }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const uint64_t m = __ballot(e[q]);
-        const int w = 16 * g + 2 * q + lane;
-        if (lane < 2 && w < nw) bits[(int64_t)i * ldw + w] = (uint32_t)(m >> (32 * lane));
+        for (int q = 0; q < 8; ++q) {
+            const uint64_t m = __ballot(e[q]);
+            const int w = 16 * g + 2 * q + lane;
+            if (lane < 2 && w < nw) bits[(int64_t)i * ldw + w] = (uint32_t)(m >> (32 * lane));
+        }
     }
 }
 
@@ -424,15 +424,17 @@ __global__ void __launch_bounds__(256)
 bits_unpack_kernel(const uint32_t *__restrict__ bits, int n, int64_t ldw, int32_t *__restrict__ adj,
                    int64_t ld) {
     const int lane = threadIdx.x & 63;
-    const int64_t grp = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    int i, g;
-    if (!pack_group(grp, n, i, g)) return;
-    const uint32_t *brow = bits + (int64_t)i * ldw;
-    int32_t *row = adj + (int64_t)i * ld;
+    const int ng = (n + kPackCols - 1) / kPackCols;
+    const int64_t groups = (int64_t)n * ng, stride = (int64_t)gridDim.x * 4;
+    for (int64_t grp = first_group(); grp < groups; grp += stride) {
+        const int i = (int)(grp / ng), g = (int)(grp - (int64_t)(grp / ng) * ng);
+        const uint32_t *brow = bits + (int64_t)i * ldw;
+        int32_t *row = adj + (int64_t)i * ld;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int j = kPackCols * g + 64 * q + lane;
-        if (j < n) row[j] = (int32_t)((brow[j >> 5] >> (j & 31)) & 1u);
+        for (int q = 0; q < 8; ++q) {
+            const int j = kPackCols * g + 64 * q + lane;
+            if (j < n) row[j] = (int32_t)((brow[j >> 5] >> (j & 31)) & 1u);
+        }
     }
 }
 
@@ -447,8 +449,11 @@ int64_t words_of(int64_t n) { return (n + 31) / 32; }
 constexpr int64_t kMaxBitsN = 1LL << 21;
 
 // workgroups of the pack / unpack launches: four 512-column groups (one per
-// wave) each
-int64_t pack_blocks(int64_t n) { return (n * ((n + kPackCols - 1) / kPackCols) + 3) / 4; }
+// wave) each, at most kPackMaxBlocks (the waves then loop)
+int64_t pack_blocks(int64_t n) {
+    const int64_t g = (n * ((n + kPackCols - 1) / kPackCols) + 3) / 4;
+    return g < kPackMaxBlocks ? g : kPackMaxBlocks;
+}
 
 // ceil(a / b) blocks of a 1-D launch over `count` items, or -1 if too many
 int64_t blocks_for(int64_t count) {
@@ -501,8 +506,8 @@ int fw_pack_bits(const int32_t *adj, int64_t n, int64_t ld, uint32_t *bits, int6
     if (n < 0 || (n > 0 && (!adj || !bits)) || ld < n || ldw < words_of(n))
         return FW_ERR_INVALID;
     if (n == 0) return FW_OK;
+    if (n > kMaxBitsN) return FW_ERR_UNSUPPORTED;
     const int64_t g = pack_blocks(n);
-    if (n > kMaxBitsN || g > 0x7fffffffLL) return FW_ERR_UNSUPPORTED;
     bits_pack_kernel<<<(unsigned)g, 256, 0, (hipStream_t)stream>>>(adj, (int)n, ld, bits, ldw,
                                                                     (int)words_of(n));
     return status_of(hipGetLastError());
@@ -513,8 +518,8 @@ int fw_unpack_bits(const uint32_t *bits, int64_t n, int64_t ldw, int32_t *adj, i
     if (n < 0 || (n > 0 && (!adj || !bits)) || ld < n || ldw < words_of(n))
         return FW_ERR_INVALID;
     if (n == 0) return FW_OK;
+    if (n > kMaxBitsN) return FW_ERR_UNSUPPORTED;
     const int64_t g = pack_blocks(n);
-    if (n > kMaxBitsN || g > 0x7fffffffLL) return FW_ERR_UNSUPPORTED;
     bits_unpack_kernel<<<(unsigned)g, 256, 0, (hipStream_t)stream>>>(bits, (int)n, ldw, adj, ld);
     return status_of(hipGetLastError());
 }
