@@ -52,7 +52,8 @@ def test_closure_matches_oracle(n, reflexive):
     assert np.array_equal(got, reference(A, reflexive)), n
 
 
-@pytest.mark.parametrize("n,p", [(600, 0.002), (1300, 0.001), (2100, 0.0008), (300, 0.05)])
+@pytest.mark.parametrize("n,p", [(600, 0.002), (1300, 0.001), (2100, 0.0008), (300, 0.05),
+                                 (1024, 0.0015), (2048, 0.0007), (1536, 0.01)])
 def test_closure_dense_and_sparse_mixes(n, p):
     A = adjacency(n, p, seed=7 * n)
     bits = fw.pack_bits(torch.from_numpy(A).cuda())
