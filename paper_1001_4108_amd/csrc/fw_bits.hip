@@ -145,89 +145,99 @@ bits_diag_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b)
         if (i < n && w0 + c < nw) bits[(int64_t)i * ldw + w0 + c] = x[c];
 }
 
-// Row panel of stage b: the rows of block b, word block wb != b.  Thread t
-// owns row k0 + t; every row of the block is staged in S (old values) before
-// any is written.
-__device__ __forceinline__ void row_panel(uint32_t (*S)[kBW], uint32_t *__restrict__ bits, int n,
-                                          int64_t ldw, int nw, int b, int wb) {
+// The panels of stage b, each workgroup on kPW of a word block's 8 words:
+// the update of one word depends only on that word's column slice and on
+// the masks, so the 8 words split over kBW / kPW workgroups.  That fills the
+// GPU (8 (nb - 1) workgroups at kPW = 2) and shortens each workgroup's chain
+// of 256 dependent k steps per word.
+constexpr int kPW = 2;
+constexpr int kParts = kBW / kPW;
+
+// Row panel: rows of block b, words w0 .. w0 + kPW - 1 of word block wb != b.
+// Thread t owns row k0 + t; the slice of every row of the block is staged in
+// S (old values) before any is written.
+__device__ __forceinline__ void row_panel(uint32_t (*S)[kPW], uint32_t *__restrict__ bits, int n,
+                                          int64_t ldw, int nw, int b, int w0) {
     const int t = threadIdx.x;
-    const int k0 = b * kBK, w0 = wb * kBW;
+    const int k0 = b * kBK;
     const int i = k0 + t;
     const bool row_ok = i < n;
-    uint32_t dk[kBW], acc[kBW];
+    uint32_t dk[kBW], acc[kPW];
 #pragma unroll
-    for (int c = 0; c < kBW; ++c) {
-        // the thread's row of the closed diagonal block (its masks)
+    for (int c = 0; c < kBW; ++c)  // the thread's row of the closed diagonal block (its masks)
         dk[c] = (row_ok && b * kBW + c < nw) ? bits[(int64_t)i * ldw + b * kBW + c] : 0u;
+#pragma unroll
+    for (int c = 0; c < kPW; ++c) {
         acc[c] = (row_ok && w0 + c < nw) ? bits[(int64_t)i * ldw + w0 + c] : 0u;
         S[t][c] = acc[c];
     }
     __syncthreads();
 #pragma unroll
     for (int cw = 0; cw < kBW; ++cw) {
-        // a full unroll would hoist all 256 rows' LDS reads and spill
-#pragma unroll 4
+#pragma unroll 8
         for (int s = 0; s < 32; ++s) {
             const uint32_t m = bitmask(dk[cw], s);
             const int k = 32 * cw + s;
 #pragma unroll
-            for (int c = 0; c < kBW; ++c) acc[c] = and_or(m, S[k][c], acc[c]);
+            for (int c = 0; c < kPW; ++c) acc[c] = and_or(m, S[k][c], acc[c]);
         }
     }
 #pragma unroll
-    for (int c = 0; c < kBW; ++c)
+    for (int c = 0; c < kPW; ++c)
         if (row_ok && w0 + c < nw) bits[(int64_t)i * ldw + w0 + c] = acc[c];
 }
 
-// Column panel of stage b: word block b of the rows of row block rb != b.
-// Thread t owns row 256 rb + t; the closed diagonal block is staged in S.
-__device__ __forceinline__ void col_panel(uint32_t (*S)[kBW], uint32_t *__restrict__ bits, int n,
-                                          int64_t ldw, int nw, int b, int rb) {
+// Column panel: words w0 .. w0 + kPW - 1 (inside word block b) of the rows of
+// row block rb != b.  Thread t owns row 256 rb + t; its masks are its whole
+// old word block b (the product with the closed block needs no order); the
+// closed diagonal block's slice is staged in S.
+__device__ __forceinline__ void col_panel(uint32_t (*S)[kPW], uint32_t *__restrict__ bits, int n,
+                                          int64_t ldw, int nw, int b, int rb, int w0) {
     const int t = threadIdx.x;
-    const int k0 = b * kBK, w0 = b * kBW;
+    const int k0 = b * kBK, wb0 = b * kBW;
     {
         const int k = k0 + t;
 #pragma unroll
-        for (int c = 0; c < kBW; ++c)
+        for (int c = 0; c < kPW; ++c)
             S[t][c] = (k < n && w0 + c < nw) ? bits[(int64_t)k * ldw + w0 + c] : 0u;
     }
     const int i = rb * kBK + t;
     const bool row_ok = i < n;
-    uint32_t y[kBW], acc[kBW];
+    uint32_t y[kBW], acc[kPW];
 #pragma unroll
-    for (int c = 0; c < kBW; ++c) {
-        y[c] = (row_ok && w0 + c < nw) ? bits[(int64_t)i * ldw + w0 + c] : 0u;
-        acc[c] = y[c];
-    }
+    for (int c = 0; c < kBW; ++c) y[c] = (row_ok && wb0 + c < nw) ? bits[(int64_t)i * ldw + wb0 + c] : 0u;
+#pragma unroll
+    for (int c = 0; c < kPW; ++c) acc[c] = y[w0 - wb0 + c];
     __syncthreads();
 #pragma unroll
     for (int cw = 0; cw < kBW; ++cw) {
-#pragma unroll 4
+#pragma unroll 8
         for (int s = 0; s < 32; ++s) {
             const uint32_t m = bitmask(y[cw], s);
             const int k = 32 * cw + s;
 #pragma unroll
-            for (int c = 0; c < kBW; ++c) acc[c] = and_or(m, S[k][c], acc[c]);
+            for (int c = 0; c < kPW; ++c) acc[c] = and_or(m, S[k][c], acc[c]);
         }
     }
 #pragma unroll
-    for (int c = 0; c < kBW; ++c)
+    for (int c = 0; c < kPW; ++c)
         if (row_ok && w0 + c < nw) bits[(int64_t)i * ldw + w0 + c] = acc[c];
 }
 
-// Both panels of stage b in one launch of 2 (nb - 1) workgroups: the first
-// nb - 1 take the row panel's word blocks, the rest the column panel's row
-// blocks.  The two write disjoint words and read only their own words and
-// the closed diagonal block.
+// Both panels of stage b in one launch of 2 (nb - 1) kParts workgroups: the
+// first half takes the row panel's word blocks, the rest the column panel's
+// row blocks, kParts workgroups per block.  The two panels write disjoint
+// words and read only their own words and the closed diagonal block.
 __global__ void __launch_bounds__(256)
 bits_panel_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b, int nb) {
-    __shared__ uint32_t S[kBK][kBW];
-    const int x = (int)blockIdx.x;
-    if (x < nb - 1)
-        row_panel(S, bits, n, ldw, nw, b, x < b ? x : x + 1);
-    else {
+    __shared__ uint32_t S[kBK][kPW];
+    const int x = (int)blockIdx.x / kParts, part = (int)blockIdx.x % kParts;
+    if (x < nb - 1) {
+        const int wb = x < b ? x : x + 1;
+        row_panel(S, bits, n, ldw, nw, b, wb * kBW + kPW * part);
+    } else {
         const int y = x - (nb - 1);
-        col_panel(S, bits, n, ldw, nw, b, y < b ? y : y + 1);
+        col_panel(S, bits, n, ldw, nw, b, y < b ? y : y + 1, b * kBW + kPW * part);
     }
 }
 
@@ -487,7 +497,8 @@ int fw_transitive_closure_bits(uint32_t *bits, int64_t n, int64_t ldw, int refle
         // later diagonal blocks are closed by the previous bulk launch
         if (b == 0) bits_diag_kernel<<<1, 256, 0, st>>>(bits, nn, ldw, nw, b);
         if (nb > 1) {
-            bits_panel_kernel<<<(unsigned)(2 * (nb - 1)), 256, 0, st>>>(bits, nn, ldw, nw, b, nb);
+            bits_panel_kernel<<<(unsigned)(2 * (nb - 1) * kParts), 256, 0, st>>>(bits, nn, ldw, nw,
+                                                                                b, nb);
             const int skip0 = b * kBK / kTR;
             const int nskip = (nrt - skip0) < 4 ? (nrt - skip0) : 4;
             const int close_next = b + 1 < nb ? 1 : 0;
