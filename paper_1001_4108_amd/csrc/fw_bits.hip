@@ -321,11 +321,14 @@ bits_bulk_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b,
     const uint32_t *rowp[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) rowp[r] = bits + (int64_t)clampi(row0 + 4 * ty + r, n - 1) * ldw;
+    // The accumulators start at 0, the identity of OR; the tile's own words
+    // are loaded during the last slice and ORed in at the end, so the launch
+    // does not start with every workgroup waiting on HBM at once.
     uint32_t acc[4][8];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[r][j] = rowp[r][clampi(word_of(j), nw - 1)];
+        for (int j = 0; j < 8; ++j) acc[r][j] = 0u;
 
     // row-panel staging: thread loads word (tid & 127) of rows 2 e + (tid >> 7);
     // the row is the same across a wave, so its address is scalar work
@@ -342,14 +345,12 @@ bits_bulk_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b,
 #pragma unroll
         for (int r = 0; r < 4; ++r) yn[r] = rowp[r][wy];
     };
-    fetch(0);
-    for (int cw = 0; cw < kBW; ++cw) {
+    auto slice = [&](int cw) {
         __syncthreads();  // every wave is done with the previous slice
 #pragma unroll
         for (int e = 0; e < 16; ++e) P[2 * e + kl][wl] = pf[e];
         // bits 32 cw .. 32 cw + 31 of block b in the thread's rows (the
-        // column panel, final since the column-panel launch), vertices >= n
-        // dropped
+        // column panel, final since the panel launch), vertices >= n dropped
         const int valid = n - (k0 + 32 * cw);
         const uint32_t vmask = valid >= 32 ? ~0u : valid <= 0 ? 0u : (1u << valid) - 1u;
         uint32_t yw[4];
@@ -378,7 +379,19 @@ bits_bulk_kernel(uint32_t *__restrict__ bits, int n, int64_t ldw, int nw, int b,
             pa = na;
             pb = nb;
         }
-    }
+    };
+    fetch(0);
+    for (int cw = 0; cw < kBW - 1; ++cw) slice(cw);
+    uint32_t x[4][8];  // the tile's own words, in flight during the last slice
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[r][j] = rowp[r][clampi(word_of(j), nw - 1)];
+    slice(kBW - 1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[r][j] |= x[r][j];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = row0 + 4 * ty + r;
