@@ -41,15 +41,21 @@ ONE_INSTR_64LANE_PEAK = 256 * 64 * 2.4e9
 
 PROFILE = os.path.join(ROOT, "profiles", "bulk_dma_kernel_f32_t128_n16384.md")
 KERNEL_SOURCES = ("paper_1001_4108_amd/csrc/fw_tiles.h", "paper_1001_4108_amd/csrc/fw_kernels.hip")
+BITS_PROFILE = os.path.join(ROOT, "profiles", "bits_kernels_reachability_n16384.md")
+BITS_SOURCES = ("paper_1001_4108_amd/csrc/fw_bits.hip",)
+# Bit-packed reachability: 32-bit integer VALU issues 64 lanes per clock per
+# CU on gfx950, and the bulk needs 1.125 instructions per 32-cell word-update
+# (one v_and_or_b32, plus one v_bfe_i32 per 8 words)
+BITS_WORD_PEAK = 256 * 64 * 2.4e9 / 1.125
 
 
-def measured_traffic():
-    """HBM bytes per bulk launch from the committed rocprofv3 FETCH_SIZE /
+def measured_traffic(profile=PROFILE, sources=KERNEL_SOURCES):
+    """HBM bytes per bulk launch from a committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary (already scaled by the copy-kernel calibration), or
     None when the kernel sources changed since the counters were taken."""
     import hashlib
     try:
-        text = open(PROFILE).read()
+        text = open(profile).read()
     except OSError:
         return None
     vals = {}
@@ -60,7 +66,7 @@ def measured_traffic():
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if vals.get("kernel_source_sha256") != h.hexdigest():
         return None
@@ -166,8 +172,9 @@ def bench_closure(torch, fw, gen, dev, n=16384, reps=5):
     """Reachability (reflexive transitive closure) of an n=16384 digraph with
     edge probability 1.2/n (long paths, many unreachable pairs), bit-packed:
     the closure timed on resident packed words; packing the int32 0/1 matrix
-    and unpacking the result timed once each; the int32 (max, min) closure
-    of the same 0/1 matrix timed once beside it; rows checked against BFS."""
+    and unpacking the result timed once each; one closure more with phase
+    events for the bulk kernel's roofline; the int32 (max, min) closure of
+    the same 0/1 matrix timed once beside it; rows checked against BFS."""
     import numpy as np
     import oracle
     W = gen.dense_graph(n, 1.2 / n, 1, 1, seed=19, dtype=np.int32)
@@ -206,6 +213,30 @@ def bench_closure(torch, fw, gen, dev, n=16384, reps=5):
     ms_unpack = ev0.elapsed_time(ev1)
     rows = full[torch.tensor(srcs, device=dev)].cpu().numpy()
     del full
+    # one more closure with the library's phase events: the bulk kernel's
+    # average launch time on its own stream, for the roofline
+    fw.profile_read()
+    fw.profile_enable(True)
+    work = pristine.clone()
+    fw.fw_transitive_closure_bits(work, n)
+    torch.cuda.synchronize(dev)
+    prof = fw.profile_read()
+    fw.profile_enable(False)
+    del work
+    bulk_ms, bulk_launches, _ = prof["bits_bulk"]
+    nw = fw.words_per_row(n)
+    kb = min(256, n)
+    words_per_launch = float(n - kb) * (nw - (kb + 31) // 32) * kb  # every stage: one block out
+    avg_us = bulk_ms * 1e3 / max(bulk_launches, 1)
+    achieved = words_per_launch / (avg_us * 1e-6) if avg_us > 0 else 0.0
+    roofline = {"bound": "alu", "kernel": "bits_bulk_kernel (bulk tiles + next diagonal block)",
+                "achieved": achieved / 1e12, "peak": BITS_WORD_PEAK / 1e12,
+                "unit": "T word-updates/s (32 cells each)", "frac": achieved / BITS_WORD_PEAK,
+                "traffic": measured_traffic(BITS_PROFILE, BITS_SOURCES),
+                "traffic_unit": "bytes per bulk launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "avg_launch_us": avg_us, "word_updates_per_launch": words_per_launch,
+                "launches": int(bulk_launches),
+                "phase_ms": {k: prof[k][0] for k in ("bits_diag", "bits_panel", "bits_bulk")}}
     ok = all(np.array_equal(rows[q].astype(bool), oracle.reach_row(W, s)) for q, s in enumerate(srcs))
     # the same closure through the int32 (max, min) semiring, one cell per int
     adj.fill_diagonal_(1)
@@ -220,7 +251,7 @@ def bench_closure(torch, fw, gen, dev, n=16384, reps=5):
                         f"({n} x {fw.words_per_row(n)} words)",
             "ms": ms, "cell_updates_per_s": float(n) ** 3 / (ms / 1e3),
             "int32_maxmin_ms": ms_int, "speedup_vs_int32_maxmin": ms_int / ms,
-            "pack_ms": ms_pack, "unpack_ms": ms_unpack,
+            "pack_ms": ms_pack, "unpack_ms": ms_unpack, "roofline": roofline,
             "check": "ok" if ok else "mismatch"}
 
 

@@ -427,8 +427,10 @@ int fw_graph_cache_clear(void);
  * phase kind, the summed kernel time in ms and the launch count
  * (kinds: 0 = diagonal tile, 1 = panels, 2 = bulk tiles (without the
  * look-ahead part), 3 = predecessor init/fix-up, 4 = batched persistent
- * kernel, 5 = look-ahead part of the bulk); it returns the number of kinds
- * written and clears the accumulators.  While profiling is enabled solves do
+ * kernel, 5 = look-ahead part of the bulk; fw_transitive_closure_bits:
+ * 6 = stage 0's diagonal block, 7 = panels, 8 = bulk with the next diagonal
+ * block); it returns the number of kinds written and clears the
+ * accumulators.  While profiling is enabled solves do
  * not use captured graphs.
  */
 int fw_profile_enable(int on);

@@ -502,7 +502,8 @@ def profile_enable(on: bool = True) -> None:
     lib().fw_profile_enable(1 if on else 0)
 
 
-KINDS = ("diag", "panel", "bulk", "pred", "batched", "bulk_ahead")
+KINDS = ("diag", "panel", "bulk", "pred", "batched", "bulk_ahead", "bits_diag", "bits_panel",
+         "bits_bulk")
 OPTIONS = {"lookahead": 1, "graphs": 2}
 
 
@@ -522,13 +523,14 @@ def graph_cache_clear() -> None:
 
 def profile_read():
     """{kind: (ms, launches, updates)} accumulated since the last read."""
-    ms = (ctypes.c_double * 8)()
-    cnt = (ctypes.c_int64 * 8)()
-    k = lib().fw_profile_read(ms, cnt, 8)
+    cap = len(KINDS)
+    ms = (ctypes.c_double * cap)()
+    cnt = (ctypes.c_int64 * cap)()
+    k = lib().fw_profile_read(ms, cnt, cap)
     if k < 0:
         raise FwError(-k, "fw_profile_read")
-    upd = (ctypes.c_double * 8)()
-    lib().fw_profile_updates(upd, 8)
+    upd = (ctypes.c_double * cap)()
+    lib().fw_profile_updates(upd, cap)
     return {KINDS[i]: (ms[i], cnt[i], upd[i]) for i in range(k)}
 
 

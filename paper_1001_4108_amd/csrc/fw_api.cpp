@@ -463,6 +463,11 @@ int validate_matrix(const void *d, int dtype, int64_t n, int64_t ld, const int32
     return validate(d, dtype, n, ld, pred, ldp);
 }
 
+hipError_t timed_launch(int kind, double updates, hipStream_t st, hipError_t (*launch)(void *),
+                        void *ctx) {
+    return timed(kind, updates, st, [&] { return launch(ctx); });
+}
+
 hipError_t timed_launch_batched(double updates, hipStream_t st, int dtype, bool pred, bool big,
                                 BatchHeader *hdr, const BatchItem *items, int grid) {
     return timed(kBatched, updates, st,

@@ -23,6 +23,7 @@
 #include <cstdint>
 
 #include "../../include/fwapsp.h"
+#include "fw_internal.h"
 
 namespace fw {
 namespace {
@@ -461,6 +462,37 @@ bits_unpack_kernel(const uint32_t *__restrict__ bits, int n, int64_t ldw, int32_
     }
 }
 
+// One stage's launches, each timed as its own phase kind when profiling is on.
+struct BitsStage {
+    uint32_t *bits;
+    int n, nw, b, nb, nrt, nwt, close_next;
+    int64_t ldw;
+    hipStream_t st;
+};
+
+hipError_t run_bits_diag(void *c) {
+    const auto *a = static_cast<const BitsStage *>(c);
+    bits_diag_kernel<<<1, 256, 0, a->st>>>(a->bits, a->n, a->ldw, a->nw, a->b);
+    return hipGetLastError();
+}
+
+hipError_t run_bits_panels(void *c) {
+    const auto *a = static_cast<const BitsStage *>(c);
+    bits_panel_kernel<<<(unsigned)(2 * (a->nb - 1) * kParts), 256, 0, a->st>>>(a->bits, a->n, a->ldw,
+                                                                             a->nw, a->b, a->nb);
+    return hipGetLastError();
+}
+
+hipError_t run_bits_bulk(void *c) {
+    const auto *a = static_cast<const BitsStage *>(c);
+    const int skip0 = a->b * kBK / kTR;
+    const int nskip = (a->nrt - skip0) < 4 ? (a->nrt - skip0) : 4;
+    const int64_t groups = (int64_t)a->nwt * (a->nrt - nskip) + a->close_next;
+    bits_bulk_kernel<<<(unsigned)groups, 256, 0, a->st>>>(a->bits, a->n, a->ldw, a->nw, a->b, a->nrt,
+                                                         a->nwt, a->close_next);
+    return hipGetLastError();
+}
+
 int status_of(hipError_t e) {
     if (e == hipSuccess) return FW_OK;
     if (e == hipErrorOutOfMemory) return FW_ERR_NOMEM;
@@ -507,19 +539,20 @@ int fw_transitive_closure_bits(uint32_t *bits, int64_t n, int64_t ldw, int refle
     const int nrt = (nn + kTR - 1) / kTR;         // bulk row tiles
     const int nwt = (nw + kTW - 1) / kTW;         // bulk word tiles
     for (int b = 0; b < nb; ++b) {
+        // cell updates of each phase (for the profile counters): kb vertices
+        // in block b, the rest of the matrix outside it
+        const double kb = (double)(nn - b * kBK < kBK ? nn - b * kBK : kBK), rest = (double)nn - kb;
+        BitsStage a{bits, nn, nw, b, nb, nrt, nwt, b + 1 < nb ? 1 : 0, ldw, st};
+        hipError_t e = hipSuccess;
         // later diagonal blocks are closed by the previous bulk launch
-        if (b == 0) bits_diag_kernel<<<1, 256, 0, st>>>(bits, nn, ldw, nw, b);
-        if (nb > 1) {
-            bits_panel_kernel<<<(unsigned)(2 * (nb - 1) * kParts), 256, 0, st>>>(bits, nn, ldw, nw,
-                                                                                b, nb);
-            const int skip0 = b * kBK / kTR;
-            const int nskip = (nrt - skip0) < 4 ? (nrt - skip0) : 4;
-            const int close_next = b + 1 < nb ? 1 : 0;
-            const int64_t groups = (int64_t)nwt * (nrt - nskip) + close_next;
-            bits_bulk_kernel<<<(unsigned)groups, 256, 0, st>>>(bits, nn, ldw, nw, b, nrt, nwt,
-                                                               close_next);
+        if (b == 0) e = timed_launch(kBitsDiag, kb * kb * kb, st, run_bits_diag, &a);
+        if (e == hipSuccess && nb > 1) {
+            e = timed_launch(kBitsPanel, 2.0 * rest * kb * kb, st, run_bits_panels, &a);
+            // the bulk launch also closes block b + 1 (kn vertices)
+            const double kn = a.close_next ? (double)(nn - (b + 1) * kBK < kBK ? nn - (b + 1) * kBK : kBK) : 0.0;
+            if (e == hipSuccess)
+                e = timed_launch(kBitsBulk, rest * rest * kb + kn * kn * kn, st, run_bits_bulk, &a);
         }
-        const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return status_of(e);
     }
     return FW_OK;

@@ -17,8 +17,16 @@ enum PhaseKind {
     kPredFix = 3,
     kBatched = 4,
     kBulkAhead = 5, // look-ahead part of the bulk (row and column b+1)
-    kNumKinds = 6
+    kBitsDiag = 6,  // bit-packed reachability: stage 0's diagonal block
+    kBitsPanel = 7, // bit-packed reachability: both panels
+    kBitsBulk = 8,  // bit-packed reachability: the bulk (+ next diagonal block)
+    kNumKinds = 9
 };
+
+// Phase timing for launches made outside the host driver: calls
+// launch(ctx), bracketed by HIP events on st while profiling is enabled.
+hipError_t timed_launch(int kind, double updates, hipStream_t st, hipError_t (*launch)(void *),
+                        void *ctx);
 
 // Closed semirings the sweep runs over.
 enum Semiring { kMinPlus = 0, kMaxMin = 1 };
