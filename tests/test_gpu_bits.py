@@ -91,15 +91,16 @@ def test_int32_entry_point_unchanged_semantics():
     assert set(np.unique(got)) <= {0, 1} and (np.diag(got) == 1).all()
 
 
-def test_large_sampled_rows_against_bfs():
-    n = 8192
+@pytest.mark.parametrize("n", [8192, 8225])
+def test_large_sampled_rows_against_bfs(n):
+    # 8225: a 33-vertex last block and a 2-word last word tile at scale
     W = gen.dense_graph(n, 1.2 / n, 1, 1, seed=17, dtype=np.int32)
     A = np.where(W == gen.I32_INF, 0, 1).astype(np.int32)
     bits = fw.pack_bits(torch.from_numpy(A).cuda())
     fw.fw_transitive_closure_bits(bits, n)
     got = fw.unpack_bits(bits, n).cpu().numpy()
-    for s in (0, 1, 777, 4095, 4096, 8191):
-        assert np.array_equal(got[s].astype(bool), oracle.reach_row(W, s)), s
+    for s in (0, 1, 777, 4095, 4096, 8191, n - 1):
+        assert np.array_equal(got[s].astype(bool), oracle.reach_row(W, s)), (n, s)
 
 
 @pytest.mark.parametrize("n", [1, 31, 32, 33, 63, 64, 65, 100, 333, 1000])
