@@ -44,6 +44,28 @@ def test_profile_traffic_figures_parse():
     assert t is None or abs(t - (fetch + write)) < 1.0
 
 
+def test_bits_profile_traffic_figures_parse(tmp_path):
+    # the bit-packed reachability summary: the same fields, bytes at least the
+    # bulk words read and written once at n=16384; a different source hash
+    # turns the figure off
+    text = open(bench.BITS_PROFILE).read()
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    assert len(fields["kernel_source_sha256"]) == 64
+    fetch = float(fields["bulk_fetch_bytes_per_launch"])
+    write = float(fields["bulk_write_bytes_per_launch"])
+    words = 16128 * 504 * 4
+    assert fetch >= words and write >= words
+    t = bench.measured_traffic(bench.BITS_PROFILE, bench.BITS_SOURCES)
+    assert t is None or abs(t - (fetch + write)) < 1.0
+    stale = tmp_path / "stale.md"
+    stale.write_text(text.replace(fields["kernel_source_sha256"], "0" * 64))
+    assert bench.measured_traffic(str(stale), bench.BITS_SOURCES) is None
+
+
 def test_cpu_baseline_leg_matches_the_oracle_prefix():
     W = gen.dense_graph(96, 0.3, 1, 1000, seed=3)
     out = bench.cpu_baseline(W, 40)
