@@ -180,45 +180,134 @@ void oracle_reach_row(const void *W, int dtype, int64_t n, int64_t ld,
  * the matrix's own precision (fp32 round-to-nearest, or exact int64 for
  * int32), and -1 is written if no p qualifies (which cannot happen for exact
  * shortest-path distances).
+ *
+ * Search order: for each (i, j) the candidates p are tested in increasing
+ * order and the first that qualifies is the minimum of the set above.  The
+ * weights are read through a transposed copy (column j of W as one
+ * contiguous row, its diagonal entry marked absent, since p != j), in chunks
+ * of 64 candidates whose tests are independent of each other.  Reachability
+ * from i is a breadth-first search over the edges, with the adjacency rows
+ * and the visited set held as 64-bit masks.
  */
+static void adjacency_masks(const void *W, int dtype, int64_t ldw, int64_t n,
+                            uint64_t *adj, int64_t nw) {
+    for (int64_t u = 0; u < n; ++u) {
+        uint64_t *row = adj + u * nw;
+        memset(row, 0, (size_t)nw * sizeof(uint64_t));
+        for (int64_t v = 0; v < n; ++v)
+            if (is_edge(W, dtype, ldw, u, v)) row[v >> 6] |= 1ull << (v & 63);
+    }
+}
+
+/* reach[j] = 1 iff j is reachable from src over the edges (reach[src] = 1). */
+static void reach_masks(const uint64_t *adj, int64_t nw, int64_t n, int64_t src,
+                        uint64_t *seen, int64_t *queue, uint8_t *reach) {
+    memset(seen, 0, (size_t)nw * sizeof(uint64_t));
+    int64_t head = 0, tail = 0;
+    seen[src >> 6] |= 1ull << (src & 63);
+    queue[tail++] = src;
+    while (head < tail) {
+        const uint64_t *row = adj + queue[head++] * nw;
+        for (int64_t w = 0; w < nw; ++w) {
+            uint64_t fresh = row[w] & ~seen[w];
+            seen[w] |= fresh;
+            while (fresh) {
+                const int b = __builtin_ctzll(fresh);
+                fresh &= fresh - 1;
+                queue[tail++] = w * 64 + b;
+            }
+        }
+    }
+    for (int64_t v = 0; v < n; ++v) reach[v] = (uint8_t)((seen[v >> 6] >> (v & 63)) & 1);
+}
+
+/* First p in [0, n) with ok[p] and dr[p] + wt[p] == target (fp32 sum), or -1. */
+static int64_t first_hit_f32(const float *dr, const float *wt, const uint8_t *ok, int64_t n,
+                             float target) {
+    for (int64_t p0 = 0; p0 < n; p0 += 64) {
+        const int64_t cnt = n - p0 < 64 ? n - p0 : 64;
+        uint8_t hit[64];
+        for (int64_t q = 0; q < cnt; ++q) {
+            const float w = wt[p0 + q];
+            const float sum = dr[p0 + q] + w;
+            hit[q] = (uint8_t)(ok[p0 + q] & (w != INFINITY) & (sum == target));
+        }
+        for (int64_t q = 0; q < cnt; ++q)
+            if (hit[q]) return p0 + q;
+    }
+    return -1;
+}
+
+/* As first_hit_f32 for int32 weights, the sum exact in int64. */
+static int64_t first_hit_i32(const int32_t *dr, const int32_t *wt, const uint8_t *ok, int64_t n,
+                             int64_t target) {
+    for (int64_t p0 = 0; p0 < n; p0 += 64) {
+        const int64_t cnt = n - p0 < 64 ? n - p0 : 64;
+        uint8_t hit[64];
+        for (int64_t q = 0; q < cnt; ++q) {
+            const int32_t w = wt[p0 + q];
+            const int64_t sum = (int64_t)dr[p0 + q] + (int64_t)w;
+            hit[q] = (uint8_t)(ok[p0 + q] & (w != ORACLE_I32_INF) & (sum == target));
+        }
+        for (int64_t q = 0; q < cnt; ++q)
+            if (hit[q]) return p0 + q;
+    }
+    return -1;
+}
+
 void oracle_canonical_pred_rows(const void *D, int64_t ldd, const void *W,
                                 int64_t ldw, int dtype, int64_t n,
                                 const int64_t *rows, int64_t nrows, int32_t *P,
                                 int64_t ldp, int nthreads) {
     int nt = oracle_threads(nthreads);
+    const int64_t nw = (n + 63) / 64;
+    const size_t nn = (size_t)(n > 0 ? n : 1) * (size_t)(n > 0 ? n : 1);
+    uint64_t *adj = (uint64_t *)malloc((size_t)(n > 0 ? n : 1) * (size_t)(nw > 0 ? nw : 1) *
+                                       sizeof(uint64_t));
+    adjacency_masks(W, dtype, ldw, n, adj, nw);
+    /* wt[j * n + p] = W[p][j]; the diagonal marked absent (p != j) */
+    void *wt = malloc(nn * 4);
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t q = 0; q < n; ++q) {
+            if (dtype == 0)
+                ((float *)wt)[j * n + q] =
+                    q == j ? INFINITY : ((const float *)W)[q * ldw + j];
+            else
+                ((int32_t *)wt)[j * n + q] =
+                    q == j ? ORACLE_I32_INF : ((const int32_t *)W)[q * ldw + j];
+        }
 #pragma omp parallel num_threads(nt)
     {
         uint8_t *reach = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+        uint64_t *seen = (uint64_t *)malloc((size_t)(nw > 0 ? nw : 1) * sizeof(uint64_t));
+        int64_t *queue = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
 #pragma omp for schedule(dynamic, 1)
         for (int64_t r = 0; r < nrows; ++r) {
-            int64_t i = rows[r];
-            oracle_reach_row(W, dtype, n, ldw, i, reach);
+            const int64_t i = rows[r];
+            reach_masks(adj, nw, n, i, seen, queue, reach);
             int32_t *Pr = P + r * ldp;
             for (int64_t j = 0; j < n; ++j) {
-                Pr[j] = -1;
-                if (j == i || !reach[j]) continue;
-                for (int64_t p = 0; p < n; ++p) {
-                    if (!reach[p] || !is_edge(W, dtype, ldw, p, j)) continue;
-                    int hit;
+                int64_t p = -1;
+                if (j != i && reach[j]) {
                     if (dtype == 0) {
                         const float *Dr = (const float *)D + r * ldd;
-                        float s = Dr[p] + ((const float *)W)[p * ldw + j];
-                        hit = (s == Dr[j]);
+                        p = first_hit_f32(Dr, (const float *)wt + j * n, reach, n, Dr[j]);
                     } else {
                         const int32_t *Dr = (const int32_t *)D + r * ldd;
-                        int64_t s = (int64_t)Dr[p] +
-                                    (int64_t)((const int32_t *)W)[p * ldw + j];
-                        hit = (s == (int64_t)Dr[j]);
-                    }
-                    if (hit) {
-                        Pr[j] = (int32_t)p;
-                        break;
+                        p = first_hit_i32(Dr, (const int32_t *)wt + j * n, reach, n,
+                                          (int64_t)Dr[j]);
                     }
                 }
+                Pr[j] = (int32_t)p;
             }
         }
+        free(queue);
+        free(seen);
         free(reach);
     }
+    free(wt);
+    free(adj);
 }
 
 /*
