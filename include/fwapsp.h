@@ -99,7 +99,11 @@ int fw_apsp_i32(int32_t *d, int64_t n, int64_t ld, void *stream);
  *              same for every tile size and batch composition.)  It is computed
  *              during the sweep by a lexicographic minimum over (distance, last
  *              hop) and requires, besides the distance preconditions, that the
- *              graph has no zero-weight cycle.
+ *              graph has no zero-weight cycle.  Outside the problem statement
+ *              (a negative cycle), pred[i*ld_pred+i] keeps the last hop of the
+ *              closed walk that made d_ii negative (see
+ *              fw_negative_cycle_find); the other entries are then as
+ *              computed.
  * Errors: as fw_apsp, plus FW_ERR_INVALID for a bad dtype or, with pred
  * non-NULL, ld_pred < n or n*ld_pred overflowing int64.
  */
@@ -378,12 +382,50 @@ int fw_server_get_stats(fw_server s, fw_server_stats *out);
 int fw_server_destroy(fw_server s);
 
 /*
- * fw_negative_cycle -- after a solve, write 1 to *flag_dev (device int32) if
- * some d_ii < 0 (a negative cycle through i, section 3.1's excluded case),
- * else 0.  Stream-ordered.
+ * fw_negative_cycle -- after a solve, write to *flag_dev (device int32) the
+ * number of vertices i with d_ii < 0 (a negative cycle through i: the case
+ * the problem statement of section 3.1 excludes), 0 when there is none.
+ * Stream-ordered.  Errors: the argument errors of fw_apsp_pred, or
+ * FW_ERR_INVALID for flag_dev == NULL.
  */
 int fw_negative_cycle(const void *d, int dtype, int64_t n, int64_t ld,
                       int32_t *flag_dev, void *stream);
+
+/*
+ * fw_negative_cycle_vertices -- the vertices i with d_ii < 0 after a solve,
+ * in ascending order, written to list_dev[0 .. c-1] (device int32, capacity
+ * n), and c written to *count_dev (device int32).  One workgroup scans the
+ * diagonal.  Stream-ordered.  Errors: the argument errors of fw_apsp_pred, or
+ * FW_ERR_INVALID for count_dev == NULL or list_dev == NULL with n > 0.
+ */
+int fw_negative_cycle_vertices(const void *d, int dtype, int64_t n, int64_t ld,
+                               int32_t *list_dev, int32_t *count_dev, void *stream);
+
+/*
+ * fw_negative_cycle_find -- one negative cycle reachable from vertex v and
+ * back, given v with d_vv < 0 (from fw_negative_cycle_vertices).  Host call;
+ * every pointer is HOST memory.
+ *   w_host     the ORIGINAL weights (n x n, leading dimension ld, fw_dtype
+ *              `dtype`), the matrix before the solve overwrote it.
+ *   pred_host  NULL, or the predecessor matrix of the same solve
+ *              (fw_apsp_pred; ld_pred >= n).  When d_vv < 0 the solve keeps
+ *              P_vv, the last hop of the closed walk that made d_vv negative,
+ *              and the walk back along row v (v <- P_vv <- P_v,P_vv <- ...)
+ *              runs into a cycle of edges.  That cycle is returned if its
+ *              weight over w_host is negative (*from_pred = 1).
+ *   otherwise  (no pred, or the walk's cycle is not negative) Bellman-Ford
+ *              from v over w_host, in-place relaxation, stopping at the
+ *              first pass after which the parent graph holds a cycle (which
+ *              then has negative weight); O(n^2) per pass, at most n + 1
+ *              passes.
+ * Writes the cycle c_0, ..., c_{m-1} (edges c_t -> c_{t+1} and c_{m-1} ->
+ * c_0, weights summed exactly in double) to `cycle` (capacity cap) and
+ * returns m; returns 0 if no negative cycle is reachable from v, and -1 for
+ * invalid arguments or insufficient capacity.  from_pred may be NULL.
+ */
+int64_t fw_negative_cycle_find(const void *w_host, int dtype, int64_t n, int64_t ld,
+                               const int32_t *pred_host, int64_t ld_pred, int64_t v,
+                               int64_t *cycle, int64_t cap, int *from_pred);
 
 /*
  * fw_path -- reconstruct one shortest path from a predecessor matrix that was
@@ -396,42 +438,47 @@ int64_t fw_path(const int32_t *pred_host, int64_t n, int64_t ld_pred, int64_t i,
                 int64_t j, int64_t *path, int64_t cap);
 
 /*
- * Library options (process-wide).  Both are off and cannot be enabled
- * (fw_set_option returns FW_ERR_UNSUPPORTED for a non-zero value):
- * a run that cycled through them ended in a host-side fault whose cause has
- * not been identified.
- *   FW_OPT_LOOKAHEAD: with at least 3 tile rows, split each
- *     stage's bulk so that the next stage's diagonal tile and panels run on a
- *     library-owned side stream while the rest of the bulk runs on the
- *     caller's stream (joined back before the call's last kernel).
- *   FW_OPT_GRAPHS: capture the whole stage loop of a (matrix,
- *     plan) once into a hipGraph and replay it with one graph launch; up to 32
- *     graphs are cached, keyed by device, pointers, n, leading dimensions,
- *     dtype, tile and look-ahead, least recently used evicted.  A graph only
- *     touches the matrix it was captured for, so a later allocation at the
- *     same address with the same shape replays correctly;
- *     fw_graph_cache_clear releases every cached graph.
- * Results are bit-identical for every option setting.  fw_set_option returns
- * FW_OK or FW_ERR_INVALID; fw_get_option returns the value or -1.
+ * Solve plans: the stage loop of section 3.2 for one matrix, captured once
+ * into a hipGraph and replayed by one graph launch per solve.
+ *   fw_solve_plan_create  validates (d, dtype, n, ld, pred, ld_pred) as
+ *                         fw_apsp_pred does and fixes the tile: `tile` (one
+ *                         of fw_plan_tiles()) or 0 for the plan table's
+ *                         choice at creation.  Nothing is enqueued; the
+ *                         matrices must stay allocated for the plan's
+ *                         lifetime and are re-solved in place on every
+ *                         launch.
+ *   fw_solve_plan_launch  mode 0: the solve as eager launches on `stream`
+ *                         (fw_apsp_plan); mode 1: on the first call the
+ *                         launches are captured into a hipGraph on a stream
+ *                         the plan owns (kept, with the graph, until the plan
+ *                         is destroyed; no event is recorded during the
+ *                         capture, so phase timing does not see graph
+ *                         launches), and every call launches that graph on
+ *                         `stream`.  Both modes give bit-identical results.
+ *                         Launches of one plan must not overlap in time.
+ *   fw_solve_plan_tile    the plan's tile (-1 for NULL).
+ *   fw_solve_plan_destroy synchronises the plan's device and frees it.
+ * Errors: FW_ERR_INVALID for bad arguments (NULL plan, bad mode or tile),
+ * FW_ERR_HIP / FW_ERR_NOMEM when capture or instantiation fails.
  */
-#define FW_OPT_LOOKAHEAD 1
-#define FW_OPT_GRAPHS 2
-int fw_set_option(int option, int64_t value);
-int64_t fw_get_option(int option);
-int fw_graph_cache_clear(void);
+typedef struct fw_solve_plan_s *fw_solve_plan;
+int fw_solve_plan_create(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred,
+                         int64_t ld_pred, int tile, fw_solve_plan *out);
+int fw_solve_plan_launch(fw_solve_plan plan, int mode, void *stream);
+int fw_solve_plan_tile(fw_solve_plan plan);
+int fw_solve_plan_destroy(fw_solve_plan plan);
 
 /*
- * Phase timing.  While enabled, every phase launch of the calls above is
- * bracketed by HIP events on its stream (launches run eagerly, not from a
- * captured graph).  fw_profile_read synchronises those events and writes, per
- * phase kind, the summed kernel time in ms and the launch count
- * (kinds: 0 = diagonal tile, 1 = panels, 2 = bulk tiles (without the
- * look-ahead part), 3 = predecessor init/fix-up, 4 = batched persistent
- * kernel, 5 = look-ahead part of the bulk; fw_transitive_closure_bits:
- * 6 = stage 0's diagonal block, 7 = panels, 8 = bulk with the next diagonal
+ * Phase timing.  While enabled, every eager phase launch of the calls above
+ * is bracketed by HIP events on its stream (graph launches of solve plans and
+ * batch plans are not).  fw_profile_read synchronises those events and
+ * writes, per phase kind, the summed kernel time in ms and the launch count
+ * (kinds: 0 = diagonal tile, 1 = panels, 2 = bulk tiles (with the next
+ * diagonal tile where the bulk launch closes it), 3 = predecessor
+ * init/fix-up, 4 = batched persistent kernel; fw_transitive_closure_bits:
+ * 5 = stage 0's diagonal block, 6 = panels, 7 = bulk with the next diagonal
  * block); it returns the number of kinds written and clears the
- * accumulators.  While profiling is enabled solves do
- * not use captured graphs.
+ * accumulators.
  */
 int fw_profile_enable(int on);
 int fw_profile_read(double *ms, int64_t *launches, int cap);

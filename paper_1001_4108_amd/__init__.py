@@ -11,9 +11,12 @@ I32_INF = gen.I32_INF
 
 _EXPORTS = {
     "fw_apsp", "fw_apsp_i32", "fw_apsp_pred", "fw_apsp_plan", "fw_apsp_batched",
-    "fw_negative_cycle", "fw_apsp_semiring", "fw_apsp_ladder", "LADDER_RUNGS", "fw_transitive_closure", "fw_transitive_closure_bits", "pack_bits", "unpack_bits", "words_per_row", "fw_path", "plan_tiles", "plan_tile", "plan_set", "plan_reset", "autotune", "save_plan", "load_plan",
-    "batched_max_n", "BatchPlan", "Server", "profile_enable", "profile_read", "set_option", "get_option",
-    "graph_cache_clear", "FwError", "lib", "LIB_PATH",
+    "fw_negative_cycle", "fw_negative_cycle_vertices", "fw_negative_cycle_find",
+    "fw_apsp_semiring", "fw_apsp_ladder", "LADDER_RUNGS", "fw_transitive_closure",
+    "fw_transitive_closure_bits", "pack_bits", "unpack_bits", "words_per_row", "fw_path",
+    "plan_tiles", "plan_tile", "plan_set", "plan_reset", "autotune", "save_plan", "load_plan",
+    "batched_max_n", "BatchPlan", "SolvePlan", "Server", "profile_enable", "profile_read",
+    "FwError", "lib", "LIB_PATH",
 }
 
 

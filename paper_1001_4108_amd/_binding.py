@@ -101,6 +101,13 @@ def _declare(L):
         "fw_batch_plan_destroy": ([vp], ci),
         "fw_batch_plan_grid": ([vp], i64),
         "fw_negative_cycle": ([vp, ci, i64, i64, vp, vp], ci),
+        "fw_negative_cycle_vertices": ([vp, ci, i64, i64, vp, vp, vp], ci),
+        "fw_negative_cycle_find": ([vp, ci, i64, i64, vp, i64, i64, P64, i64,
+                                    ctypes.POINTER(ci)], i64),
+        "fw_solve_plan_create": ([vp, ci, i64, i64, vp, i64, ci, ctypes.POINTER(vp)], ci),
+        "fw_solve_plan_launch": ([vp, ci, vp], ci),
+        "fw_solve_plan_tile": ([vp], ci),
+        "fw_solve_plan_destroy": ([vp], ci),
         "fw_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)], ci),
         "fw_server_submit": ([vp, vp, i64, i64, vp, i64, ci, P64], ci),
         "fw_server_poll": ([vp, ctypes.POINTER(Completion), ci, i64], ci),
@@ -110,9 +117,6 @@ def _declare(L):
         "fw_server_get_stats": ([vp, ctypes.POINTER(ServerStats)], ci),
         "fw_server_destroy": ([vp], ci),
         "fw_path": ([vp, i64, i64, i64, i64, P64, i64], i64),
-        "fw_set_option": ([ci, i64], ci),
-        "fw_get_option": ([ci], i64),
-        "fw_graph_cache_clear": ([], ci),
         "fw_profile_enable": ([ci], ci),
         "fw_profile_read": ([ctypes.POINTER(ctypes.c_double), P64, ci], ci),
         "fw_profile_updates": ([ctypes.POINTER(ctypes.c_double), ci], ci),
@@ -155,6 +159,16 @@ def _stream(t: torch.Tensor, stream):
     if stream is None:
         stream = torch.cuda.current_stream(t.device)
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _empty_on(stream, device, *shape, dtype=torch.int32):
+    """A new device tensor for work enqueued on ``stream``: allocated while
+    that stream is current, so the caching allocator ties the block to it and
+    does not hand it out again before the stream's work on it is done."""
+    if stream is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    with torch.cuda.stream(stream):
+        return torch.empty(shape, dtype=dtype, device=device)
 
 
 def fw_apsp(d: torch.Tensor, stream=None) -> torch.Tensor:
@@ -266,7 +280,7 @@ def pack_bits(adj: torch.Tensor, stream=None) -> torch.Tensor:
     if adj.dtype != torch.int32:
         raise TypeError("pack_bits takes an int32 0/1 matrix")
     p, n, ld = _matrix(adj, "adj")
-    out = torch.empty((n, words_per_row(n)), dtype=torch.int32, device=adj.device)
+    out = _empty_on(stream, adj.device, n, words_per_row(n))
     with torch.cuda.device(adj.device):
         _check(lib().fw_pack_bits(p, n, ld, out.data_ptr(), words_per_row(n),
                                   _stream(adj, stream)), "fw_pack_bits")
@@ -278,7 +292,7 @@ def unpack_bits(bits: torch.Tensor, n: int, out: torch.Tensor | None = None,
     """The n x n int32 0/1 matrix of a bit-packed one (into ``out`` if given)."""
     bp, ldw = _bits(bits, n, "bits")
     if out is None:
-        out = torch.empty((n, n), dtype=torch.int32, device=bits.device)
+        out = _empty_on(stream, bits.device, n, n)
     if out.dtype != torch.int32:
         raise TypeError("unpack_bits writes an int32 matrix")
     p, m, ld = _matrix(out, "out")
@@ -307,6 +321,8 @@ def fw_transitive_closure(adj: torch.Tensor, stream=None) -> torch.Tensor:
     if adj.dtype != torch.int32:
         raise TypeError("transitive closure takes an int32 0/1 matrix")
     n = adj.shape[0]
+    # the packed temporary is allocated on `stream` (see _empty_on): freed on
+    # return, its block is reused only by later work of that stream
     bits = pack_bits(adj, stream)
     fw_transitive_closure_bits(bits, n, True, stream)
     return unpack_bits(bits, n, adj, stream)
@@ -468,6 +484,50 @@ class BatchPlan:
             pass
 
 
+class SolvePlan:
+    """One matrix's solve (fw_solve_plan_*): ``launch("graph")`` replays the
+    stage loop captured once into a hipGraph, ``launch("eager")`` enqueues the
+    same launches one by one.  The matrices are solved in place on every
+    launch and must outlive the plan."""
+
+    MODES = {"eager": 0, "graph": 1}
+
+    def __init__(self, d: torch.Tensor, pred: torch.Tensor | None = None, tile: int = 0):
+        code = _dtype_code(d)
+        p, n, ld = _matrix(d, "d")
+        pp, pld = _pred_args(d, pred)
+        self.device = d.device
+        self._d, self._pred = d, pred
+        h = ctypes.c_void_p()
+        with torch.cuda.device(d.device):
+            _check(lib().fw_solve_plan_create(p, code, n, ld, pp, pld, int(tile),
+                                              ctypes.byref(h)), "fw_solve_plan_create")
+        self._h = h
+
+    @property
+    def tile(self) -> int:
+        return int(lib().fw_solve_plan_tile(self._h))
+
+    def launch(self, mode: str = "graph", stream=None) -> None:
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        with torch.cuda.device(self.device):
+            _check(lib().fw_solve_plan_launch(self._h, self.MODES[mode], _stream(self._d, stream)),
+                   "fw_solve_plan_launch")
+
+    def destroy(self) -> None:
+        if self._h is not None:
+            with torch.cuda.device(self.device):
+                lib().fw_solve_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
 def batched_max_n(dtype, with_pred: bool = False) -> int:
     code = FW_F32 if dtype in (torch.float32, "f32", FW_F32) else FW_I32
     return int(lib().fw_batched_max_n(code, int(bool(with_pred))))
@@ -477,13 +537,51 @@ def fw_negative_cycle(d: torch.Tensor, stream=None) -> bool:
     """True when some d_ii < 0 after a solve (a negative cycle).  Synchronises."""
     code = _dtype_code(d)
     p, n, ld = _matrix(d, "d")
-    flag = torch.zeros(1, dtype=torch.int32, device=d.device)
+    flag = _empty_on(stream, d.device, 1)
     with torch.cuda.device(d.device):
         s = _stream(d, stream)
         _check(lib().fw_negative_cycle(p, code, n, ld, flag.data_ptr(), s), "fw_negative_cycle")
-    if stream is not None:
-        stream.synchronize()
+    (stream if stream is not None else torch.cuda.current_stream(d.device)).synchronize()
     return bool(flag.item())
+
+
+def fw_negative_cycle_vertices(d: torch.Tensor, stream=None) -> list[int]:
+    """Vertices i with d_ii < 0 after a solve, ascending (device scan).  Synchronises."""
+    code = _dtype_code(d)
+    p, n, ld = _matrix(d, "d")
+    out = _empty_on(stream, d.device, max(n, 1) + 1)
+    with torch.cuda.device(d.device):
+        s = _stream(d, stream)
+        _check(lib().fw_negative_cycle_vertices(p, code, n, ld, out[1:].data_ptr(),
+                                                out.data_ptr(), s),
+               "fw_negative_cycle_vertices")
+    (stream if stream is not None else torch.cuda.current_stream(d.device)).synchronize()
+    host = out.cpu().tolist()
+    return host[1:1 + host[0]]
+
+
+def fw_negative_cycle_find(w_host, v: int, pred_host=None):
+    """One negative cycle through the walk from ``v`` (a vertex with d_vv < 0),
+    from the original host weights ``w_host`` and optionally the solve's host
+    predecessor matrix: ``(cycle, from_pred)`` with cycle = [c_0, ..., c_{m-1}]
+    (edges c_t -> c_t+1 and c_{m-1} -> c_0), or ``([], False)`` if none."""
+    import numpy as np
+    W = np.ascontiguousarray(w_host)
+    code = FW_F32 if W.dtype == np.float32 else FW_I32 if W.dtype == np.int32 else None
+    if code is None:
+        raise TypeError("weights are float32 or int32")
+    n = W.shape[0]
+    pp, pld = None, 0
+    if pred_host is not None:
+        P = np.ascontiguousarray(pred_host, dtype=np.int32)
+        pp, pld = P.ctypes.data, P.strides[0] // 4
+    buf = (ctypes.c_int64 * max(n, 1))()
+    fp = ctypes.c_int(0)
+    m = lib().fw_negative_cycle_find(W.ctypes.data, code, n, W.strides[0] // W.itemsize, pp,
+                                     pld, int(v), buf, max(n, 1), ctypes.byref(fp))
+    if m < 0:
+        raise FwError(1, "fw_negative_cycle_find")
+    return [buf[t] for t in range(m)], bool(fp.value)
 
 
 def fw_path(pred_host, i: int, j: int) -> list[int]:
@@ -502,23 +600,7 @@ def profile_enable(on: bool = True) -> None:
     lib().fw_profile_enable(1 if on else 0)
 
 
-KINDS = ("diag", "panel", "bulk", "pred", "batched", "bulk_ahead", "bits_diag", "bits_panel",
-         "bits_bulk")
-OPTIONS = {"lookahead": 1, "graphs": 2}
-
-
-def set_option(name: str, value) -> None:
-    """Library options: "lookahead" (split bulk, side stream) and "graphs"
-    (cached hipGraph replay of the stage loop); results never change."""
-    _check(lib().fw_set_option(OPTIONS[name], int(value)), "fw_set_option")
-
-
-def get_option(name: str) -> int:
-    return int(lib().fw_get_option(OPTIONS[name]))
-
-
-def graph_cache_clear() -> None:
-    _check(lib().fw_graph_cache_clear(), "fw_graph_cache_clear")
+KINDS = ("diag", "panel", "bulk", "pred", "batched", "bits_diag", "bits_panel", "bits_bulk")
 
 
 def profile_read():

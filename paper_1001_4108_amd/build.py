@@ -4,7 +4,9 @@
 
 Every source under csrc/ is compiled by hipcc for gfx950 and linked into
 paper_1001_4108_amd/libfwapsp.so.  Packed-FP32 instruction selection is
-switched off for the device code (the kernels use scalar fp32 adds).
+switched off for the device code (the kernels use scalar fp32 adds).  The
+vector-ALU issue-rate probe (probe/valu_probe.hip, measurement only) is built
+beside it as libfwprobe.so.
 """
 import os
 import subprocess
@@ -16,6 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 OUT = os.environ.get("FWAPSP_OUT") or os.path.join(HERE, "libfwapsp.so")
 BUILD = os.environ.get("FWAPSP_BUILD_DIR") or os.path.join(ROOT, "_build")
+PROBE_SRC = os.path.join(HERE, "probe", "valu_probe.hip")
+PROBE_OUT = os.path.join(HERE, "libfwprobe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("FWAPSP_ARCH", "gfx950")
 
@@ -59,7 +63,20 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(OUT + ".tmp", OUT)
+    build_probe(verbose)
     return OUT
+
+
+def build_probe(verbose: bool = False) -> str:
+    cmd = [HIPCC, *COMMON, "-shared", PROBE_SRC, "-o", PROBE_OUT + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed on the probe")
+    os.replace(PROBE_OUT + ".tmp", PROBE_OUT)
+    return PROBE_OUT
 
 
 if __name__ == "__main__":

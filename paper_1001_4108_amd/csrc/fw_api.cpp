@@ -9,11 +9,10 @@
 // bracket each launch with HIP events for per-phase timing.
 #include <hip/hip_runtime.h>
 
+#include <math.h>
+
 #include <algorithm>
-#include <atomic>
-#include <map>
 #include <mutex>
-#include <tuple>
 #include <vector>
 
 #include "../../include/fwapsp.h"
@@ -163,281 +162,75 @@ int validate(const void *d, int dtype, int64_t n, int64_t ld, const int32_t *pre
     return FW_OK;
 }
 
-// ---------------------------------------------------------------------------
-// Per-device resources: the look-ahead side stream and a pool of events.
-// ---------------------------------------------------------------------------
-struct DeviceRes {
-    std::mutex mu;                 // serialises eager enqueues that use `side`
-    hipStream_t side = nullptr;
-    std::vector<hipEvent_t> free_events;
-};
-
-std::mutex g_dev_mu;
-std::map<int, DeviceRes *> g_dev;
-
-DeviceRes *device_res() {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    std::lock_guard<std::mutex> lk(g_dev_mu);
-    DeviceRes *&r = g_dev[dev];
-    if (!r) {
-        r = new DeviceRes();
-        if (hipStreamCreateWithFlags(&r->side, hipStreamNonBlocking) != hipSuccess) {
-            delete r;
-            r = nullptr;
-        }
-    }
-    return r;
-}
-
-hipError_t take_events(DeviceRes *r, size_t k, std::vector<hipEvent_t> &out) {
-    std::lock_guard<std::mutex> lk(g_dev_mu);
-    while (out.size() < k) {
-        if (!r->free_events.empty()) {
-            out.push_back(r->free_events.back());
-            r->free_events.pop_back();
-            continue;
-        }
-        hipEvent_t e = nullptr;
-        hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
-        if (err != hipSuccess) return err;
-        out.push_back(e);
-    }
-    return hipSuccess;
-}
-
-// Events may be reused as soon as every wait on them has been enqueued.
-void give_events(DeviceRes *r, std::vector<hipEvent_t> &ev) {
-    std::lock_guard<std::mutex> lk(g_dev_mu);
-    for (auto e : ev) r->free_events.push_back(e);
-    ev.clear();
-}
-
-// Library options (fw_set_option).  Both schedules are switched off: a test
-// that cycled through them ended in a host-side segmentation fault whose cause
-// has not been identified, so they cannot be enabled until it is.
-std::atomic<int> g_opt_lookahead{0};
-std::atomic<int> g_opt_graphs{0};
-constexpr bool kLookaheadAvailable = false;
-constexpr bool kGraphsAvailable = false;
-
-// Enqueue the whole blocked solve of one graph on `st` (and, with
-// look-ahead, on `side`, joined back into `st` before the last bulk).
-// Arguments already validated; n > 1.
-//
-// Look-ahead (nb >= 3): the bulk of stage b is split into the tiles of row
-// and column b+1 ("ahead") and the rest.  The side stream runs ahead(b),
-// then stage b+1's diagonal tile and panels, while `st` runs rest(b); the
-// two touch disjoint tiles.  Dependencies are events: rest(b) waits for the
-// panels of stage b, ahead(b) waits for rest(b-1) (which last wrote row and
-// column b+1).
+// Enqueue the whole blocked solve of one graph on `st`.  Arguments already
+// validated; n > 1.  Per stage: the panels and the bulk; the diagonal tile has
+// its own launch only where the previous bulk launch did not close it.
+// `capturing`: the launches are being recorded into a hipGraph, so no phase
+// events are recorded around them (an event recorded during a capture belongs
+// to that capture and is not reused outside it).
 int enqueue_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
-                  hipStream_t st, hipStream_t side, bool lookahead, std::vector<hipEvent_t> &evs,
-                  int sr = kMinPlus) {
+                  hipStream_t st, bool capturing, int sr = kMinPlus) {
     const int nb = (n + tile - 1) / tile;
     hipError_t e;
+    auto run = [&](int kind, double upd, auto &&launch) -> hipError_t {
+        if (capturing) return launch();
+        return timed(kind, upd, st, launch);
+    };
     if (pred) {
-        e = timed(kPredFix, 0.0, st, [&] { return launch_pred_init(dtype, d, pred, n, ld, ldp, st); });
+        e = run(kPredFix, 0.0, [&] { return launch_pred_init(dtype, d, pred, n, ld, ldp, st); });
         if (e != hipSuccess) return status_of(e);
     }
     // algorithmic updates of each launch: the n^3 tasks split by where the
     // (i, j) cell lies relative to block b (real cells only, padding excluded)
     const double nn = (double)n;
     auto real = [&](int blk) { return std::max(0.0, std::min<double>(tile, nn - (double)blk * tile)); };
-    auto diag = [&](int b, hipStream_t s) {
+    bool closed = false;  // the previous bulk launch closed this stage's diagonal tile
+    for (int b = 0; b < nb; ++b) {
         const double kb = real(b);
-        return timed(kDiag, kb * kb * kb, s,
-                     [&] { return launch_diag(dtype, sr, tile, d, pred, n, ld, ldp, b, s); });
-    };
-    auto panels = [&](int b, hipStream_t s) {
-        const double kb = real(b);
-        return timed(kPanel, 2.0 * kb * kb * (nn - kb), s, [&] {
-            return launch_panels(dtype, sr, tile, d, pred, n, ld, ldp, b, nb, s);
+        if (!closed) {
+            e = run(kDiag, kb * kb * kb,
+                    [&] { return launch_diag(dtype, sr, tile, d, pred, n, ld, ldp, b, st); });
+            if (e != hipSuccess) return status_of(e);
+        }
+        closed = false;
+        if (nb == 1) break;
+        e = run(kPanel, 2.0 * kb * kb * (nn - kb), [&] {
+            return launch_panels(dtype, sr, tile, d, pred, n, ld, ldp, b, nb, st);
         });
-    };
-    // close_next: the launch also closes the next diagonal tile (its updates
-    // are counted with the bulk's, the launch that does them)
-    auto bulk = [&](int b, int part, hipStream_t s, bool close_next = false) {
-        const double kb = real(b), r1 = real(b + 1), rest = nn - kb;
-        double upd = kb * rest * rest;
-        int kind = kBulk;
-        if (part == kBulkAheadPart) {
-            upd = kb * (r1 * rest + (rest - r1) * r1);
-            kind = kBulkAhead;
-        } else if (part == kBulkRestPart) {
-            upd = kb * (rest - r1) * (rest - r1);
-        }
-        if (close_next) upd += r1 * r1 * r1;
-        return timed(kind, upd, s, [&] {
-            return launch_bulk(dtype, sr, tile, d, pred, n, ld, ldp, b, nb, part, close_next, s);
+        if (e != hipSuccess) return status_of(e);
+        // close_next: the bulk launch also closes the next diagonal tile (its
+        // updates are counted with the bulk's, the launch that does them)
+        const bool close_next = bulk_closes_next_diag(sr, tile, d, pred, n, ld, b);
+        const double r1 = real(b + 1), rest = nn - kb;
+        const double upd = kb * rest * rest + (close_next ? r1 * r1 * r1 : 0.0);
+        e = run(kBulk, upd, [&] {
+            return launch_bulk(dtype, sr, tile, d, pred, n, ld, ldp, b, nb, close_next, st);
         });
-    };
-
-    if (!lookahead || nb < 3) {
-        bool closed = false;  // the previous bulk launch closed this stage's diagonal tile
-        for (int b = 0; b < nb; ++b) {
-            if (!closed && (e = diag(b, st)) != hipSuccess) return status_of(e);
-            closed = false;
-            if (nb > 1) {
-                if ((e = panels(b, st)) != hipSuccess) return status_of(e);
-                closed = bulk_closes_next_diag(sr, tile, d, pred, n, ld, b);
-                if ((e = bulk(b, kBulkAll, st, closed)) != hipSuccess) return status_of(e);
-            }
-        }
-    } else {
-        size_t ei = 0;
-        if ((e = diag(0, st)) != hipSuccess) return status_of(e);
-        if ((e = panels(0, st)) != hipSuccess) return status_of(e);
-        hipEvent_t ev_panels = evs[ei++];  // panels of the current stage are done
-        hipEvent_t ev_rest = nullptr;      // rest of the previous stage's bulk is done
-        if ((e = hipEventRecord(ev_panels, st)) != hipSuccess) return status_of(e);
-        for (int b = 0; b < nb; ++b) {
-            if (b == nb - 1) {
-                if ((e = hipStreamWaitEvent(st, ev_panels, 0)) != hipSuccess) return status_of(e);
-                if ((e = bulk(b, kBulkAll, st)) != hipSuccess) return status_of(e);
-                break;
-            }
-            if ((e = hipStreamWaitEvent(side, ev_panels, 0)) != hipSuccess) return status_of(e);
-            if (ev_rest && (e = hipStreamWaitEvent(side, ev_rest, 0)) != hipSuccess)
-                return status_of(e);
-            if ((e = bulk(b, kBulkAheadPart, side)) != hipSuccess) return status_of(e);
-            if ((e = diag(b + 1, side)) != hipSuccess) return status_of(e);
-            if ((e = panels(b + 1, side)) != hipSuccess) return status_of(e);
-            hipEvent_t ev_next = evs[ei++];
-            if ((e = hipEventRecord(ev_next, side)) != hipSuccess) return status_of(e);
-            if ((e = hipStreamWaitEvent(st, ev_panels, 0)) != hipSuccess) return status_of(e);
-            if (nb > 2 && (e = bulk(b, kBulkRestPart, st)) != hipSuccess) return status_of(e);
-            ev_rest = evs[ei++];
-            if ((e = hipEventRecord(ev_rest, st)) != hipSuccess) return status_of(e);
-            ev_panels = ev_next;
-        }
+        if (e != hipSuccess) return status_of(e);
+        closed = close_next;
     }
     if (pred) {
-        e = timed(kPredFix, 0.0, st, [&] { return launch_pred_fix(dtype, d, pred, n, ld, ldp, st); });
+        e = run(kPredFix, 0.0, [&] { return launch_pred_fix(dtype, d, pred, n, ld, ldp, st); });
         if (e != hipSuccess) return status_of(e);
     }
     return FW_OK;
 }
 
-// ---------------------------------------------------------------------------
-// Graph cache: the whole stage loop of one (matrix, plan) captured once and
-// replayed with a single graph launch.
-// ---------------------------------------------------------------------------
-struct GraphKey {
-    int dev, dtype, n, tile, lookahead;
-    int64_t ld, ldp;
-    void *d;
-    int32_t *pred;
-    bool operator<(const GraphKey &o) const {
-        return std::tie(dev, dtype, n, tile, lookahead, ld, ldp, d, pred) <
-               std::tie(o.dev, o.dtype, o.n, o.tile, o.lookahead, o.ld, o.ldp, o.d, o.pred);
-    }
-};
-struct GraphEntry {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    uint64_t last_use = 0;
-};
-std::mutex g_graph_mu;
-std::map<GraphKey, GraphEntry> g_graphs;
-uint64_t g_graph_clock = 0;
-constexpr size_t kMaxGraphs = 32;
-
-int capture_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
-                  bool lookahead, DeviceRes *res, GraphEntry &out) {
-    hipStream_t cs = nullptr, cside = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cside, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        if (cs) hipStreamDestroy(cs);
-        return status_of(e);
-    }
-    const int nb = (n + tile - 1) / tile;
-    std::vector<hipEvent_t> evs;
-    int s = status_of(take_events(res, 2 * (size_t)nb + 2, evs));
-    hipGraph_t g = nullptr;
-    if (s == FW_OK) {
-        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) {
-            s = status_of(e);
-        } else {
-            s = enqueue_solve(d, dtype, n, ld, pred, ldp, tile, cs, cside, lookahead, evs);
-            e = hipStreamEndCapture(cs, &g);
-            if (s == FW_OK && e != hipSuccess) s = status_of(e);
-        }
-    }
-    if (s == FW_OK) {
-        e = hipGraphInstantiate(&out.exec, g, nullptr, nullptr, 0);
-        if (e != hipSuccess) s = status_of(e);
-    }
-    if (s == FW_OK) {
-        out.graph = g;
-    } else if (g) {
-        hipGraphDestroy(g);
-    }
-    give_events(res, evs);
-    hipStreamDestroy(cside);
-    hipStreamDestroy(cs);
-    return s;
-}
-
-bool profiling_on() {
-    std::lock_guard<std::mutex> lk(g_prof_mu);
-    return g_prof_on;
-}
-
 // Enqueue the whole solve for one graph.  Arguments already valid.
 int solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
-          hipStream_t st, bool allow_graph = true, int sr = kMinPlus) {
+          hipStream_t st, bool capturing = false, int sr = kMinPlus) {
     if (n <= 1) {
         if (pred && n == 1) {
-            hipError_t e = timed(kPredFix, 0.0, st, [&] {
-                return launch_pred_fix(dtype, d, pred, n, ld, ldp, st);
-            });
+            hipError_t e = capturing ? launch_pred_fix(dtype, d, pred, n, ld, ldp, st)
+                                     : timed(kPredFix, 0.0, st, [&] {
+                                           return launch_pred_fix(dtype, d, pred, n, ld, ldp, st);
+                                       });
             return status_of(e);
         }
         return FW_OK;
     }
     if (!tile_supported(tile)) return FW_ERR_INVALID;
-    const bool lookahead = g_opt_lookahead.load() != 0;
-    const bool graphs = allow_graph && g_opt_graphs.load() && !profiling_on();
-    if ((!lookahead && !graphs) || sr != kMinPlus) {
-        // plain schedule on the caller's stream: no side stream, no events
-        std::vector<hipEvent_t> none;
-        return enqueue_solve(d, dtype, n, ld, pred, ldp, tile, st, nullptr, false, none, sr);
-    }
-    DeviceRes *res = device_res();
-    if (!res) return FW_ERR_HIP;
-    if (graphs) {
-        int dev = 0;
-        hipGetDevice(&dev);
-        GraphKey key{dev, dtype, n, tile, lookahead ? 1 : 0, ld, ldp, d, pred};
-        std::lock_guard<std::mutex> lk(g_graph_mu);
-        auto it = g_graphs.find(key);
-        if (it == g_graphs.end()) {
-            if (g_graphs.size() >= kMaxGraphs) {
-                auto victim = g_graphs.begin();
-                for (auto jt = g_graphs.begin(); jt != g_graphs.end(); ++jt)
-                    if (jt->second.last_use < victim->second.last_use) victim = jt;
-                hipGraphExecDestroy(victim->second.exec);
-                hipGraphDestroy(victim->second.graph);
-                g_graphs.erase(victim);
-            }
-            GraphEntry ent;
-            int s = capture_solve(d, dtype, n, ld, pred, ldp, tile, lookahead, res, ent);
-            if (s != FW_OK) return s;
-            it = g_graphs.emplace(key, ent).first;
-        }
-        it->second.last_use = ++g_graph_clock;
-        return status_of(hipGraphLaunch(it->second.exec, st));
-    }
-    std::lock_guard<std::mutex> lk(res->mu);
-    std::vector<hipEvent_t> evs;
-    const int nb = (n + tile - 1) / tile;
-    int s = status_of(take_events(res, 2 * (size_t)nb + 2, evs));
-    if (s == FW_OK) s = enqueue_solve(d, dtype, n, ld, pred, ldp, tile, st, res->side, lookahead, evs);
-    give_events(res, evs);
-    return s;
+    return enqueue_solve(d, dtype, n, ld, pred, ldp, tile, st, capturing, sr);
 }
 
 }  // namespace
@@ -448,14 +241,12 @@ int plan_tile_for(int dtype, int64_t n, bool pred) {
 
 int solve_single(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64_t ldp,
                  hipStream_t st) {
-    // eager launches: callers (the per-graph batch baseline, the server) solve
-    // many different matrices, which a graph cache would only churn
-    return solve(d, dtype, (int)n, ld, pred, ldp, plan_tile(plan_key(dtype, pred), n), st, false);
+    return solve(d, dtype, (int)n, ld, pred, ldp, plan_tile(plan_key(dtype, pred), n), st);
 }
 
 int solve_with_tile(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
                     hipStream_t st) {
-    return solve(d, dtype, n, ld, pred, ldp, tile, st, false);
+    return solve(d, dtype, n, ld, pred, ldp, tile, st);
 }
 
 int validate_matrix(const void *d, int dtype, int64_t n, int64_t ld, const int32_t *pred,
@@ -563,7 +354,144 @@ int fw_negative_cycle(const void *d, int dtype, int64_t n, int64_t ld, int32_t *
     int s = validate(d, dtype, n, ld, nullptr, 0);
     if (s != FW_OK) return s;
     if (!flag_dev) return FW_ERR_INVALID;
-    return status_of(launch_negcycle(dtype, d, (int)n, ld, flag_dev, (hipStream_t)stream));
+    return status_of(
+        launch_negcycle(dtype, d, (int)n, ld, nullptr, flag_dev, (hipStream_t)stream));
+}
+
+int fw_negative_cycle_vertices(const void *d, int dtype, int64_t n, int64_t ld,
+                               int32_t *list_dev, int32_t *count_dev, void *stream) {
+    int s = validate(d, dtype, n, ld, nullptr, 0);
+    if (s != FW_OK) return s;
+    if (!count_dev || (n > 0 && !list_dev)) return FW_ERR_INVALID;
+    return status_of(
+        launch_negcycle(dtype, d, (int)n, ld, list_dev, count_dev, (hipStream_t)stream));
+}
+
+}  // extern "C"
+
+namespace {
+
+// Weight of the edge p -> q of a host weight matrix as a double (exact for
+// int32 and for fp32), or +INF when there is no such edge (absent entry or
+// the diagonal).
+double edge_weight(const void *w, int dtype, int64_t ld, int64_t p, int64_t q) {
+    if (p == q) return HUGE_VAL;
+    if (dtype == FW_F32) {
+        const float x = static_cast<const float *>(w)[p * ld + q];
+        return x == HUGE_VALF ? HUGE_VAL : (double)x;
+    }
+    const int32_t x = static_cast<const int32_t *>(w)[p * ld + q];
+    return x == FW_I32_INF ? HUGE_VAL : (double)x;
+}
+
+// Weight of the closed walk cyc[0] -> cyc[1] -> ... -> cyc[m-1] -> cyc[0]
+// (+INF if some hop is not an edge).
+double cycle_weight(const void *w, int dtype, int64_t ld, const int64_t *cyc, int64_t m) {
+    double sum = 0.0;
+    for (int64_t t = 0; t < m; ++t) {
+        const double e = edge_weight(w, dtype, ld, cyc[t], cyc[(t + 1) % m]);
+        if (e == HUGE_VAL) return HUGE_VAL;
+        sum += e;
+    }
+    return sum;
+}
+
+// The cycle that a chain of last hops x_{t+1} = hop(x_t) runs into, in
+// forward edge order (each hop(x) -> x is an edge): written to `out`, its
+// length returned; 0 when the chain ends (hop < 0) before repeating.
+template <typename Hop>
+int64_t chain_cycle(int64_t n, int64_t start, Hop hop, std::vector<int64_t> &out) {
+    std::vector<int64_t> pos((size_t)n, -1), seq;
+    int64_t cur = start;
+    pos[(size_t)cur] = 0;
+    seq.push_back(cur);
+    while (true) {
+        const int64_t p = hop(cur);
+        if (p < 0 || p >= n) return 0;
+        if (pos[(size_t)p] >= 0) {
+            // x_a = p, ..., x_t = cur: edges x_{u+1} -> x_u and p -> cur
+            const int64_t a = pos[(size_t)p], t = (int64_t)seq.size() - 1;
+            out.clear();
+            out.push_back(seq[(size_t)a]);
+            for (int64_t u = t; u > a; --u) out.push_back(seq[(size_t)u]);
+            return (int64_t)out.size();
+        }
+        pos[(size_t)p] = (int64_t)seq.size();
+        seq.push_back(p);
+        cur = p;
+    }
+}
+
+// Bellman-Ford from `src` over the edges of w (in-place relaxation in vertex
+// order), checking the parent graph for a cycle after every pass.  A cycle of
+// a Bellman-Ford parent graph has negative weight, and one appears once the
+// distances of a negative cycle reachable from src keep falling; with no such
+// cycle the relaxation settles within n - 1 passes.  Returns the cycle length
+// (written to out) or 0.
+int64_t bellman_ford_cycle(const void *w, int dtype, int64_t n, int64_t ld, int64_t src,
+                           std::vector<int64_t> &out) {
+    std::vector<double> dist((size_t)n, HUGE_VAL);
+    std::vector<int64_t> parent((size_t)n, -1);
+    std::vector<int32_t> mark((size_t)n, 0);
+    dist[(size_t)src] = 0.0;
+    for (int64_t pass = 0; pass <= n; ++pass) {
+        bool changed = false;
+        for (int64_t u = 0; u < n; ++u) {
+            const double du = dist[(size_t)u];
+            if (du == HUGE_VAL) continue;
+            for (int64_t v = 0; v < n; ++v) {
+                const double e = edge_weight(w, dtype, ld, u, v);
+                if (e == HUGE_VAL) continue;
+                if (du + e < dist[(size_t)v]) {
+                    dist[(size_t)v] = du + e;
+                    parent[(size_t)v] = u;
+                    changed = true;
+                }
+            }
+        }
+        if (!changed) return 0;
+        // look for a cycle in the parent graph: follow parents from every
+        // unvisited vertex, marking the walk with its start (+1)
+        std::fill(mark.begin(), mark.end(), 0);
+        for (int64_t s0 = 0; s0 < n; ++s0) {
+            int64_t x = s0;
+            while (x >= 0 && mark[(size_t)x] == 0) {
+                mark[(size_t)x] = (int32_t)(s0 + 1);
+                x = parent[(size_t)x];
+            }
+            if (x >= 0 && mark[(size_t)x] == (int32_t)(s0 + 1))
+                return chain_cycle(n, x, [&](int64_t y) { return parent[(size_t)y]; }, out);
+        }
+    }
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t fw_negative_cycle_find(const void *w_host, int dtype, int64_t n, int64_t ld,
+                               const int32_t *pred_host, int64_t ld_pred, int64_t v,
+                               int64_t *cycle, int64_t cap, int *from_pred) {
+    if (!w_host || (dtype != FW_F32 && dtype != FW_I32) || n <= 0 || ld < n || v < 0 ||
+        v >= n || !cycle || cap <= 0 || (pred_host && ld_pred < n) || n > 0x7fffffffLL)
+        return -1;
+    if (from_pred) *from_pred = 0;
+    std::vector<int64_t> cyc;
+    int64_t m = 0;
+    if (pred_host) {
+        // walk the last hops of row v back from v itself (P_vv is the last
+        // hop of the closed walk that made d_vv negative); the result is kept
+        // only if its weight over the original edges is negative
+        m = chain_cycle(n, v, [&](int64_t x) { return (int64_t)pred_host[v * ld_pred + x]; }, cyc);
+        if (m > 0 && !(cycle_weight(w_host, dtype, ld, cyc.data(), m) < 0.0)) m = 0;
+        if (m > 0 && from_pred) *from_pred = 1;
+    }
+    if (m == 0) m = bellman_ford_cycle(w_host, dtype, n, ld, v, cyc);
+    if (m == 0) return 0;
+    if (m > cap) return -1;
+    std::copy(cyc.begin(), cyc.end(), cycle);
+    return m;
 }
 
 int64_t fw_path(const int32_t *pred, int64_t n, int64_t ldp, int64_t i, int64_t j,
@@ -589,35 +517,102 @@ int64_t fw_path(const int32_t *pred, int64_t n, int64_t ldp, int64_t i, int64_t 
     return len;
 }
 
-int fw_set_option(int option, int64_t value) {
-    switch (option) {
-    case FW_OPT_LOOKAHEAD:
-        if (value && !kLookaheadAvailable) return FW_ERR_UNSUPPORTED;
-        g_opt_lookahead.store(value ? 1 : 0);
-        return FW_OK;
-    case FW_OPT_GRAPHS:
-        if (value && !kGraphsAvailable) return FW_ERR_UNSUPPORTED;
-        g_opt_graphs.store(value ? 1 : 0);
-        return FW_OK;
-    default: return FW_ERR_INVALID;
+// ---------------------------------------------------------------------------
+// Solve plans: the stage loop of one matrix captured once into a hipGraph.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct fw_solve_plan_s {
+    void *d = nullptr;
+    int dtype = 0;
+    int n = 0;
+    int64_t ld = 0, ldp = 0;
+    int32_t *pred = nullptr;
+    int tile = 0;
+    int device = 0;
+    // the capture stream lives as long as the plan (and with it the graph
+    // captured on it); no event is recorded during the capture
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+void free_solve_plan(fw_solve_plan_s *pl) {
+    if (pl->exec) hipGraphExecDestroy(pl->exec);
+    if (pl->graph) hipGraphDestroy(pl->graph);
+    if (pl->cap_stream) hipStreamDestroy(pl->cap_stream);
+    delete pl;
+}
+}  // namespace
+
+extern "C" {
+
+int fw_solve_plan_create(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred,
+                         int64_t ld_pred, int tile, fw_solve_plan *out) {
+    if (!out) return FW_ERR_INVALID;
+    *out = nullptr;
+    int s = validate(d, dtype, n, ld, pred, ld_pred);
+    if (s != FW_OK) return s;
+    if (tile != 0 && !tile_supported(tile)) return FW_ERR_INVALID;
+    auto *pl = new fw_solve_plan_s();
+    pl->d = d;
+    pl->dtype = dtype;
+    pl->n = (int)n;
+    pl->ld = ld;
+    pl->pred = pred;
+    pl->ldp = pred ? ld_pred : 0;
+    pl->tile = n <= 1 ? 32 : tile ? tile : plan_tile(plan_key(dtype, pred), n);
+    if (hipGetDevice(&pl->device) != hipSuccess) {
+        delete pl;
+        return FW_ERR_HIP;
     }
+    *out = pl;
+    return FW_OK;
 }
 
-int64_t fw_get_option(int option) {
-    switch (option) {
-    case FW_OPT_LOOKAHEAD: return g_opt_lookahead.load();
-    case FW_OPT_GRAPHS: return g_opt_graphs.load();
-    default: return -1;
+int fw_solve_plan_launch(fw_solve_plan pl, int mode, void *stream) {
+    if (!pl || (mode != 0 && mode != 1)) return FW_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    if (mode == 0 || pl->n <= 1)
+        return solve(pl->d, pl->dtype, pl->n, pl->ld, pl->pred, pl->ldp, pl->tile, st);
+    if (!pl->exec) {
+        hipError_t e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            pl->cap_stream = nullptr;
+            return status_of(e);
+        }
+        e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return status_of(e);
+        int s = solve(pl->d, pl->dtype, pl->n, pl->ld, pl->pred, pl->ldp, pl->tile,
+                      pl->cap_stream, true);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(pl->cap_stream, &g);
+        if (s != FW_OK) {
+            if (g) hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return status_of(e);
+        pl->graph = g;
+        e = hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            pl->exec = nullptr;
+            return status_of(e);
+        }
     }
+    return status_of(hipGraphLaunch(pl->exec, st));
 }
 
-int fw_graph_cache_clear(void) {
-    std::lock_guard<std::mutex> lk(g_graph_mu);
-    for (auto &kv : g_graphs) {
-        hipGraphExecDestroy(kv.second.exec);
-        hipGraphDestroy(kv.second.graph);
-    }
-    g_graphs.clear();
+int fw_solve_plan_tile(fw_solve_plan pl) { return pl ? pl->tile : -1; }
+
+int fw_solve_plan_destroy(fw_solve_plan pl) {
+    if (!pl) return FW_ERR_INVALID;
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipSetDevice(pl->device);
+    hipDeviceSynchronize();
+    free_solve_plan(pl);
+    hipSetDevice(dev);
     return FW_OK;
 }
 

@@ -122,7 +122,7 @@ __device__ void solve_graph(const BatchItem &it, char *smem) {
         for (int64_t c = threadIdx.x; c < (int64_t)n * n; c += kBatchThreads) {
             const int i = (int)(c / n), j = (int)(c - (int64_t)i * n);
             int32_t &q = p[(int64_t)i * ldp + j];
-            if (i == j || q == kPredNone || Ar<T>::unreachable(d[(int64_t)i * ld + j])) q = -1;
+            q = final_pred<T>(i, j, d[(int64_t)i * ld + j], q);
         }
         __syncthreads();
     }
@@ -250,8 +250,8 @@ staged_kernel(const BatchItem *items, const StagedWork *work, int kind, int b) {
                 int32_t &q = as_global(it.p)[(int64_t)i * it.ldp + j];
                 if (kind == kStagedPredInit)
                     q = (i != j && !Ar<T>::absent(v)) ? i : kPredNone;
-                else if (i == j || q == kPredNone || Ar<T>::unreachable(v))
-                    q = -1;
+                else
+                    q = final_pred<T>(i, j, v, q);
             }
         }
         return;
@@ -430,6 +430,12 @@ void launch_batched_t(bool pred, bool big, BatchHeader *hdr, const BatchItem *it
     }
 }
 
+bool batch_needs_big(const BatchItem *items, int64_t count) {
+    for (int64_t g = 0; g < count; ++g)
+        if (items[g].n > 1 && items[g].tile > 64) return true;
+    return false;
+}
+
 hipError_t launch_batched_raw(int dtype, bool pred, BatchHeader *hdr, const BatchItem *items,
                               int grid, hipStream_t st, bool big) {
     if (dtype == FW_F32)
@@ -555,7 +561,7 @@ int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t coun
     pl->updates = upd;
     pl->bytes = sizeof(BatchHeader) + sizeof(BatchItem) * (size_t)std::max<int64_t>(count, 1);
     if (hipGetDevice(&pl->device) != hipSuccess) return FW_ERR_HIP;
-    for (int64_t g = n_staged; g < count; ++g) pl->big |= items[(size_t)g].tile > 64;
+    pl->big = batch_needs_big(items.data() + n_staged, count - n_staged);
     const int grid = resident_grid(dtype, any_pred, pl->big);
     if (grid <= 0) return FW_ERR_HIP;
     pl->grid = (int)std::min<int64_t>(grid, std::max<int64_t>(count - n_staged, 1));

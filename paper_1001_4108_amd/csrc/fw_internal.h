@@ -13,14 +13,13 @@ constexpr int32_t kPredNone = 0x7fffffff; // in-sweep "no last hop yet"
 enum PhaseKind {
     kDiag = 0,
     kPanel = 1,
-    kBulk = 2,      // the bulk, or its rest part under look-ahead
+    kBulk = 2,      // the bulk (+ the next diagonal tile where the kernel closes it)
     kPredFix = 3,
     kBatched = 4,
-    kBulkAhead = 5, // look-ahead part of the bulk (row and column b+1)
-    kBitsDiag = 6,  // bit-packed reachability: stage 0's diagonal block
-    kBitsPanel = 7, // bit-packed reachability: both panels
-    kBitsBulk = 8,  // bit-packed reachability: the bulk (+ next diagonal block)
-    kNumKinds = 9
+    kBitsDiag = 5,  // bit-packed reachability: stage 0's diagonal block
+    kBitsPanel = 6, // bit-packed reachability: both panels
+    kBitsBulk = 7,  // bit-packed reachability: the bulk (+ next diagonal block)
+    kNumKinds = 8
 };
 
 // Phase timing for launches made outside the host driver: calls
@@ -31,9 +30,6 @@ hipError_t timed_launch(int kind, double updates, hipStream_t st, hipError_t (*l
 // Closed semirings the sweep runs over.
 enum Semiring { kMinPlus = 0, kMaxMin = 1 };
 
-// Bulk launch parts (tile_kernel modes).
-enum BulkPart { kBulkAll = 1, kBulkAheadPart = 2, kBulkRestPart = 3 };
-
 // One stage-phase launch of the blocked schedule.  `d`/`p` are the matrix
 // and the (optional) predecessor matrix; `b` is the k-block index, `nb` the
 // number of tile rows.  Returns hipSuccess or the launch error.
@@ -43,17 +39,19 @@ hipError_t launch_panels(int dtype, int sr, int tile, void *d, int32_t *p, int n
                          int64_t ldp, int b, int nb, hipStream_t st);
 // With close_next the launch also closes the next stage's diagonal tile
 // (b+1, b+1), which replaces launch_diag(b + 1); allowed exactly when
-// bulk_closes_next_diag(sr, tile, d, p, n, ld, b) holds (and part is kBulkAll).
+// bulk_closes_next_diag(sr, tile, d, p, n, ld, b) holds.
 hipError_t launch_bulk(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
-                       int64_t ldp, int b, int nb, int part, bool close_next, hipStream_t st);
+                       int64_t ldp, int b, int nb, bool close_next, hipStream_t st);
 bool bulk_closes_next_diag(int sr, int tile, const void *d, const int32_t *p, int n, int64_t ld,
                            int b);
 hipError_t launch_pred_init(int dtype, const void *d, int32_t *p, int n, int64_t ld,
                             int64_t ldp, hipStream_t st);
 hipError_t launch_pred_fix(int dtype, const void *d, int32_t *p, int n, int64_t ld,
                            int64_t ldp, hipStream_t st);
-hipError_t launch_negcycle(int dtype, const void *d, int n, int64_t ld, int32_t *flag,
-                           hipStream_t st);
+// Vertices with d_ii < 0, ascending, into list (NULL: not written) and their
+// number into *count (device memory).
+hipError_t launch_negcycle(int dtype, const void *d, int n, int64_t ld, int32_t *list,
+                           int32_t *count, hipStream_t st);
 
 // Descriptor of one graph of a persistent batched launch.
 struct BatchItem {
@@ -74,9 +72,12 @@ struct BatchHeader {
 // Persistent batched kernel (fw_batched.hip) and host helpers (fw_api.cpp)
 // shared by the batch plans and the server.
 // big: some item has a 128-wide tile (selects the kernel form that has the
-// 128-wide path; the other one runs more workgroups per CU).
+// 128-wide path; the other one runs more workgroups per CU).  Callers compute
+// it from the items with batch_needs_big: the form without the 128-wide path
+// cannot solve a 128-wide item.
 hipError_t launch_batched_raw(int dtype, bool pred, BatchHeader *hdr, const BatchItem *items,
-                              int grid, hipStream_t st, bool big = true);
+                              int grid, hipStream_t st, bool big);
+bool batch_needs_big(const BatchItem *items, int64_t count);
 int batched_resident_grid(int dtype, bool pred);
 void fill_batch_item(BatchItem &it, void *d, int dtype, int64_t n, int64_t ld, int32_t *p,
                      int64_t ldp);

@@ -66,9 +66,7 @@ diag_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
 // Phases 2 and 3: one tile per workgroup.
 //   mode 0: blockIdx.x enumerates the 2(nb-1) panel tiles of stage b;
 //   mode 1: blockIdx.x enumerates the (nb-1)^2 bulk tiles;
-//   mode 2: the 2(nb-1)-1 bulk tiles in row or column b+1 (look-ahead part);
-//   mode 3: the (nb-2)^2 remaining bulk tiles;
-//   mode 4: the 2(nb-1)-1 bulk tiles in the last block row or column (the
+//   mode 2: the 2(nb-1)-1 bulk tiles in the last block row or column (the
 //           part of the bulk that bulk_dma_kernel leaves when the last block
 //           is partial).
 // int32 with predecessors takes the keyed form (product_tile_key).
@@ -111,8 +109,6 @@ tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
     switch (mode) {
     case 0: panel_coords(idx, b, nb - 1, bi, bj); break;
     case 1: bulk_coords(idx, b, nb - 1, bi, bj); break;
-    case 2: ahead_coords(idx, b, nb - 1, bi, bj); break;
-    case 3: rest_coords(idx, b, nb - 1, bi, bj); break;
     default: edge_coords(idx, b, nb - 1, bi, bj); break;
     }
     if constexpr (keyed_tile<T, S, BK, PRED, A>())
@@ -188,23 +184,40 @@ pred_fix_kernel(const T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t
                 int64_t ldp) {
     for (int i = blockIdx.y; i < n; i += gridDim.y)
         for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
-            const T v = d[(int64_t)i * ld + j];
             int32_t &p = P[(int64_t)i * ldp + j];
-            if (i == j || p == kPredNone || Ar<T>::unreachable(v)) p = -1;
+            p = final_pred<T>(i, j, d[(int64_t)i * ld + j], p);
         }
 }
 
+// The vertices i with d_ii < 0 after a solve, in ascending order, and their
+// number; one workgroup of 1024 threads walks the diagonal in chunks of 1024,
+// each chunk compacted by wave ballots and a scan of the 16 wave counts.
+// Either output may be NULL (the flag-only call passes list = NULL).
 template <typename T>
 __global__ void __launch_bounds__(1024)
-negcycle_kernel(const T *__restrict__ d, int n, int64_t ld, int32_t *__restrict__ flag) {
-    __shared__ int any;
-    if (threadIdx.x == 0) any = 0;
+negcycle_kernel(const T *__restrict__ d, int n, int64_t ld, int32_t *__restrict__ list,
+                int32_t *__restrict__ count) {
+    __shared__ int wave_cnt[16];
+    __shared__ int total;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) total = 0;
     __syncthreads();
-    int mine = 0;
-    for (int i = threadIdx.x; i < n; i += 1024) mine |= (d[(int64_t)i * ld + i] < T(0)) ? 1 : 0;
-    if (mine) atomicOr(&any, 1);
-    __syncthreads();
-    if (threadIdx.x == 0) *flag = any;
+    for (int base = 0; base < n; base += 1024) {
+        const int i = base + (int)threadIdx.x;
+        const bool neg = i < n && d[(int64_t)i * ld + i] < T(0);
+        const uint64_t mask = __ballot(neg);
+        if (lane == 0) wave_cnt[wave] = __popcll(mask);
+        __syncthreads();
+        int before = total;  // entries of earlier chunks and earlier waves
+        for (int w = 0; w < wave; ++w) before += wave_cnt[w];
+        const uint64_t below = lane ? (mask & (~0ull >> (64 - lane))) : 0ull;
+        if (neg && list) list[before + __popcll(below)] = i;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int w = 0; w < 16; ++w) total += wave_cnt[w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && count) *count = total;
 }
 
 dim3 elementwise_grid(int n) {
@@ -285,8 +298,7 @@ template <typename T, class A, bool ALLOW_PRED>
 hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b,
                          int nb, int mode, bool close_next, hipStream_t st) {
     const int64_t m = nb - 1;
-    const int64_t grid = mode == 0 ? 2 * m : mode == 1 ? m * m : mode == 2 ? 2 * m - 1
-                                                                           : (m - 1) * (m - 1);
+    const int64_t grid = mode == 0 ? 2 * m : m * m;
     if (grid <= 0) return close_next ? hipErrorInvalidValue : hipSuccess;
     if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
     const bool vec = vec_ok(d, ld) && (p == nullptr || vec_ok(p, ldp));
@@ -336,7 +348,7 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
             if (e != hipSuccess) return e;
         }
         if (nf < nb)
-            return tile_t<T, true, false, A>(tile, d, p, n, ld, ldp, b, nb, 4,
+            return tile_t<T, true, false, A>(tile, d, p, n, ld, ldp, b, nb, 2,
                                              (unsigned)(2 * m - 1), st);
         return hipSuccess;
     }
@@ -393,12 +405,10 @@ bool bulk_closes_next_diag(int sr, int tile, const void *d, const int32_t *p, in
 }
 
 hipError_t launch_bulk(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
-                       int64_t ldp, int b, int nb, int part, bool close_next, hipStream_t st) {
+                       int64_t ldp, int b, int nb, bool close_next, hipStream_t st) {
     if (dtype == 0)
-        return tile_any<float>(sr, tile, (float *)d, p, n, ld, ldp, b, nb, part, close_next,
-                               st);
-    return tile_any<int32_t>(sr, tile, (int32_t *)d, p, n, ld, ldp, b, nb, part, close_next,
-                             st);
+        return tile_any<float>(sr, tile, (float *)d, p, n, ld, ldp, b, nb, 1, close_next, st);
+    return tile_any<int32_t>(sr, tile, (int32_t *)d, p, n, ld, ldp, b, nb, 1, close_next, st);
 }
 
 hipError_t launch_pred_init(int dtype, const void *d, int32_t *p, int n, int64_t ld,
@@ -421,12 +431,12 @@ hipError_t launch_pred_fix(int dtype, const void *d, int32_t *p, int n, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_negcycle(int dtype, const void *d, int n, int64_t ld, int32_t *flag,
-                           hipStream_t st) {
+hipError_t launch_negcycle(int dtype, const void *d, int n, int64_t ld, int32_t *list,
+                           int32_t *count, hipStream_t st) {
     if (dtype == 0)
-        negcycle_kernel<float><<<1, 1024, 0, st>>>((const float *)d, n, ld, flag);
+        negcycle_kernel<float><<<1, 1024, 0, st>>>((const float *)d, n, ld, list, count);
     else
-        negcycle_kernel<int32_t><<<1, 1024, 0, st>>>((const int32_t *)d, n, ld, flag);
+        negcycle_kernel<int32_t><<<1, 1024, 0, st>>>((const int32_t *)d, n, ld, list, count);
     return hipGetLastError();
 }
 

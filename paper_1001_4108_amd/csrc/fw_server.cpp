@@ -220,7 +220,8 @@ int enqueue_group(fw_server_s *s, Group *g) {
             auto *dh = static_cast<BatchHeader *>(w.dev_table);
             auto *di = reinterpret_cast<const BatchItem *>(static_cast<char *>(w.dev_table) +
                                                            sizeof(BatchHeader));
-            e = launch_batched_raw(dt, false, dh, di, std::min(cnt, s->grid), st);
+            e = launch_batched_raw(dt, false, dh, di, std::min(cnt, s->grid), st,
+                                   batch_needs_big(items, cnt));
             if (e != hipSuccess) return status_of(e);
         }
     } else {

@@ -108,6 +108,17 @@ __device__ __forceinline__ void lex_update(T &c, int32_t &p, T cand, int32_t pc)
     p = take ? pc : p;
 }
 
+// The predecessor a cell keeps after the sweep: -1 where no last hop was
+// found, for an unreachable pair, and on the diagonal -- except where d_ii < 0
+// (a negative cycle through i, outside the problem statement), whose last hop
+// is kept so that the cycle can be walked back from the matrix.
+template <typename T>
+__device__ __forceinline__ int32_t final_pred(int i, int j, T v, int32_t p) {
+    if (p == kPredNone) return -1;
+    if (i == j) return v < T(0) ? p : -1;
+    return Ar<T>::unreachable(v) ? -1 : p;
+}
+
 template <typename T> struct Vec4 { typedef T type __attribute__((ext_vector_type(4))); };
 
 // Load E consecutive elements of one matrix row starting at column `col`;
@@ -827,22 +838,6 @@ __device__ __forceinline__ void bulk_coords(int idx, int b, int m, int &bi, int 
     bj = r < b ? r : r + 1;
 }
 
-// Look-ahead split of the stage-b bulk (b + 1 < nb, m = nb - 1):
-//   ahead: the bulk tiles in row b+1 or column b+1, 2m - 1 of them -- after
-//          they are done, stage b+1's diagonal tile and panels are final and
-//          can be processed while the rest of stage b's bulk still runs;
-//   rest:  the other (m - 1)^2 bulk tiles.
-__device__ __forceinline__ void ahead_coords(int idx, int b, int m, int &bi, int &bj) {
-    if (idx < m) {
-        bi = b + 1;
-        bj = idx < b ? idx : idx + 1;
-    } else {
-        idx -= m;
-        bi = idx < b ? idx : idx + 2;
-        bj = b + 1;
-    }
-}
-
 // Bulk tiles of stage b (b < nb - 1) that lie in the last block row or
 // column, nb - 1 being a partial block: 2m - 1 of them (m = nb - 1).  The
 // other bulk tiles are the (m - 1)^2 of bulk_coords over the first nb - 1
@@ -856,13 +851,6 @@ __device__ __forceinline__ void edge_coords(int idx, int b, int m, int &bi, int 
         bi = idx < b ? idx : idx + 1;
         bj = m;
     }
-}
-
-__device__ __forceinline__ void rest_coords(int idx, int b, int m, int &bi, int &bj) {
-    const int w = m - 1;
-    const int q = idx / w, r = idx - q * w;
-    bi = q < b ? q : q + 2;
-    bj = r < b ? r : r + 2;
 }
 
 }  // namespace fw

@@ -158,3 +158,32 @@ def serving_trace(rate: float = 2000.0, duration: float = 60.0, nlo: int = 64,
     o = rng.integers(0, nhi - n + 1).astype(np.int64) if m else np.zeros(0, np.int64)
     return ServingTrace(t=t, n=n, b=b.astype(np.int64), o=o, base_n=nhi, nbase=nbase,
                         p=p, wlo=wlo, whi=whi, seed=seed)
+
+
+def cycle_permutation(n: int, seed) -> np.ndarray:
+    """A seeded random order of the n vertices: the directed cycle
+    perm[0] -> perm[1] -> ... -> perm[n-1] -> perm[0] is a graph whose
+    shortest paths run up to n - 1 hops (the long-path parity input)."""
+    return np.random.default_rng(seed).permutation(n)
+
+
+def planted_negative_cycle(n: int, p: float, length: int, seed, dtype=np.int32):
+    """A graph with exactly one negative simple cycle: Bernoulli(p) edges with
+    integer weights in [length, length + 99] and, on `length` seeded distinct
+    vertices c_0 .. c_{L-1}, the edges c_t -> c_{t+1 mod L} of weight -1.
+    No other edge enters a cycle vertex (edges leave it freely), so no other
+    vertex lies on a closed walk through the cycle and only c_0 .. c_{L-1}
+    reach themselves at negative cost; every other simple cycle avoids the
+    cycle vertices and weighs at least L.  Floyd-Warshall's values then stay
+    above -L * 2^L (each cycle vertex at most doubles the negative part).
+    Returns (matrix, cycle vertices in order)."""
+    ss = np.random.SeedSequence(seed)
+    s_mat, s_cyc = ss.spawn(2)
+    w = dense_graph(n, p, length, length + 99, s_mat, dtype=dtype)
+    cyc = np.random.default_rng(s_cyc).choice(n, length, replace=False)
+    absent = np.float32(np.inf) if np.dtype(dtype) == np.float32 else np.int32(I32_INF)
+    w[:, cyc] = absent
+    w[cyc, cyc] = 0
+    for t in range(length):
+        w[cyc[t], cyc[(t + 1) % length]] = -1
+    return w, cyc

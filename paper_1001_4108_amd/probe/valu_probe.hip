@@ -1,0 +1,111 @@
+// Vector-ALU issue-rate probe for gfx950 (measurement only; not part of the
+// library's ABI).  Each form runs register-only loops of one instruction mix
+// and reports lane-instructions per second: every thread keeps 64
+// accumulators and two operand vectors of 8 values that differ per lane (read
+// from memory once, so nothing folds), and the accumulators are stored at the
+// end so nothing is dead.  The mixes are the inner loops of the library's
+// kernels:
+//   form 0  v_add_f32 alone                        (c = c + a, 64 per step)
+//   form 1  fp32 min-plus, two k-steps fused       (2 v_add_f32 + 1 v_minimum3_f32
+//                                                   per cell and k-pair)
+//   form 2  int32 min-plus, two k-steps fused      (2 v_add_u32 + 1 v_min3_i32)
+//   form 3  v_fma_f32                              (c = a * b + c)
+//   form 4  bit-packed reachability                (v_and_or_b32 per word)
+// Instructions per step and thread: 64 (forms 0, 3, 4) or 192 (forms 1, 2).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace {
+
+template <int FORM>
+__global__ void __launch_bounds__(256) valu_kernel(const float *__restrict__ src,
+                                                   float *__restrict__ dst, int iters) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    float a[8], b[8], a1[8], b1[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        a[q] = src[(t * 7 + q) & 4095];
+        b[q] = src[(t * 5 + q + 8) & 4095];
+        a1[q] = src[(t * 3 + q + 16) & 4095];
+        b1[q] = src[(t * 11 + q + 24) & 4095];
+    }
+    float c[8][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) c[i][j] = src[(t + i * 8 + j) & 4095];
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if constexpr (FORM == 0) {
+                    c[i][j] = c[i][j] + a[i];
+                } else if constexpr (FORM == 1) {
+                    c[i][j] = __builtin_elementwise_minimum(
+                        __builtin_elementwise_minimum(c[i][j], a[i] + b[j]), a1[i] + b1[j]);
+                } else if constexpr (FORM == 2) {
+                    const int x = __float_as_int(c[i][j]);
+                    const int s0 = __float_as_int(a[i]) + __float_as_int(b[j]);
+                    const int s1 = __float_as_int(a1[i]) + __float_as_int(b1[j]);
+                    int m = x < s0 ? x : s0;
+                    m = m < s1 ? m : s1;
+                    c[i][j] = __int_as_float(m);
+                } else if constexpr (FORM == 3) {
+                    c[i][j] = __builtin_fmaf(a[i], b[j], c[i][j]);
+                } else {
+                    const uint32_t x = __float_as_uint(c[i][j]);
+                    c[i][j] = __uint_as_float((x & __float_as_uint(a[i])) | __float_as_uint(b[j]));
+                }
+            }
+        // operands drift so the loop body cannot be hoisted
+#pragma unroll
+        for (int q = 0; q < 8; ++q) asm volatile("" : "+v"(a[q]), "+v"(b[q]), "+v"(a1[q]), "+v"(b1[q]));
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) dst[(int64_t)t * 64 + i * 8 + j] = c[i][j];
+}
+
+}  // namespace
+
+extern "C" {
+
+// Instructions per loop step and thread of each form (the counts above).
+int fw_probe_valu_instr_per_step(int form) {
+    return (form == 1 || form == 2) ? 192 : 64;
+}
+
+// Runs `form` on `blocks` x 256 threads for `iters` steps on `stream` after
+// one warm-up launch; writes the kernel time in ms (HIP events).  src: 4096
+// floats of device memory; dst: blocks * 256 * 64 floats.  0 on success.
+int fw_probe_valu(int form, int blocks, int iters, const float *src, float *dst, void *stream,
+                  float *ms) {
+    if (form < 0 || form > 4 || blocks <= 0 || iters <= 0 || !src || !dst || !ms) return 1;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return 2;
+    if (hipEventCreate(&e1) != hipSuccess) return 2;
+    auto go = [&](int n) {
+        switch (form) {
+        case 0: valu_kernel<0><<<blocks, 256, 0, st>>>(src, dst, n); break;
+        case 1: valu_kernel<1><<<blocks, 256, 0, st>>>(src, dst, n); break;
+        case 2: valu_kernel<2><<<blocks, 256, 0, st>>>(src, dst, n); break;
+        case 3: valu_kernel<3><<<blocks, 256, 0, st>>>(src, dst, n); break;
+        default: valu_kernel<4><<<blocks, 256, 0, st>>>(src, dst, n); break;
+        }
+    };
+    go(iters);
+    int rc = hipEventRecord(e0, st) == hipSuccess ? 0 : 2;
+    go(iters);
+    if (hipEventRecord(e1, st) != hipSuccess) rc = 2;
+    if (hipGetLastError() != hipSuccess) rc = 2;
+    if (hipEventSynchronize(e1) != hipSuccess) rc = 2;
+    if (rc == 0 && hipEventElapsedTime(ms, e0, e1) != hipSuccess) rc = 2;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+}  // extern "C"

@@ -130,13 +130,65 @@ def test_fw_path_host_reconstruction():
         B.fw_path(bad, 0, 3)
 
 
-def test_disabled_schedules_cannot_be_enabled():
+def test_solve_plan_and_negative_cycle_argument_validation():
     L = B.lib()
-    assert L.fw_get_option(1) == 0 and L.fw_get_option(2) == 0
-    assert L.fw_set_option(1, 1) == 4 and L.fw_set_option(2, 1) == 4  # FW_ERR_UNSUPPORTED
-    assert L.fw_set_option(1, 0) == 0 and L.fw_set_option(2, 0) == 0
-    assert L.fw_set_option(99, 0) == 1
-    assert L.fw_get_option(99) == -1
+    null = None
+    some = ctypes.c_void_p(16)
+    h = ctypes.c_void_p()
+    assert L.fw_solve_plan_create(null, 0, 5, 5, null, 0, 0, ctypes.byref(h)) == 1
+    assert L.fw_solve_plan_create(some, 0, 5, 4, null, 0, 0, ctypes.byref(h)) == 1   # ld < n
+    assert L.fw_solve_plan_create(some, 0, 64, 64, null, 0, 48, ctypes.byref(h)) == 1  # tile
+    assert L.fw_solve_plan_create(some, 0, 64, 64, null, 0, 0, null) == 1
+    assert L.fw_solve_plan_launch(null, 1, null) == 1
+    assert L.fw_solve_plan_destroy(null) == 1
+    assert L.fw_solve_plan_tile(null) == -1
+    assert L.fw_negative_cycle_vertices(some, 0, 4, 4, null, some, null) == 1  # no list
+    assert L.fw_negative_cycle_vertices(some, 0, 4, 4, some, null, null) == 1  # no count
+    assert L.fw_negative_cycle_vertices(some, 9, 4, 4, some, some, null) == 1  # dtype
+    buf = (ctypes.c_int64 * 4)()
+    W = np.zeros((4, 4), np.int32)
+    f = L.fw_negative_cycle_find
+    assert f(null, 1, 4, 4, null, 0, 0, buf, 4, null) == -1          # no weights
+    assert f(W.ctypes.data, 1, 4, 4, null, 0, 4, buf, 4, null) == -1  # v out of range
+    assert f(W.ctypes.data, 1, 4, 3, null, 0, 0, buf, 4, null) == -1  # ld < n
+    assert f(W.ctypes.data, 1, 4, 4, W.ctypes.data, 3, 0, buf, 4, null) == -1  # ld_pred < n
+
+
+def _cycle_weight(W, cyc):
+    return sum(int(W[cyc[t], cyc[(t + 1) % len(cyc)]]) for t in range(len(cyc)))
+
+
+def test_negative_cycle_find_on_host():
+    """Cycle extraction from a predecessor row and by the Bellman-Ford
+    fallback, on hand-built inputs (host only)."""
+    M = B.I32_INF
+    # 0 -> 1 -> 2 -> 0 weighs -3; 3 -> 0 and 2 -> 4 hang off it
+    W = np.full((5, 5), M, np.int32)
+    np.fill_diagonal(W, 0)
+    W[0, 1] = W[1, 2] = W[2, 0] = -1
+    W[3, 0] = 5
+    W[2, 4] = 2
+    # a predecessor row 0 whose last hops follow the cycle
+    P = np.full((5, 5), -1, np.int32)
+    P[0, 0], P[0, 1], P[0, 2], P[0, 4] = 2, 0, 1, 2
+    cyc, from_pred = B.fw_negative_cycle_find(W, 0, P)
+    assert from_pred and cyc == [0, 1, 2] and _cycle_weight(W, cyc) == -3
+    # without predecessors: Bellman-Ford from 1 finds the same cycle (a rotation)
+    cyc, from_pred = B.fw_negative_cycle_find(W, 1)
+    assert not from_pred and sorted(cyc) == [0, 1, 2] and _cycle_weight(W, cyc) == -3
+    # a predecessor row whose walk closes a non-negative cycle is not trusted
+    P2 = P.copy()
+    W2 = W.copy()
+    W2[1, 0] = 7            # 0 -> 1 -> 0 weighs 6
+    P2[0, 0], P2[0, 1] = 1, 0
+    cyc, from_pred = B.fw_negative_cycle_find(W2, 0, P2)
+    assert not from_pred and _cycle_weight(W2, cyc) < 0 and sorted(cyc) == [0, 1, 2]
+    # no negative cycle reachable from 4: empty
+    assert B.fw_negative_cycle_find(W, 4) == ([], False)
+    # fp32 weights
+    Wf = np.where(W == M, np.float32(np.inf), W.astype(np.float32)).astype(np.float32)
+    cyc, _ = B.fw_negative_cycle_find(Wf, 2)
+    assert sorted(cyc) == [0, 1, 2]
 
 
 def test_autotune_argument_validation():

@@ -68,9 +68,11 @@ def test_bits_profile_traffic_figures_parse(tmp_path):
 
 def test_cpu_baseline_leg_matches_the_oracle_prefix():
     W = gen.dense_graph(96, 0.3, 1, 1000, seed=3)
-    out = bench.cpu_baseline(W, 40)
+    out = bench.cpu_baseline(W, 40, 8)
     assert out["kind"] == "oracle" and out["unit"] == "cell-updates/s"
     assert out["cores"] >= 1 and out["value"] > 0
+    assert out["one_core"]["cores"] == 1 and out["one_core"]["value"] > 0
+    assert out["cpu_model"] is None or isinstance(out["cpu_model"], str)
     # the leg runs the first 40 k-iterations of the plain loop: compare with
     # the same prefix computed directly
     ref = np.array(W, copy=True)
