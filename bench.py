@@ -24,29 +24,30 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X vector-ALU ceiling: the published fp32 vector rate, 157.3 TFLOP/s =
-# 256 CUs x 2.4 GHz x 128 lanes x 2 flops (an FMA counts 2), i.e. 128 32-bit
-# lane-operations per clock per CU = 7.86e13 lane-ops/s.  Simple 32-bit ops
-# (add, min3) do issue at that rate on gfx950 (FMA at half of it).  A cell
-# update costs at least 1.5 lane-instructions with scalar fp32 adds (two
-# v_add_f32 and one v_min3_f32 per two updates; packed fp32 is not used), so
-# the fp32 update ceiling is 5.24e13 updates/s.
-VALU_LANE_OPS_PER_S = 256 * 128 * 2.4e9
-MIN_INSTR_PER_UPDATE = 1.5
-UPDATE_PEAK = VALU_LANE_OPS_PER_S / MIN_INSTR_PER_UPDATE
-# the 1-instruction-per-update figure some analyses quote for this chip
-# (16-lane SIMDs at one instruction per 4 clocks, packed adds): 3.93e13 upd/s
-ONE_INSTR_64LANE_PEAK = 256 * 64 * 2.4e9
+# MI355X's published fp32 vector peak, 157.3 TFLOP/s = 256 CUs x 2.4 GHz x
+# 256 flops per clock per CU, an FMA counting two flops: 7.86e13 32-bit
+# lane-operations per second.  A cell update is two operations (one add, one
+# min), so the roofline's "achieved" is 2 x updates/s in TFLOP/s against this
+# peak.  The ceiling of the bulk's own instruction mix (two v_add_f32 and one
+# v_minimum3_f32 per two updates: 1.5 lane-instructions per update; packed
+# fp32 is not used) is reported beside it, from the issue-rate probe run in
+# the same process (bench_valu_probe).
+FP32_VECTOR_PEAK_FLOPS = 157.3e12
+OPS_PER_UPDATE = 2
+VALU_LANE_OPS_PER_S = FP32_VECTOR_PEAK_FLOPS / 2
+MIX_INSTR_PER_UPDATE = 1.5
+CUS, CLOCK_HZ = 256, 2.4e9
 
 
 PROFILE = os.path.join(ROOT, "profiles", "bulk_dma_kernel_f32_t128_n16384.md")
 KERNEL_SOURCES = ("paper_1001_4108_amd/csrc/fw_tiles.h", "paper_1001_4108_amd/csrc/fw_kernels.hip")
 BITS_PROFILE = os.path.join(ROOT, "profiles", "bits_kernels_reachability_n16384.md")
 BITS_SOURCES = ("paper_1001_4108_amd/csrc/fw_bits.hip",)
-# Bit-packed reachability: 32-bit integer VALU issues 64 lanes per clock per
-# CU on gfx950, and the bulk needs 1.125 instructions per 32-cell word-update
-# (one v_and_or_b32, plus one v_bfe_i32 per 8 words)
-BITS_WORD_PEAK = 256 * 64 * 2.4e9 / 1.125
+# Bit-packed reachability: the bulk needs 1.125 lane-instructions per 32-cell
+# word-update (one v_and_or_b32, plus one v_bfe_i32 per 8 words); its peak is
+# the published lane-operation rate at that count
+BITS_INSTR_PER_WORD = 1.125
+BITS_WORD_PEAK = VALU_LANE_OPS_PER_S / BITS_INSTR_PER_WORD
 
 
 def measured_traffic(profile=PROFILE, sources=KERNEL_SOURCES):
@@ -84,7 +85,13 @@ def parse():
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--cpu-ksteps", type=int, default=2048,
                     help="k-iterations of the oracle timed for the CPU baseline")
+    ap.add_argument("--cpu-ksteps-one-core", type=int, default=96,
+                    help="k-iterations of the oracle timed on one thread")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the vector-ALU issue-rate probe")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the n=512 latency / per-phase bandwidth leg")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-phase HIP events (plain timed region)")
     ap.add_argument("--no-batched", action="store_true")
@@ -97,8 +104,12 @@ def parse():
     ap.add_argument("--no-negative", action="store_true",
                     help="skip the n=8192 int32 negative-weight solve with predecessors")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=4.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="arrival window of the serving trace at the configured rate")
+    ap.add_argument("--serve-uncapped-seconds", type=float, default=4.0,
+                    help="arrival window of the same trace replayed without the queue cap")
+    ap.add_argument("--serve-point-seconds", type=float, default=10.0,
+                    help="arrival window of the 0.5x / 0.9x capacity load points")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--batched-reps", type=int, default=5)
     return ap.parse_args()
@@ -108,8 +119,122 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(W, ksteps):
-    """Oracle (plain triple loop) on the same matrix, first `ksteps` k-iterations."""
+PROBE_FORMS = {0: "v_add_f32", 1: "fp32 min-plus (2 v_add_f32 + v_minimum3_f32)",
+               2: "int32 min-plus (2 v_add_u32 + v_min3_i32)", 3: "v_fma_f32",
+               4: "v_and_or_b32"}
+
+
+def bench_valu_probe(torch, dev):
+    """Issue rates of the kernels' instruction mixes (probe/valu_probe.hip):
+    register-only loops, 2048 workgroups of 256 threads, timed by HIP events
+    on the current stream.  Lane-instructions per second, and per clock per CU
+    at the 2.4 GHz nominal clock."""
+    import ctypes
+    from paper_1001_4108_amd import build as libbuild
+    L = ctypes.CDLL(libbuild.PROBE_OUT)
+    L.fw_probe_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]
+    blocks = 2048
+    src = torch.rand(4096, device=dev) * 100
+    dst = torch.empty(blocks * 256 * 64, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    out = {"what": "register-only loops of one instruction mix, 2048 x 256 threads; "
+                   "lanes per clock per CU at the 2.4 GHz nominal clock",
+           "published_lane_ops_per_clk_per_cu": VALU_LANE_OPS_PER_S / (CUS * CLOCK_HZ),
+           "forms": {}}
+    for form, what in PROBE_FORMS.items():
+        per_step = L.fw_probe_valu_instr_per_step(form)
+        iters = 20000 if per_step > 64 else 60000
+        ms = ctypes.c_float(0)
+        rc = L.fw_probe_valu(form, blocks, iters, src.data_ptr(), dst.data_ptr(),
+                             ctypes.c_void_p(stream), ctypes.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"valu probe form {form} failed ({rc})")
+        lane_instr = float(blocks) * 256 * iters * per_step
+        rate = lane_instr / (ms.value / 1e3)
+        out["forms"][what] = {"lane_instr_per_s": rate, "ms": ms.value,
+                              "lanes_per_clk_per_cu": rate / (CUS * CLOCK_HZ)}
+    mix = out["forms"][PROBE_FORMS[1]]["lane_instr_per_s"]
+    out["fp32_minplus_update_ceiling"] = mix / MIX_INSTR_PER_UPDATE
+    out["int32_minplus_update_ceiling"] = out["forms"][PROBE_FORMS[2]]["lane_instr_per_s"] / 1.5
+    return out
+
+
+def bench_small(torch, fw, gen, dev, reps=50):
+    """n=512 fp32 (edge prob 0.5, weights [1,100]): solve latency as eager
+    launches and as one captured-graph launch (solve plan), per-phase time
+    and achieved HBM bandwidth over each phase's algorithmic bytes, and the
+    whole result against the oracle."""
+    import numpy as np
+    import oracle
+    W = gen.single_graph_512()
+    n = W.shape[0]
+    pristine = torch.from_numpy(W).to(dev)
+    work = torch.empty_like(pristine)
+    tile = fw.plan_tile(torch.float32, n)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    plan = fw.SolvePlan(work)
+    out = {"workload": f"single dense directed graph n={n} fp32, edge prob 0.5, integer "
+                       f"weights [1,100]", "tile": tile}
+    for mode in ("eager", "graph"):
+        times = []
+        for r in range(reps + 3):
+            work.copy_(pristine)
+            ev0.record()
+            plan.launch(mode)
+            ev1.record()
+            torch.cuda.synchronize(dev)
+            if r >= 3:
+                times.append(ev0.elapsed_time(ev1))
+        ms = float(np.median(times))
+        out[mode] = {"ms": ms, "updates_per_s": float(n) ** 3 / (ms / 1e3)}
+    ok = bool(np.array_equal(work.cpu().numpy().view(np.uint32), oracle.fw(W).view(np.uint32)))
+    # phase times of eager solves (HIP events around every launch)
+    fw.profile_read()
+    fw.profile_enable(True)
+    for _ in range(reps):
+        work.copy_(pristine)
+        plan.launch("eager")
+    torch.cuda.synchronize(dev)
+    fw.profile_enable(False)
+    prof = fw.profile_read()
+    s, m = tile, n - tile
+    nb = n // tile
+    # algorithmic bytes per launch (n a multiple of the tile): the diagonal
+    # tile read and written; both panels read and written plus the diagonal
+    # tile read; the bulk read and written plus both panels read (plus the
+    # next diagonal tile closed by the launch, read and written)
+    per_launch = {"diag": 2 * s * s * 4, "panel": (4 * m * s + s * s) * 4,
+                  "bulk": (2 * m * m + 2 * m * s) * 4 + 2 * s * s * 4}
+    phases = {}
+    for k, b in per_launch.items():
+        ms, cnt, upd = prof[k]
+        if cnt:
+            us = ms * 1e3 / cnt
+            phases[k] = {"launches_per_solve": cnt / reps, "us_per_launch": us,
+                         "bytes_per_launch": b, "gb_per_s": b / (us * 1e-6) / 1e9}
+    out["phases"] = phases
+    out["stages"] = nb
+    out["check"] = "ok" if ok else "mismatch"
+    plan.destroy()
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(W, ksteps, ksteps_one_core):
+    """Oracle (plain triple loop) on the same matrix, first `ksteps`
+    k-iterations on all host threads, then `ksteps_one_core` on one thread
+    (the paper's CPU column is one core)."""
     import numpy as np
     import oracle
     n = W.shape[0]
@@ -119,9 +244,18 @@ def cpu_baseline(W, ksteps):
     oracle.fw_inplace(work, nthreads=threads, k_begin=0, k_end=ksteps)
     dt = time.perf_counter() - t0
     upd = float(ksteps) * n * n
+    work = np.array(W, copy=True)
+    t0 = time.perf_counter()
+    oracle.fw_inplace(work, nthreads=1, k_begin=0, k_end=ksteps_one_core)
+    dt1 = time.perf_counter() - t0
+    upd1 = float(ksteps_one_core) * n * n
     return {"value": upd / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"first {ksteps} of {n} k-iterations of the plain triple loop on the "
-                      f"same n={n} fp32 matrix ({upd:.3e} updates, {dt:.1f} s)"}
+                      f"same n={n} fp32 matrix ({upd:.3e} updates, {dt:.1f} s)",
+            "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "one_core": {"value": upd1 / dt1, "unit": "cell-updates/s", "cores": 1,
+                         "sample": f"first {ksteps_one_core} k-iterations, one thread "
+                                   f"({upd1:.3e} updates, {dt1:.1f} s)"}}
 
 
 def pack_graphs(graphs, torch, dev):
@@ -437,8 +571,12 @@ def run_trace(torch, fw, srv, bases, tr, limit_s):
     th = threading.Thread(target=submitter)
     th.start()
     recs = []
+    next_report = time.perf_counter() + 15.0
     while th.is_alive():
         recs += srv.poll(timeout_us=20000)
+        if time.perf_counter() >= next_report:
+            log(f"serving: {len(recs)} completed, {len(ids)} accepted, {refused[0]} refused")
+            next_report += 15.0
     th.join()
     if sub_err:
         raise sub_err[0]
@@ -464,37 +602,46 @@ def run_trace(torch, fw, srv, bases, tr, limit_s):
             "deferrals": st["deferrals"], "peak_bytes": st["peak_bytes"]}
 
 
-def bench_serving(torch, fw, gen, dev, seconds, rate):
+def bench_serving(torch, fw, gen, dev, seconds, rate, uncapped_seconds, point_seconds):
     """Poisson arrivals, n log-uniform in [64, 8192], fp32 windows of resident
-    base graphs; footprint admission into a 32 GiB budget, 4 worker streams."""
+    base graphs; footprint admission into a 32 GiB budget, 4 worker streams.
+
+    The offered load (2000 req/s) is about 2.5x the GPU's capacity, so the
+    full trace runs with admission control: at most QUEUE_CAP requests may
+    wait for admission and later submissions are refused (FW_ERR_BUSY, counted);
+    p50/p99 are over the accepted requests.  The same arrivals without the cap
+    are replayed for a shorter prefix (an unbounded queue grows for as long as
+    the trace lasts, so its p99 measures the trace length).  Load points at
+    0.5x and 0.9x of the capacity measured under the cap follow."""
     import numpy as np
     tr_full = gen.serving_trace(rate=rate, duration=seconds)
     bases = [torch.from_numpy(tr_full.base_graph(b)).to(dev) for b in range(tr_full.nbase)]
     cfg = dict(budget_bytes=32 << 30, streams=4, small_n=512, max_batch=2048)
     out = {"workload": f"Poisson arrivals at {rate:.0f} req/s for {seconds:.1f} s, n log-uniform "
                        "in [64,8192], fp32, edge prob 0.3, integer weights [1,1000] (principal "
-                       "windows of 2 resident 8192-vertex base graphs)", "config": cfg}
-    with fw.Server(torch.float32, **cfg) as srv:
-        # warm-up: a few requests of each path
+                       "windows of 2 resident 8192-vertex base graphs); admission: at most "
+                       f"{QUEUE_CAP} requests waiting, later ones refused", "config": cfg}
+
+    def warm(srv):
         for n in (64, 300, 700, 2000):
             srv.submit(bases[0][:n, :n])
         srv.drain(timeout_s=60)
         srv.poll()
-        out["at_rate"] = run_trace(torch, fw, srv, bases, tr_full, 600)
-        cap = out["at_rate"]["solves_per_s"]
-        out["capacity_solves_per_s"] = cap
-        for frac in (0.5, 0.9):
-            tr = gen.serving_trace(rate=cap * frac, duration=min(seconds, 3.0), seed=50 + int(frac * 10))
-            out[f"at_{frac:.1f}x_capacity"] = run_trace(torch, fw, srv, bases, tr, 600)
-    # the same overload with admission control: at most QUEUE_CAP requests may
-    # wait, later ones are refused at submission (FW_ERR_BUSY); latency of the
-    # accepted ones
+
     with fw.Server(torch.float32, queue_cap=QUEUE_CAP, **cfg) as srv:
-        for n in (64, 300, 700, 2000):
-            srv.submit(bases[0][:n, :n])
-        srv.drain(timeout_s=60)
-        srv.poll()
-        out[f"at_rate_queue_cap_{QUEUE_CAP}"] = run_trace(torch, fw, srv, bases, tr_full, 600)
+        warm(srv)
+        out["at_rate"] = run_trace(torch, fw, srv, bases, tr_full, 600)
+    cap = out["at_rate"]["solves_per_s"]
+    out["capacity_solves_per_s"] = cap
+    with fw.Server(torch.float32, **cfg) as srv:
+        warm(srv)
+        tr = gen.serving_trace(rate=rate, duration=uncapped_seconds)
+        out[f"at_rate_uncapped_first_{uncapped_seconds:g}s"] = run_trace(torch, fw, srv, bases,
+                                                                          tr, 600)
+        for frac in (0.5, 0.9):
+            tr = gen.serving_trace(rate=cap * frac, duration=point_seconds,
+                                   seed=50 + int(frac * 10))
+            out[f"at_{frac:.1f}x_capacity"] = run_trace(torch, fw, srv, bases, tr, 600)
     # correctness: a few requests of the trace solved through the server with
     # copy-back, compared with the oracle
     import oracle
@@ -584,14 +731,39 @@ def main():
             per_launch_s = b["ms_per_step"] / b["launches_per_step"] / 1e3
             ach = per_launch_upd / per_launch_s
             roof = {"bound": "alu", "kernel": "bulk_dma_kernel (bulk tiles + next diagonal closure)",
-                    "achieved": ach / 1e12, "peak": UPDATE_PEAK / 1e12, "unit": "Tupd/s",
-                    "frac": ach / UPDATE_PEAK, "traffic": measured_traffic(),
+                    "achieved": ach * OPS_PER_UPDATE / 1e12, "peak": FP32_VECTOR_PEAK_FLOPS / 1e12,
+                    "unit": "TFLOP/s", "frac": ach * OPS_PER_UPDATE / FP32_VECTOR_PEAK_FLOPS,
+                    "traffic": measured_traffic(),
+                    "ops_per_update": OPS_PER_UPDATE,
                     "traffic_unit": "bytes per bulk launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                     "copy-calibrated)",
                     "avg_launch_us": per_launch_s * 1e6,
                     "updates_per_launch": per_launch_upd,
-                    "lane_ops_per_s": ach * MIN_INSTR_PER_UPDATE,
-                    "frac_vs_3.93e13_upd_per_s": ach / ONE_INSTR_64LANE_PEAK}
+                    "updates_per_s": ach}
+        if "panel" in phases and phases["panel"]["ms_per_step"] > 0:
+            p = phases["panel"]
+            s_ = tile
+            pbytes = (4.0 * (n - s_) * s_ + s_ * s_) * 4
+            us = p["ms_per_step"] / p["launches_per_step"] * 1e3
+            phases["panel"]["bytes_per_launch"] = pbytes
+            phases["panel"]["gb_per_s"] = pbytes / (us * 1e-6) / 1e9
+
+    probe = None
+    if not args.no_probe:
+        log("vector-ALU issue-rate probe")
+        probe = bench_valu_probe(torch, dev)
+        if roof:
+            ceil = probe["fp32_minplus_update_ceiling"]
+            roof["instruction_mix_ceiling"] = {
+                "updates_per_s": ceil, "frac": roof["updates_per_s"] / ceil,
+                "basis": "measured issue rate of the bulk's instruction mix (2 v_add_f32 + "
+                         "1 v_minimum3_f32 per two updates) on this GPU, this run"}
+
+    small = None
+    if not args.no_small:
+        log("n=512 solve latency and per-phase bandwidth")
+        small = bench_small(torch, fw, gen, dev)
+        log(f"n=512: {small['eager']['ms']:.3f} ms eager, {small['graph']['ms']:.3f} ms graph")
 
     maxmin = None
     if not args.no_maxmin:
@@ -627,19 +799,20 @@ def main():
     serving = None
     if not args.no_serving:
         log(f"serving: {args.serve_rate:.0f} req/s for {args.serve_seconds:.1f} s")
-        serving = bench_serving(torch, fw, gen, dev, args.serve_seconds, args.serve_rate)
+        serving = bench_serving(torch, fw, gen, dev, args.serve_seconds, args.serve_rate,
+                                args.serve_uncapped_seconds, args.serve_point_seconds)
         a = serving["at_rate"]
-        log(f"serving: {a['solves_per_s']:.0f} solves/s, p50 {a['p50_ms']:.1f} ms, "
+        log(f"serving, queue cap {QUEUE_CAP}: {a['solves_per_s']:.0f} solves/s, "
+            f"{a['refused']} of {a['requests']} refused, p50 {a['p50_ms']:.1f} ms, "
             f"p99 {a['p99_ms']:.1f} ms at {args.serve_rate:.0f} req/s offered")
-        c = serving[f"at_rate_queue_cap_{QUEUE_CAP}"]
-        log(f"serving, queue cap {QUEUE_CAP}: {c['solves_per_s']:.0f} solves/s, "
-            f"{c['refused']} of {c['requests']} refused, p50 {c['p50_ms']:.1f} ms, "
-            f"p99 {c['p99_ms']:.1f} ms")
+        for k in ("at_0.5x_capacity", "at_0.9x_capacity"):
+            c = serving[k]
+            log(f"serving {k}: p50 {c['p50_ms']:.1f} ms, p99 {c['p99_ms']:.1f} ms")
 
     cpu = None
     if not args.no_cpu:
         log(f"cpu baseline: {args.cpu_ksteps} oracle k-iterations")
-        cpu = cpu_baseline(W, min(args.cpu_ksteps, n))
+        cpu = cpu_baseline(W, min(args.cpu_ksteps, n), min(args.cpu_ksteps_one_core, n))
 
     out = {
         "metric": "n^3 cell-updates/s at n=16384 fp32 (% VALU peak); batched graphs/s; p99 latency",
@@ -649,9 +822,10 @@ def main():
         "config": {"workload": f"single dense directed graph n={n} fp32, edge prob 0.3, "
                                f"integer weights [1,1000], +INF absent",
                    "n": n, "tile": tile, "global_batch": 1, "parallelism": "single-gpu"},
-        "frac_of_update_peak": value / UPDATE_PEAK,
+        "frac_of_fp32_vector_peak": value * OPS_PER_UPDATE / FP32_VECTOR_PEAK_FLOPS,
         "check": "ok" if ok else "mismatch",
-        "phases": phases, "roofline": roof, "cpu_baseline": cpu, "negative_int32_pred": negative, "maxmin": maxmin,
+        "phases": phases, "roofline": roof, "cpu_baseline": cpu, "valu_probe": probe,
+        "small_n512": small, "negative_int32_pred": negative, "maxmin": maxmin,
         "transitive_closure": closure, "ladder": ladder,
         "batched": batched,
         "serving": serving,
