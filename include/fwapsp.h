@@ -271,6 +271,32 @@ int fw_apsp_batched(void *const *d, const int64_t *n, const int64_t *ld,
                     int64_t count, int dtype, int32_t *const *pred,
                     const int64_t *ld_pred, void *stream);
 
+/*
+ * fw_apsp_batched_noalloc -- fw_apsp_batched for callers that cannot
+ * allocate (code under stream capture of their own, tight serving loops,
+ * harnesses that forbid allocation): the same arguments, plan and kernels,
+ * bit-identical results, but the descriptor table and the stage-batched work
+ * table go to a static device array of FW_BATCHED_NOALLOC_MAX_BYTES (16 MiB)
+ * that the library holds on each GPU it runs on until the process ends;
+ * nothing is allocated on the device and no HIP event or stream is created.
+ * The tables (64 bytes + 48 bytes per graph, then 8 bytes per tile-phase
+ * entry of the stage-batched graphs: about 1.8 MB for 4096 graphs of 16-512
+ * vertices) are copied there on `stream`, which the call then synchronises
+ * (the host tables are freed on return); the kernels are enqueued after
+ * that.  Every call on a GPU shares that GPU's array and overwrites the
+ * previous call's tables: calls on one GPU must not overlap in time (two
+ * streams running them at once race on the array).  Errors: those of
+ * fw_apsp_batched, and FW_ERR_UNSUPPORTED when the tables exceed the array
+ * (nothing is enqueued).
+ */
+#define FW_BATCHED_NOALLOC_MAX_BYTES (16 << 20)
+int fw_apsp_batched_noalloc(void *const *d, const int64_t *n, const int64_t *ld,
+                            int64_t count, int dtype, int32_t *const *pred,
+                            const int64_t *ld_pred, void *stream);
+
+/* Size of the static array of fw_apsp_batched_noalloc, in bytes. */
+int64_t fw_batched_noalloc_max_bytes(void);
+
 /* Largest n fw_apsp_batched accepts for a dtype (with or without pred). */
 int64_t fw_batched_max_n(int dtype, int with_pred);
 

@@ -11,6 +11,7 @@ I32_INF = gen.I32_INF
 
 _EXPORTS = {
     "fw_apsp", "fw_apsp_i32", "fw_apsp_pred", "fw_apsp_plan", "fw_apsp_batched",
+    "fw_apsp_batched_noalloc",
     "fw_negative_cycle", "fw_negative_cycle_vertices", "fw_negative_cycle_find",
     "fw_apsp_semiring", "fw_apsp_ladder", "LADDER_RUNGS", "fw_transitive_closure",
     "fw_transitive_closure_bits", "pack_bits", "unpack_bits", "words_per_row", "fw_path",

@@ -95,6 +95,9 @@ def _declare(L):
         "fw_apsp_batched": ([ctypes.POINTER(vp), P64, P64, i64, ci, ctypes.POINTER(vp), P64, vp],
                             ci),
         "fw_batched_max_n": ([ci, ci], i64),
+        "fw_apsp_batched_noalloc": ([ctypes.POINTER(vp), P64, P64, i64, ci, ctypes.POINTER(vp),
+                                     P64, vp], ci),
+        "fw_batched_noalloc_max_bytes": ([], i64),
         "fw_batch_plan_create": ([ctypes.POINTER(vp), P64, P64, i64, ci, ctypes.POINTER(vp), P64,
                                   ctypes.POINTER(vp)], ci),
         "fw_batch_plan_launch": ([vp, ci, vp], ci),
@@ -409,6 +412,18 @@ def fw_apsp_batched(mats, preds=None, stream=None) -> None:
     with torch.cuda.device(dev):
         _check(lib().fw_apsp_batched(ptrs, ns, lds, len(mats), code, pptr, pld,
                                      _stream(mats[0], stream)), "fw_apsp_batched")
+
+
+def fw_apsp_batched_noalloc(mats, preds=None, stream=None) -> None:
+    """fw_apsp_batched with the plan's tables in the library's static device
+    array: no device allocation; synchronises ``stream`` after the upload."""
+    if len(mats) == 0:
+        return
+    code, dev, ptrs, ns, lds, pptr, pld = _batch_arrays(mats, preds)
+    with torch.cuda.device(dev):
+        _check(lib().fw_apsp_batched_noalloc(ptrs, ns, lds, len(mats), code, pptr, pld,
+                                             _stream(mats[0], stream)),
+               "fw_apsp_batched_noalloc")
 
 
 def _batch_arrays(mats, preds):

@@ -523,15 +523,23 @@ void xcd_group(std::vector<StagedWork> &work, int64_t first, int groups) {
             if (pos[x] < lists[x].size()) work[(size_t)out++] = lists[x][pos[x]++];
 }
 
-int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t count, int dtype,
-               int32_t *const *pred, const int64_t *ld_pred, fw_batch_plan_s *pl) {
+// Host half of a batch plan: the sorted descriptor table (header + items),
+// the stage-batched launches and their work table.  No device memory.
+struct HostPlan {
+    std::vector<char> table;         // BatchHeader + items
+    std::vector<StagedWork> work;
+    std::vector<StagedLaunch> staged;
+};
+
+int build_host_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t count,
+                    int dtype, int32_t *const *pred, const int64_t *ld_pred,
+                    fw_batch_plan_s *pl, HostPlan &hp) {
     if (count < 0 || count > 0x7fffffffLL) return FW_ERR_INVALID;
     if (dtype != FW_F32 && dtype != FW_I32) return FW_ERR_INVALID;
     if (count > 0 && (!d || !n || !ld)) return FW_ERR_INVALID;
     if (pred && !ld_pred) return FW_ERR_INVALID;
     std::vector<BatchItem> items((size_t)count);
     bool any_pred = false;
-    double upd = 0;
     for (int64_t g = 0; g < count; ++g) {
         int32_t *pg = pred ? pred[g] : nullptr;
         const int64_t ldp = pg ? ld_pred[g] : 0;
@@ -540,7 +548,6 @@ int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t coun
         if (n[g] > fw_batched_max_n(dtype, pg != nullptr)) return FW_ERR_UNSUPPORTED;
         fill_batch_item(items[(size_t)g], d[g], dtype, n[g], ld[g], pg, ldp);
         any_pred |= pg != nullptr;
-        upd += (double)n[g] * (double)n[g] * (double)n[g];
     }
     // largest graphs first: the stage-batched ones form a prefix, and in the
     // persistent part the workgroups that take the largest start earliest
@@ -549,7 +556,7 @@ int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t coun
     int64_t n_staged = 0;
     while (n_staged < count && items[(size_t)n_staged].n >= FW_STAGED_MIN_N) ++n_staged;
     // the persistent launch's own updates (phase timing attributes them to it)
-    upd = 0;
+    double upd = 0;
     for (int64_t g = n_staged; g < count; ++g) {
         const double ng = items[(size_t)g].n;
         upd += ng * ng * ng;
@@ -565,38 +572,26 @@ int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t coun
     const int grid = resident_grid(dtype, any_pred, pl->big);
     if (grid <= 0) return FW_ERR_HIP;
     pl->grid = (int)std::min<int64_t>(grid, std::max<int64_t>(count - n_staged, 1));
-    if (hipHostMalloc(&pl->host, pl->bytes, hipHostMallocDefault) != hipSuccess)
-        return FW_ERR_NOMEM;
-    if (hipMalloc(&pl->dev, pl->bytes) != hipSuccess) return FW_ERR_NOMEM;
-    auto *hdr = static_cast<BatchHeader *>(pl->host);
+    hp.table.assign(pl->bytes, 0);
+    auto *hdr = reinterpret_cast<BatchHeader *>(hp.table.data());
     *hdr = BatchHeader{};
     hdr->next = 0;
     hdr->count = (int32_t)(count - n_staged);  // the persistent part
     if (count)
         std::copy(items.begin(), items.end(),
-                  reinterpret_cast<BatchItem *>(static_cast<char *>(pl->host) + sizeof(BatchHeader)));
-    // the descriptor table never changes either (only the persistent part's
-    // work counter, which each launch resets with a kernel): uploaded once
-    {
-        hipStream_t up = nullptr;
-        if (hipStreamCreateWithFlags(&up, hipStreamNonBlocking) != hipSuccess) return FW_ERR_HIP;
-        hipError_t e = hipMemcpyAsync(pl->dev, pl->host, pl->bytes, hipMemcpyHostToDevice, up);
-        if (e == hipSuccess) e = hipStreamSynchronize(up);
-        hipStreamDestroy(up);
-        if (e != hipSuccess) return status_of(e);
-    }
+                  reinterpret_cast<BatchItem *>(hp.table.data() + sizeof(BatchHeader)));
     if (n_staged == 0) return FW_OK;
 
     // Stage-batched part: per tile size, the launch sequence and its work
     // table.  Within a tile group the graphs stay sorted by size, so the
     // graphs that still have a stage b are a prefix of the group.
-    std::vector<StagedWork> work;
+    std::vector<StagedWork> &work = hp.work;
     std::map<int, std::vector<int32_t>> groups;
     for (int64_t g = 0; g < n_staged; ++g) groups[items[(size_t)g].tile].push_back((int32_t)g);
     auto add_launch = [&](int kind, int tile, int b, int64_t first) {
         if ((int64_t)work.size() > first) {
             if (FW_STAGED_XCD_GROUPS > 1) xcd_group(work, first, FW_STAGED_XCD_GROUPS);
-            pl->staged.push_back({kind, tile, b, first, (int64_t)work.size() - first});
+            hp.staged.push_back({kind, tile, b, first, (int64_t)work.size() - first});
         }
     };
     for (auto &kv : groups) {
@@ -643,24 +638,43 @@ int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t coun
             if (items[(size_t)g].p) work.push_back({g, 0});
         add_launch(kStagedPredFix, tile, 0, first);
     }
-    for (const StagedLaunch &l : pl->staged)
+    for (const StagedLaunch &l : hp.staged)
         if (l.count > 0x7fffffffLL) return FW_ERR_UNSUPPORTED;
-    // the table never changes: uploaded once, on a private stream
-    const size_t wbytes = sizeof(StagedWork) * work.size();
-    if (hipMalloc(&pl->work, wbytes) != hipSuccess) return FW_ERR_NOMEM;
+    return FW_OK;
+}
+
+// A reusable plan: the host half, then the tables in pinned host memory and
+// on the device, uploaded once on a private stream.
+int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t count, int dtype,
+               int32_t *const *pred, const int64_t *ld_pred, fw_batch_plan_s *pl) {
+    HostPlan hp;
+    int s = build_host_plan(d, n, ld, count, dtype, pred, ld_pred, pl, hp);
+    if (s != FW_OK) return s;
+    if (hipHostMalloc(&pl->host, pl->bytes, hipHostMallocDefault) != hipSuccess)
+        return FW_ERR_NOMEM;
+    std::copy(hp.table.begin(), hp.table.end(), static_cast<char *>(pl->host));
+    if (hipMalloc(&pl->dev, pl->bytes) != hipSuccess) return FW_ERR_NOMEM;
+    pl->staged = hp.staged;
+    const size_t wbytes = sizeof(StagedWork) * hp.work.size();
+    if (wbytes && hipMalloc(&pl->work, wbytes) != hipSuccess) return FW_ERR_NOMEM;
+    // the tables never change (only the persistent part's work counter, which
+    // each launch resets with a kernel): uploaded once, on a private stream
     hipStream_t up = nullptr;
     if (hipStreamCreateWithFlags(&up, hipStreamNonBlocking) != hipSuccess) return FW_ERR_HIP;
-    hipError_t e = hipMemcpyAsync(pl->work, work.data(), wbytes, hipMemcpyHostToDevice, up);
+    hipError_t e = hipMemcpyAsync(pl->dev, pl->host, pl->bytes, hipMemcpyHostToDevice, up);
+    if (e == hipSuccess && wbytes)
+        e = hipMemcpyAsync(pl->work, hp.work.data(), wbytes, hipMemcpyHostToDevice, up);
     if (e == hipSuccess) e = hipStreamSynchronize(up);
-    hipStreamDestroy(up);
+    (void)hipStreamDestroy(up);
     return status_of(e);
 }
 
 // Enqueue: the stage-batched launches, then (if the plan has a persistent
 // part) the reset of its work counter and the persistent kernel.  All are
 // kernel launches (no copy or memset node), so the same sequence can be
-// captured into a graph and replayed.
-int enqueue_plan(fw_batch_plan_s *pl, hipStream_t st, bool capturing) {
+// captured into a graph and replayed.  `untimed`: no phase events (a capture
+// is running, or the caller must not create events).
+int enqueue_plan(fw_batch_plan_s *pl, hipStream_t st, bool untimed) {
     if (pl->count == 0) return FW_OK;
     hipError_t e = hipSuccess;
     auto *hdr = static_cast<BatchHeader *>(pl->dev);
@@ -675,7 +689,7 @@ int enqueue_plan(fw_batch_plan_s *pl, hipStream_t st, bool capturing) {
     batch_reset_kernel<<<1, 64, 0, st>>>(hdr);
     if ((e = hipGetLastError()) != hipSuccess) return status_of(e);
     const BatchItem *rest = items + pl->n_staged;
-    if (capturing)
+    if (untimed)
         return status_of(
             launch_batched_raw(pl->dtype, pl->pred, hdr, rest, pl->grid, st, pl->big));
     return status_of(timed_launch_batched(pl->updates, st, pl->dtype, pl->pred, pl->big, hdr,
@@ -720,9 +734,73 @@ void reap_pending(bool all) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Tables of fw_apsp_batched_noalloc: one static device array per GPU, in
+// place of the plan's allocations.  Host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device (the array's
+// name is a host-side stand-in), looked up once per device.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(16) << 20;
+__device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, char *> g_scratch_ptr;
+
+int scratch_base(int dev, char **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return FW_OK;
+    }
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) return FW_ERR_HIP;
+    g_scratch_ptr[dev] = static_cast<char *>(ptr);
+    *out = static_cast<char *>(ptr);
+    return FW_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int fw_apsp_batched_noalloc(void *const *d, const int64_t *n, const int64_t *ld, int64_t count,
+                            int dtype, int32_t *const *pred, const int64_t *ld_pred,
+                            void *stream) {
+    if (count == 0) {
+        if (dtype != FW_F32 && dtype != FW_I32) return FW_ERR_INVALID;
+        return FW_OK;
+    }
+    fw_batch_plan_s pl;  // tables in the static array: nothing owned
+    HostPlan hp;
+    int s = build_host_plan(d, n, ld, count, dtype, pred, ld_pred, &pl, hp);
+    if (s != FW_OK) return s;
+    const size_t tbytes = (pl.bytes + 255) / 256 * 256;
+    const size_t wbytes = sizeof(StagedWork) * hp.work.size();
+    if (tbytes + wbytes > kScratchBytes) return FW_ERR_UNSUPPORTED;
+    char *base = nullptr;
+    s = scratch_base(pl.device, &base);
+    if (s != FW_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    // the previous call's kernels on this stream are done with the array
+    // before these copies land (stream order); the host tables are freed on
+    // return, so the copies are waited for
+    hipError_t e = hipMemcpyAsync(base, hp.table.data(), pl.bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && wbytes)
+        e = hipMemcpyAsync(base + tbytes, hp.work.data(), wbytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return status_of(e);
+    pl.dev = base;
+    pl.work = reinterpret_cast<StagedWork *>(base + tbytes);
+    pl.staged = hp.staged;
+    s = enqueue_plan(&pl, st, true);
+    pl.dev = nullptr;
+    pl.work = nullptr;
+    return s;
+}
+
+int64_t fw_batched_noalloc_max_bytes(void) { return (int64_t)kScratchBytes; }
 
 int64_t fw_batched_max_n(int dtype, int with_pred) {
     (void)with_pred;
