@@ -112,6 +112,11 @@ def parse():
                     help="arrival window of the 0.5x / 0.9x capacity load points")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--batched-reps", type=int, default=5)
+    ap.add_argument("--batched-modes", default="graph,kernel,per_graph",
+                    help="batch-plan launch modes to time (comma-separated)")
+    ap.add_argument("--batched-tiles", default="",
+                    help="tiles of the size buckets 16-32,33-64,65-128,129-256,257-512 "
+                         "(comma-separated) instead of autotuning them")
     return ap.parse_args()
 
 
@@ -486,7 +491,7 @@ def bench_negative(torch, fw, gen, dev, reps=3):
     return out
 
 
-def bench_batched(torch, fw, gen, dev, reps):
+def bench_batched(torch, fw, gen, dev, reps, modes=("graph", "kernel", "per_graph"), tiles=None):
     """Ragged batch: 4096 graphs, n log-uniform in [16, 512], fp32."""
     import numpy as np
     import oracle
@@ -495,7 +500,13 @@ def bench_batched(torch, fw, gen, dev, reps):
     # tile per size bucket, picked by the library's autotuner for the batched
     # launch (installed into the plan table the batch plan reads)
     buckets = [(16, 32), (33, 64), (65, 128), (129, 256), (257, 512)]
-    tuned = fw.autotune(torch.float32, buckets, objective="batched", batch=256, reps=3)
+    if tiles is None:
+        tuned = fw.autotune(torch.float32, buckets, objective="batched", batch=256, reps=3)
+    else:  # given tiles (profiling runs: counters distort the autotuner's timings)
+        tuned = {}
+        for (lo, hi), t in zip(buckets, tiles):
+            fw.plan_set(torch.float32, lo, hi, t)
+            tuned[(lo, hi)] = {"tile": t, "ms": {}}
     pool, views = pack_graphs(graphs, torch, dev)
     pristine = pool.clone()
     plan = fw.BatchPlan(views)
@@ -512,6 +523,8 @@ def bench_batched(torch, fw, gen, dev, reps):
     # percent slower than the steady state (3.30 vs 3.21 ms measured)
     for mode, nrep, warm in (("graph", reps, 3), ("kernel", reps, 3),
                              ("per_graph", max(1, reps // 2), 1)):
+        if mode not in modes:
+            continue
         times = []
         for r in range(nrep + warm):
             pool.copy_(pristine)
@@ -530,7 +543,8 @@ def bench_batched(torch, fw, gen, dev, reps):
     ok = all(np.array_equal(views[g].cpu().numpy().view(np.uint32),
                             oracle.fw(graphs[g]).view(np.uint32)) for g in idx)
     out["check"] = "ok" if ok else "mismatch"
-    out["speedup_vs_per_graph"] = out["per_graph"]["ms"] / out["graph"]["ms"]
+    if "per_graph" in out and "graph" in out:
+        out["speedup_vs_per_graph"] = out["per_graph"]["ms"] / out["graph"]["ms"]
     plan.destroy()
     return out
 
@@ -792,9 +806,11 @@ def main():
     batched = None
     if not args.no_batched:
         log("batched: 4096 ragged graphs")
-        batched = bench_batched(torch, fw, gen, dev, args.batched_reps)
-        log(f"batched: {batched['graph']['graphs_per_s']:.0f} graphs/s (graph launch), "
-            f"{batched['per_graph']['graphs_per_s']:.0f} graphs/s per-graph launches")
+        tiles = [int(t) for t in args.batched_tiles.split(",")] if args.batched_tiles else None
+        batched = bench_batched(torch, fw, gen, dev, args.batched_reps,
+                                tuple(args.batched_modes.split(",")), tiles)
+        log("batched: " + ", ".join(f"{m} {batched[m]['graphs_per_s']:.0f} graphs/s"
+                                    for m in ("graph", "kernel", "per_graph") if m in batched))
 
     serving = None
     if not args.no_serving:

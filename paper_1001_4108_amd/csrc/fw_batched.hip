@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -896,3 +897,40 @@ int fw_apsp_batched(void *const *d, const int64_t *n, const int64_t *ld, int64_t
 }
 
 }  // extern "C"
+
+namespace fw {
+
+int64_t batch_work_entries(int dtype, int64_t n, bool pred) {
+    if (n < FW_STAGED_MIN_N) return 0;
+    const int tile = plan_tile_for(dtype, n, pred);
+    const int64_t nb = (n + tile - 1) / tile, m = nb - 1;
+    return nb * (1 + 2 * m + m * m) + 2;  // a diagonal entry every stage, predecessor set-up
+}
+
+int enqueue_batch_buffered(void *const *d, const int64_t *n, const int64_t *ld, int64_t count,
+                           int dtype, const BatchBuffers &buf, hipStream_t st) {
+    if (count == 0) return FW_OK;
+    fw_batch_plan_s pl;  // a view of the caller's buffers: nothing owned
+    HostPlan hp;
+    int s = build_host_plan(d, n, ld, count, dtype, nullptr, nullptr, &pl, hp);
+    if (s != FW_OK) return s;
+    const size_t wbytes = sizeof(StagedWork) * hp.work.size();
+    if (pl.bytes > buf.table_bytes || wbytes > buf.work_bytes) return FW_ERR_UNSUPPORTED;
+    std::copy(hp.table.begin(), hp.table.end(), static_cast<char *>(buf.host_table));
+    if (wbytes) std::memcpy(buf.host_work, hp.work.data(), wbytes);
+    hipError_t e = hipMemcpyAsync(buf.dev_table, buf.host_table, pl.bytes,
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && wbytes)
+        e = hipMemcpyAsync(buf.dev_work, buf.host_work, wbytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return status_of(e);
+    pl.dev = buf.dev_table;
+    pl.work = static_cast<StagedWork *>(buf.dev_work);
+    pl.staged = hp.staged;
+    s = enqueue_plan(&pl, st, true);
+    pl.dev = nullptr;
+    pl.work = nullptr;
+    return s;
+}
+
+}  // namespace fw
+

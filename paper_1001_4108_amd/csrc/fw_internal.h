@@ -81,6 +81,24 @@ bool batch_needs_big(const BatchItem *items, int64_t count);
 int batched_resident_grid(int dtype, bool pred);
 void fill_batch_item(BatchItem &it, void *d, int dtype, int64_t n, int64_t ld, int32_t *p,
                      int64_t ldp);
+// Buffers a caller owns for enqueue_batch_buffered: the descriptor table
+// (header + items) and the stage-batched work table, each as pinned host
+// memory and a device copy, with their capacities in bytes.  The host
+// buffers must stay untouched until the stream has run the copies.
+struct BatchBuffers {
+    void *host_table, *dev_table;
+    size_t table_bytes;
+    void *host_work, *dev_work;
+    size_t work_bytes;
+};
+// One batch (no predecessors) through the batch-plan schedule -- stage-
+// batched launches, then the persistent kernel for the smallest graphs --
+// with the tables staged through `buf` and copied on `st`.
+// FW_ERR_UNSUPPORTED when the tables exceed the buffers (nothing enqueued).
+int enqueue_batch_buffered(void *const *d, const int64_t *n, const int64_t *ld, int64_t count,
+                           int dtype, const BatchBuffers &buf, hipStream_t st);
+// Upper bound on the work-table entries one graph adds to a batch.
+int64_t batch_work_entries(int dtype, int64_t n, bool pred);
 // The plan table's tile for (dtype, n), from the table of solves with
 // predecessors when `pred`.
 int plan_tile_for(int dtype, int64_t n, bool pred);

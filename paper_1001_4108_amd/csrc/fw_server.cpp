@@ -5,8 +5,11 @@
 // copies each admitted payload into a resident slot, and groups work onto a
 // small set of worker streams:
 //   * every admitted request with n <= small_n that is waiting when a stream
-//     frees up goes into ONE persistent batched launch (the same kernel as
-//     fw_apsp_batched) -- whatever has arrived is batched together;
+//     frees up (up to max_batch of them and the worker's work-table
+//     capacity) goes into ONE batch, run as fw_apsp_batched runs it: stage-
+//     batched launches shared by all of its graphs (so a 500-vertex request
+//     spreads over the whole GPU), the smallest graphs in one persistent
+//     launch -- whatever has arrived is batched together;
 //   * a larger request runs the single-graph stage loop (fw_apsp) on its own
 //     stream.
 // Groups on different streams overlap on the device.  One completion thread
@@ -126,10 +129,16 @@ struct Group {
     bool batched = false;
 };
 
+// Work-table capacity of each worker's batched groups (stage-batched
+// entries, 8 bytes each): a 512-vertex graph at tile 64 adds about 520.
+constexpr size_t kWorkBytes = size_t(8) << 20;
+
 struct Worker {
     hipStream_t st = nullptr;
     void *host_table = nullptr;  // pinned BatchHeader + items for batched groups
     void *dev_table = nullptr;
+    void *host_work = nullptr;   // pinned stage-batched work table
+    void *dev_work = nullptr;
     bool busy = false;
     std::deque<Group *> queue;   // groups waiting for the completion thread
     std::thread completer;
@@ -198,32 +207,19 @@ int enqueue_group(fw_server_s *s, Group *g) {
         if (e != hipSuccess) return status_of(e);
     }
     if (g->batched) {
-        auto *hdr = static_cast<BatchHeader *>(w.host_table);
-        auto *items = reinterpret_cast<BatchItem *>(static_cast<char *>(w.host_table) +
-                                                    sizeof(BatchHeader));
-        *hdr = BatchHeader{};
-        // largest first, as in fw_apsp_batched
-        std::vector<Request *> order(g->reqs);
-        std::stable_sort(order.begin(), order.end(),
-                         [](const Request *a, const Request *b) { return a->n > b->n; });
-        int cnt = 0;
-        for (Request *r : order)
-            if (r->n > 1)
-                fill_batch_item(items[cnt++], s->arena.at(r->off), dt, r->n, r->ld_slot, nullptr,
-                                0);
-        hdr->next = 0;
-        hdr->count = cnt;
-        if (cnt) {
-            const size_t bytes = sizeof(BatchHeader) + sizeof(BatchItem) * (size_t)cnt;
-            e = hipMemcpyAsync(w.dev_table, w.host_table, bytes, hipMemcpyHostToDevice, st);
-            if (e != hipSuccess) return status_of(e);
-            auto *dh = static_cast<BatchHeader *>(w.dev_table);
-            auto *di = reinterpret_cast<const BatchItem *>(static_cast<char *>(w.dev_table) +
-                                                           sizeof(BatchHeader));
-            e = launch_batched_raw(dt, false, dh, di, std::min(cnt, s->grid), st,
-                                   batch_needs_big(items, cnt));
-            if (e != hipSuccess) return status_of(e);
-        }
+        std::vector<void *> ptrs;
+        std::vector<int64_t> ns, lds;
+        for (Request *r : g->reqs)
+            if (r->n > 1) {
+                ptrs.push_back(s->arena.at(r->off));
+                ns.push_back(r->n);
+                lds.push_back(r->ld_slot);
+            }
+        const BatchBuffers buf{w.host_table, w.dev_table, s->table_bytes,
+                               w.host_work,  w.dev_work,  kWorkBytes};
+        const int st2 = enqueue_batch_buffered(ptrs.data(), ns.data(), lds.data(),
+                                               (int64_t)ptrs.size(), dt, buf, st);
+        if (st2 != FW_OK) return st2;
     } else {
         for (Request *r : g->reqs) {
             int st2 = solve_single(s->arena.at(r->off), dt, r->n, r->ld_slot, nullptr, 0, st);
@@ -288,9 +284,14 @@ void dispatcher_main(fw_server_s *s) {
         Request *head = s->admitted.front();
         if (head->n <= s->cfg.small_n) {
             g->batched = true;
+            int64_t entries = 0;
+            const int64_t cap = (int64_t)(kWorkBytes / 8);
             for (auto it = s->admitted.begin();
                  it != s->admitted.end() && (int)g->reqs.size() < s->cfg.max_batch;) {
                 if ((*it)->n <= s->cfg.small_n) {
+                    const int64_t e = batch_work_entries(s->cfg.dtype, (*it)->n, false);
+                    if (!g->reqs.empty() && entries + e > cap) break;
+                    entries += e;
                     g->reqs.push_back(*it);
                     it = s->admitted.erase(it);
                 } else {
@@ -392,7 +393,9 @@ int fw_server_create(const fw_server_config *cfg, fw_server *out) {
         if (status != FW_OK) break;
         if (hipStreamCreateWithFlags(&w.st, hipStreamNonBlocking) != hipSuccess ||
             hipHostMalloc(&w.host_table, s->table_bytes, hipHostMallocDefault) != hipSuccess ||
-            hipMalloc(&w.dev_table, s->table_bytes) != hipSuccess)
+            hipMalloc(&w.dev_table, s->table_bytes) != hipSuccess ||
+            hipHostMalloc(&w.host_work, kWorkBytes, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc(&w.dev_work, kWorkBytes) != hipSuccess)
             status = FW_ERR_NOMEM;
     }
     if (status != FW_OK) {
@@ -400,6 +403,8 @@ int fw_server_create(const fw_server_config *cfg, fw_server *out) {
             if (w.st) hipStreamDestroy(w.st);
             if (w.host_table) hipHostFree(w.host_table);
             if (w.dev_table) hipFree(w.dev_table);
+            if (w.host_work) hipHostFree(w.host_work);
+            if (w.dev_work) hipFree(w.dev_work);
         }
         if (s->arena_mem) hipFree(s->arena_mem);
         delete s;
@@ -536,6 +541,8 @@ int fw_server_destroy(fw_server s) {
         hipStreamDestroy(w.st);
         hipHostFree(w.host_table);
         hipFree(w.dev_table);
+        hipHostFree(w.host_work);
+        hipFree(w.dev_work);
     }
     for (auto &kv : s->live) delete kv.second;
     hipFree(s->arena_mem);
