@@ -88,6 +88,8 @@ def parse():
     ap.add_argument("--cpu-ksteps-one-core", type=int, default=96,
                     help="k-iterations of the oracle timed on one thread")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-captured", action="store_true",
+                    help="skip timing the solve as one captured-graph launch")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the vector-ALU issue-rate probe")
     ap.add_argument("--no-small", action="store_true",
@@ -762,6 +764,25 @@ def main():
             phases["panel"]["bytes_per_launch"] = pbytes
             phases["panel"]["gb_per_s"] = pbytes / (us * 1e-6) / 1e9
 
+    # the same solve as one captured-graph launch of a solve plan (the stage
+    # loop captured once; same step: pristine refresh + solve)
+    captured = None
+    if not args.no_captured:
+        plan = fw.SolvePlan(work)
+        work.copy_(pristine)
+        plan.launch("graph")
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            work.copy_(pristine)
+            plan.launch("graph")
+        torch.cuda.synchronize(dev)
+        cms = (time.perf_counter() - t0) * 1e3 / args.steps
+        captured = {"ms_per_step": cms, "updates_per_s": float(n) ** 3 / (cms / 1e3),
+                    "launches_captured": 2 * (n // tile)}
+        plan.destroy()
+        log(f"captured stage loop: {cms:.2f} ms per step (eager {ms_per_step:.2f})")
+
     probe = None
     if not args.no_probe:
         log("vector-ALU issue-rate probe")
@@ -840,7 +861,8 @@ def main():
                    "n": n, "tile": tile, "global_batch": 1, "parallelism": "single-gpu"},
         "frac_of_fp32_vector_peak": value * OPS_PER_UPDATE / FP32_VECTOR_PEAK_FLOPS,
         "check": "ok" if ok else "mismatch",
-        "phases": phases, "roofline": roof, "cpu_baseline": cpu, "valu_probe": probe,
+        "phases": phases, "captured_graph": captured, "roofline": roof, "cpu_baseline": cpu,
+        "valu_probe": probe,
         "small_n512": small, "negative_int32_pred": negative, "maxmin": maxmin,
         "transitive_closure": closure, "ladder": ladder,
         "batched": batched,

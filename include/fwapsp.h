@@ -428,9 +428,10 @@ int fw_negative_cycle_vertices(const void *d, int dtype, int64_t n, int64_t ld,
                                int32_t *list_dev, int32_t *count_dev, void *stream);
 
 /*
- * fw_negative_cycle_find -- one negative cycle reachable from vertex v and
- * back, given v with d_vv < 0 (from fw_negative_cycle_vertices).  Host call;
- * every pointer is HOST memory.
+ * fw_negative_cycle_find -- one negative cycle reachable from vertex v, for
+ * v with d_vv < 0 (from fw_negative_cycle_vertices: a negative closed walk
+ * runs through v, so one is reachable).  Host call; every pointer is HOST
+ * memory.
  *   w_host     the ORIGINAL weights (n x n, leading dimension ld, fw_dtype
  *              `dtype`), the matrix before the solve overwrote it.
  *   pred_host  NULL, or the predecessor matrix of the same solve

@@ -203,3 +203,32 @@ def test_autotune_argument_validation():
     assert L.fw_autotune(0, lo, hi, 1, 2, 1, 1, out, None) == 1   # objective
     assert L.fw_autotune(0, lo, hi, 1, 1, 0, 1, out, None) == 1   # empty batch
     assert L.fw_autotune(0, lo, hi, 0, 0, 1, 1, out, None) == 1   # no buckets
+
+
+def test_negative_cycle_find_on_random_graphs():
+    """On random graphs with negative cycles (host only): for every vertex v
+    whose oracle distance d_vv is negative (a negative closed walk through v),
+    Bellman-Ford from v returns a simple cycle of real edges with negative
+    weight.  Graphs stay small enough (n <= 12, weights >= -4) that the
+    oracle's values cannot overflow int32."""
+    import oracle
+    rng = np.random.default_rng(77)
+    M = B.I32_INF
+    found_any = 0
+    for trial in range(80):
+        n = int(rng.integers(3, 13))
+        W = np.where(rng.random((n, n)) < rng.uniform(0.1, 0.5),
+                     rng.integers(-4, 20, (n, n)), M).astype(np.int32)
+        np.fill_diagonal(W, 0)
+        D = oracle.fw(W)
+        for v in range(n):
+            cyc, _ = B.fw_negative_cycle_find(W, v)
+            if D[v, v] < 0:
+                assert cyc, (trial, v)
+                m = len(cyc)
+                assert all(W[cyc[t], cyc[(t + 1) % m]] != M and cyc[t] != cyc[(t + 1) % m]
+                           for t in range(m))
+                assert _cycle_weight(W, cyc) < 0
+                assert len(set(cyc)) == m  # a simple cycle
+                found_any += 1
+    assert found_any > 20
