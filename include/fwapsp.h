@@ -104,6 +104,15 @@ int fw_apsp_i32(int32_t *d, int64_t n, int64_t ld, void *stream);
  *              closed walk that made d_ii negative (see
  *              fw_negative_cycle_find); the other entries are then as
  *              computed.
+ * int32 with pred, 2 <= n <= 16383: the (distance, last hop) pairs are first
+ * swept as 32-bit keys (distance * 2^14 + last hop) held in `pred`, at the
+ * cost of the distances-only sweep; this takes 8n + 16 bytes of
+ * stream-ordered device memory (hipMallocAsync on `stream`, freed on it).
+ * When some distance met during that sweep has |d| >= 2^14, or a diagonal
+ * entry ends negative, the 64-bit form already queued behind it (each launch
+ * gated on a device flag) solves again from the untouched d.  The results are
+ * the same in every case, so the choice is invisible except in time
+ * (fw_pred_fallbacks counts the second sweeps).
  * Errors: as fw_apsp, plus FW_ERR_INVALID for a bad dtype or, with pred
  * non-NULL, ld_pred < n or n*ld_pred overflowing int64.
  */
@@ -473,7 +482,10 @@ int64_t fw_path(const int32_t *pred_host, int64_t n, int64_t ld_pred, int64_t i,
  *                         choice at creation.  Nothing is enqueued; the
  *                         matrices must stay allocated for the plan's
  *                         lifetime and are re-solved in place on every
- *                         launch.
+ *                         launch.  An int32 plan with predecessors allocates
+ *                         the keyed sweep's 8n + 16 bytes of scratch here
+ *                         (FW_ERR_NOMEM if it cannot); its launches then
+ *                         allocate nothing.
  *   fw_solve_plan_launch  mode 0: the solve as eager launches on `stream`
  *                         (fw_apsp_plan); mode 1: on the first call the
  *                         launches are captured into a hipGraph on a stream
@@ -502,10 +514,12 @@ int fw_solve_plan_destroy(fw_solve_plan plan);
  * writes, per phase kind, the summed kernel time in ms and the launch count
  * (kinds: 0 = diagonal tile, 1 = panels, 2 = bulk tiles (with the next
  * diagonal tile where the bulk launch closes it), 3 = predecessor
- * init/fix-up, 4 = batched persistent kernel; fw_transitive_closure_bits:
+ * init/fix-up (and the key packing and unpacking of int32 solves with
+ * predecessors), 4 = batched persistent kernel; fw_transitive_closure_bits:
  * 5 = stage 0's diagonal block, 6 = panels, 7 = bulk with the next diagonal
- * block); it returns the number of kinds written and clears the
- * accumulators.
+ * block; 8 = the gated 64-bit predecessor sweep behind a keyed one, every
+ * launch whether it ran or found its gate closed); it returns the number of
+ * kinds written and clears the accumulators.
  */
 int fw_profile_enable(int on);
 int fw_profile_read(double *ms, int64_t *launches, int cap);
@@ -513,6 +527,14 @@ int fw_profile_read(double *ms, int64_t *launches, int cap);
 /* Work counters of the last fw_profile_read window: algorithmic cell updates
  * per kind (the n^3 tasks of section 1 split by phase). */
 int fw_profile_updates(double *updates, int cap);
+
+/*
+ * fw_pred_fallbacks -- how many int32 solves with predecessors on the current
+ * device have run their 64-bit sweep because the 32-bit keyed one gave up
+ * (see fw_apsp_pred), since the library was loaded.  Synchronises the device;
+ * -1 when the count cannot be read.
+ */
+int64_t fw_pred_fallbacks(void);
 
 #ifdef __cplusplus
 }

@@ -17,6 +17,7 @@ _EXPORTS = {
     "fw_transitive_closure_bits", "pack_bits", "unpack_bits", "words_per_row", "fw_path",
     "plan_tiles", "plan_tile", "plan_set", "plan_reset", "autotune", "save_plan", "load_plan",
     "batched_max_n", "BatchPlan", "SolvePlan", "Server", "profile_enable", "profile_read",
+    "pred_fallbacks",
     "FwError", "lib", "LIB_PATH",
 }
 

@@ -105,6 +105,7 @@ def _declare(L):
         "fw_batch_plan_grid": ([vp], i64),
         "fw_negative_cycle": ([vp, ci, i64, i64, vp, vp], ci),
         "fw_negative_cycle_vertices": ([vp, ci, i64, i64, vp, vp, vp], ci),
+        "fw_pred_fallbacks": ([], i64),
         "fw_negative_cycle_find": ([vp, ci, i64, i64, vp, i64, i64, P64, i64,
                                     ctypes.POINTER(ci)], i64),
         "fw_solve_plan_create": ([vp, ci, i64, i64, vp, i64, ci, ctypes.POINTER(vp)], ci),
@@ -615,7 +616,17 @@ def profile_enable(on: bool = True) -> None:
     lib().fw_profile_enable(1 if on else 0)
 
 
-KINDS = ("diag", "panel", "bulk", "pred", "batched", "bits_diag", "bits_panel", "bits_bulk")
+KINDS = ("diag", "panel", "bulk", "pred", "batched", "bits_diag", "bits_panel", "bits_bulk",
+         "pred_fallback")
+
+
+def pred_fallbacks() -> int:
+    """Number of int32 solves with predecessors on the current device whose
+    32-bit keyed sweep gave up and ran the 64-bit sweep (synchronises)."""
+    v = lib().fw_pred_fallbacks()
+    if v < 0:
+        raise FwError(2, "fw_pred_fallbacks")
+    return int(v)
 
 
 def profile_read():

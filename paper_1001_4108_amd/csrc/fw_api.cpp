@@ -167,17 +167,22 @@ int validate(const void *d, int dtype, int64_t n, int64_t ld, const int32_t *pre
 // its own launch only where the previous bulk launch did not close it.
 // `capturing`: the launches are being recorded into a hipGraph, so no phase
 // events are recorded around them (an event recorded during a capture belongs
-// to that capture and is not reused outside it).
+// to that capture and is not reused outside it).  `flag`: the keyed sweep's
+// range flag (sr == kKey).  `gate`: every launch runs only if *gate != 0 (the
+// 64-bit predecessor sweep behind a keyed one; timed as kPredFallback).
 int enqueue_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
-                  hipStream_t st, bool capturing, int sr = kMinPlus) {
+                  hipStream_t st, bool capturing, int sr = kMinPlus, int32_t *flag = nullptr,
+                  const int32_t *gate = nullptr) {
     const int nb = (n + tile - 1) / tile;
     hipError_t e;
     auto run = [&](int kind, double upd, auto &&launch) -> hipError_t {
         if (capturing) return launch();
+        if (gate) return timed(kPredFallback, 0.0, st, launch);
         return timed(kind, upd, st, launch);
     };
     if (pred) {
-        e = run(kPredFix, 0.0, [&] { return launch_pred_init(dtype, d, pred, n, ld, ldp, st); });
+        e = run(kPredFix, 0.0,
+                [&] { return launch_pred_init(dtype, d, pred, n, ld, ldp, st, gate); });
         if (e != hipSuccess) return status_of(e);
     }
     // algorithmic updates of each launch: the n^3 tasks split by where the
@@ -188,14 +193,15 @@ int enqueue_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t 
     for (int b = 0; b < nb; ++b) {
         const double kb = real(b);
         if (!closed) {
-            e = run(kDiag, kb * kb * kb,
-                    [&] { return launch_diag(dtype, sr, tile, d, pred, n, ld, ldp, b, st); });
+            e = run(kDiag, kb * kb * kb, [&] {
+                return launch_diag(dtype, sr, tile, d, pred, n, ld, ldp, b, st, flag, gate);
+            });
             if (e != hipSuccess) return status_of(e);
         }
         closed = false;
         if (nb == 1) break;
         e = run(kPanel, 2.0 * kb * kb * (nn - kb), [&] {
-            return launch_panels(dtype, sr, tile, d, pred, n, ld, ldp, b, nb, st);
+            return launch_panels(dtype, sr, tile, d, pred, n, ld, ldp, b, nb, st, flag, gate);
         });
         if (e != hipSuccess) return status_of(e);
         // close_next: the bulk launch also closes the next diagonal tile (its
@@ -204,21 +210,75 @@ int enqueue_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t 
         const double r1 = real(b + 1), rest = nn - kb;
         const double upd = kb * rest * rest + (close_next ? r1 * r1 * r1 : 0.0);
         e = run(kBulk, upd, [&] {
-            return launch_bulk(dtype, sr, tile, d, pred, n, ld, ldp, b, nb, close_next, st);
+            return launch_bulk(dtype, sr, tile, d, pred, n, ld, ldp, b, nb, close_next, st, flag,
+                               gate);
         });
         if (e != hipSuccess) return status_of(e);
         closed = close_next;
     }
     if (pred) {
-        e = run(kPredFix, 0.0, [&] { return launch_pred_fix(dtype, d, pred, n, ld, ldp, st); });
+        e = run(kPredFix, 0.0,
+                [&] { return launch_pred_fix(dtype, d, pred, n, ld, ldp, st, gate); });
         if (e != hipSuccess) return status_of(e);
     }
     return FW_OK;
 }
 
-// Enqueue the whole solve for one graph.  Arguments already valid.
+// int32 with predecessors as a keyed sweep (fw_internal.h): the pairs packed
+// into 32-bit keys in the predecessor matrix, the distances-only schedule and
+// arithmetic over them with tile `key_tile`, the keys unpacked into d and P.
+// If a real key leaves its range or a diagonal entry ends negative, the
+// unpack leaves d untouched and the 64-bit sweep queued behind it (tile
+// `tile`, every launch gated on the flag) solves from the original d; the
+// results are the same either way.  Scratch: `scratch` (a solve plan's), else
+// stream-ordered memory of this call.  Returns FW_ERR_UNSUPPORTED, nothing
+// enqueued, when no scratch can be had (the caller then runs the 64-bit sweep).
+int enqueue_solve_keyed(int32_t *d, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
+                        int key_tile, hipStream_t st, bool capturing, int32_t *scratch) {
+    bool own = false;
+    if (!scratch) {
+        if (capturing) return FW_ERR_UNSUPPORTED;
+        void *mem = nullptr;
+        if (hipMallocAsync(&mem, (size_t)key_scratch_words(n) * 4, st) != hipSuccess) {
+            (void)hipGetLastError();
+            return FW_ERR_UNSUPPORTED;
+        }
+        scratch = (int32_t *)mem;
+        own = true;
+    }
+    auto run = [&](int kind, auto &&launch) -> hipError_t {
+        if (capturing) return launch();
+        return timed(kind, 0.0, st, launch);
+    };
+    int s = FW_OK;
+    hipError_t e =
+        run(kPredFix, [&] { return launch_key_prepare(d, pred, n, ld, ldp, scratch, st); });
+    if (e != hipSuccess) s = status_of(e);
+    if (s == FW_OK)
+        s = enqueue_solve(pred, FW_I32, n, ldp, nullptr, 0, key_tile, st, capturing, kKey,
+                          scratch, nullptr);
+    if (s == FW_OK) {
+        e = run(kPredFix, [&] { return launch_key_finish(d, pred, n, ld, ldp, scratch, st); });
+        if (e != hipSuccess) s = status_of(e);
+    }
+    if (s == FW_OK)
+        s = enqueue_solve(d, FW_I32, n, ld, pred, ldp, tile, st, capturing, kMinPlus, nullptr,
+                          scratch);
+    if (own) hipFreeAsync(scratch, st);
+    return s;
+}
+
+bool keyed_solve(int dtype, const int32_t *pred, int n, int sr) {
+    return dtype == FW_I32 && pred && sr == kMinPlus && n > 1 && n <= kKeyMaxN;
+}
+
+// Enqueue the whole solve for one graph.  Arguments already valid.  `tile`
+// is the tile of the solve (for int32 with predecessors: of the 64-bit
+// sweep); `key_tile` that of a keyed sweep (0: `tile`); `key_scratch` a solve
+// plan's scratch for it.
 int solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
-          hipStream_t st, bool capturing = false, int sr = kMinPlus) {
+          hipStream_t st, bool capturing = false, int sr = kMinPlus, int key_tile = 0,
+          int32_t *key_scratch = nullptr) {
     if (n <= 1) {
         if (pred && n == 1) {
             hipError_t e = capturing ? launch_pred_fix(dtype, d, pred, n, ld, ldp, st)
@@ -230,7 +290,20 @@ int solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int
         return FW_OK;
     }
     if (!tile_supported(tile)) return FW_ERR_INVALID;
+    if (keyed_solve(dtype, pred, n, sr)) {
+        if (key_tile == 0) key_tile = tile;
+        if (!tile_supported(key_tile)) return FW_ERR_INVALID;
+        const int s = enqueue_solve_keyed((int32_t *)d, n, ld, pred, ldp, tile, key_tile, st,
+                                          capturing, key_scratch);
+        if (s != FW_ERR_UNSUPPORTED) return s;
+    }
     return enqueue_solve(d, dtype, n, ld, pred, ldp, tile, st, capturing, sr);
+}
+
+// The keyed sweep's tile from the plan table: the distances-only entry (the
+// keyed sweep runs the distances-only kernels).
+int key_tile_for(int dtype, const int32_t *pred, int64_t n) {
+    return dtype == FW_I32 && pred ? plan_tile(FW_I32, n) : 0;
 }
 
 }  // namespace
@@ -241,7 +314,8 @@ int plan_tile_for(int dtype, int64_t n, bool pred) {
 
 int solve_single(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64_t ldp,
                  hipStream_t st) {
-    return solve(d, dtype, (int)n, ld, pred, ldp, plan_tile(plan_key(dtype, pred), n), st);
+    return solve(d, dtype, (int)n, ld, pred, ldp, plan_tile(plan_key(dtype, pred), n), st, false,
+                 kMinPlus, key_tile_for(dtype, pred, n));
 }
 
 int solve_with_tile(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
@@ -303,7 +377,7 @@ int fw_apsp_pred(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64
     int s = validate(d, dtype, n, ld, pred, ld_pred);
     if (s != FW_OK) return s;
     return solve(d, dtype, (int)n, ld, pred, ld_pred, plan_tile(plan_key(dtype, pred), n),
-                 (hipStream_t)stream);
+                 (hipStream_t)stream, false, kMinPlus, key_tile_for(dtype, pred, n));
 }
 
 int fw_apsp_plan(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64_t ld_pred,
@@ -528,7 +602,8 @@ struct fw_solve_plan_s {
     int n = 0;
     int64_t ld = 0, ldp = 0;
     int32_t *pred = nullptr;
-    int tile = 0;
+    int tile = 0, key_tile = 0;
+    int32_t *key_scratch = nullptr;  // the keyed int32 predecessor sweep's
     int device = 0;
     // the capture stream lives as long as the plan (and with it the graph
     // captured on it); no event is recorded during the capture
@@ -542,6 +617,7 @@ void free_solve_plan(fw_solve_plan_s *pl) {
     if (pl->exec) hipGraphExecDestroy(pl->exec);
     if (pl->graph) hipGraphDestroy(pl->graph);
     if (pl->cap_stream) hipStreamDestroy(pl->cap_stream);
+    if (pl->key_scratch) hipFree(pl->key_scratch);
     delete pl;
 }
 }  // namespace
@@ -563,9 +639,19 @@ int fw_solve_plan_create(void *d, int dtype, int64_t n, int64_t ld, int32_t *pre
     pl->pred = pred;
     pl->ldp = pred ? ld_pred : 0;
     pl->tile = n <= 1 ? 32 : tile ? tile : plan_tile(plan_key(dtype, pred), n);
+    pl->key_tile = n <= 1 ? 0 : tile ? tile : key_tile_for(dtype, pred, n);
     if (hipGetDevice(&pl->device) != hipSuccess) {
         delete pl;
         return FW_ERR_HIP;
+    }
+    if (keyed_solve(dtype, pred, (int)n, kMinPlus)) {
+        void *mem = nullptr;
+        hipError_t e = hipMalloc(&mem, (size_t)key_scratch_words(n) * 4);
+        if (e != hipSuccess) {
+            delete pl;
+            return status_of(e);
+        }
+        pl->key_scratch = (int32_t *)mem;
     }
     *out = pl;
     return FW_OK;
@@ -575,7 +661,8 @@ int fw_solve_plan_launch(fw_solve_plan pl, int mode, void *stream) {
     if (!pl || (mode != 0 && mode != 1)) return FW_ERR_INVALID;
     hipStream_t st = (hipStream_t)stream;
     if (mode == 0 || pl->n <= 1)
-        return solve(pl->d, pl->dtype, pl->n, pl->ld, pl->pred, pl->ldp, pl->tile, st);
+        return solve(pl->d, pl->dtype, pl->n, pl->ld, pl->pred, pl->ldp, pl->tile, st, false,
+                     kMinPlus, pl->key_tile, pl->key_scratch);
     if (!pl->exec) {
         hipError_t e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
         if (e != hipSuccess) {
@@ -585,7 +672,7 @@ int fw_solve_plan_launch(fw_solve_plan pl, int mode, void *stream) {
         e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return status_of(e);
         int s = solve(pl->d, pl->dtype, pl->n, pl->ld, pl->pred, pl->ldp, pl->tile,
-                      pl->cap_stream, true);
+                      pl->cap_stream, true, kMinPlus, pl->key_tile, pl->key_scratch);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(pl->cap_stream, &g);
         if (s != FW_OK) {
@@ -615,6 +702,8 @@ int fw_solve_plan_destroy(fw_solve_plan pl) {
     hipSetDevice(dev);
     return FW_OK;
 }
+
+int64_t fw_pred_fallbacks(void) { return pred_fallbacks(); }
 
 int fw_profile_enable(int on) {
     std::lock_guard<std::mutex> lk(g_prof_mu);

@@ -10,6 +10,29 @@ namespace fw {
 constexpr int32_t kI32Inf = 1073741823;   // "no edge" for int32
 constexpr int32_t kPredNone = 0x7fffffff; // in-sweep "no last hop yet"
 
+// 32-bit keys of the int32 sweep with predecessors.  A cell's (distance d,
+// last hop p) pair is held as key = d * 2^kKeyBits + p with 0 <= p <=
+// kKeyHop, so that keys order exactly as the pairs do lexicographically; the
+// candidate through k is (key_ik with its hop field cleared) + key_kj, the
+// int32 sum of the distances with kj's last hop.  The hop value kKeyHop means
+// "no last hop" (it orders after every vertex), so graphs have at most
+// kKeyMaxN vertices.  Real (finite) distances must keep |d| < 2^14, i.e.
+// keys in [kKeyLow, kKeyReal); every key at or above kKeyInfFloor is
+// infinite and is stored as kKeyInf.  Within those bounds no sum overflows and a finite key
+// never meets an infinite one: finite sums lie in (-2^29, 2^29), sums with an
+// infinite operand in [kKeyInf - 2^28, 2 kKeyInf] with 2 kKeyInf < 2^31.
+constexpr int kKeyBits = 14;
+constexpr int32_t kKeyHop = (1 << kKeyBits) - 1;
+constexpr int32_t kKeyInf = (1 << 30) - (1 << kKeyBits);
+constexpr int32_t kKeyReal = 1 << 28;
+constexpr int32_t kKeyLow = -kKeyReal + (1 << kKeyBits);
+constexpr int32_t kKeyInfFloor = 1 << 29;
+constexpr int kKeyMaxN = kKeyHop;
+// Scratch of one keyed solve, int32 words: [0] the fallback flag (set when a
+// real key left its range or a diagonal went negative), [1..3] unused, then
+// the row minima and the column minima of the finite distances (n each).
+constexpr int64_t key_scratch_words(int64_t n) { return 4 + 2 * n; }
+
 enum PhaseKind {
     kDiag = 0,
     kPanel = 1,
@@ -19,7 +42,8 @@ enum PhaseKind {
     kBitsDiag = 5,  // bit-packed reachability: stage 0's diagonal block
     kBitsPanel = 6, // bit-packed reachability: both panels
     kBitsBulk = 7,  // bit-packed reachability: the bulk (+ next diagonal block)
-    kNumKinds = 8
+    kPredFallback = 8, // the 64-bit predecessor sweep behind a keyed one (gated)
+    kNumKinds = 9
 };
 
 // Phase timing for launches made outside the host driver: calls
@@ -27,27 +51,48 @@ enum PhaseKind {
 hipError_t timed_launch(int kind, double updates, hipStream_t st, hipError_t (*launch)(void *),
                         void *ctx);
 
-// Closed semirings the sweep runs over.
-enum Semiring { kMinPlus = 0, kMaxMin = 1 };
+// What the sweep runs over: closed semirings, and kKey, min-plus over the
+// 32-bit (distance, last hop) keys above (int32 only, no predecessor matrix:
+// the keys are the matrix).
+enum Semiring { kMinPlus = 0, kMaxMin = 1, kKey = 2 };
 
 // One stage-phase launch of the blocked schedule.  `d`/`p` are the matrix
 // and the (optional) predecessor matrix; `b` is the k-block index, `nb` the
-// number of tile rows.  Returns hipSuccess or the launch error.
+// number of tile rows.  `flag` (kKey only, device int32): set to 1 when a
+// real key leaves its range.  `gate` (device int32 or NULL): when non-NULL
+// the launch does nothing unless *gate != 0 at the time it runs.  Returns
+// hipSuccess or the launch error.
 hipError_t launch_diag(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
-                       int64_t ldp, int b, hipStream_t st);
+                       int64_t ldp, int b, hipStream_t st, int32_t *flag = nullptr,
+                       const int32_t *gate = nullptr);
 hipError_t launch_panels(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
-                         int64_t ldp, int b, int nb, hipStream_t st);
+                         int64_t ldp, int b, int nb, hipStream_t st, int32_t *flag = nullptr,
+                         const int32_t *gate = nullptr);
 // With close_next the launch also closes the next stage's diagonal tile
 // (b+1, b+1), which replaces launch_diag(b + 1); allowed exactly when
 // bulk_closes_next_diag(sr, tile, d, p, n, ld, b) holds.
 hipError_t launch_bulk(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
-                       int64_t ldp, int b, int nb, bool close_next, hipStream_t st);
+                       int64_t ldp, int b, int nb, bool close_next, hipStream_t st,
+                       int32_t *flag = nullptr, const int32_t *gate = nullptr);
 bool bulk_closes_next_diag(int sr, int tile, const void *d, const int32_t *p, int n, int64_t ld,
                            int b);
 hipError_t launch_pred_init(int dtype, const void *d, int32_t *p, int n, int64_t ld,
-                            int64_t ldp, hipStream_t st);
+                            int64_t ldp, hipStream_t st, const int32_t *gate = nullptr);
+// With a gate, a fix-up that runs also counts one fallback (pred_fallbacks).
 hipError_t launch_pred_fix(int dtype, const void *d, int32_t *p, int n, int64_t ld,
-                           int64_t ldp, hipStream_t st);
+                           int64_t ldp, hipStream_t st, const int32_t *gate = nullptr);
+// The keyed int32 predecessor solve around the sweep (scratch as
+// key_scratch_words): key_prepare zeroes the scratch and writes the keys of
+// d into `keys`; key_finish takes the row and column minima, raises the flag
+// on a negative diagonal, and -- unless the flag is set -- writes the
+// distances into d and the predecessors into `keys`, in place.
+hipError_t launch_key_prepare(const int32_t *d, int32_t *keys, int n, int64_t ld, int64_t ldk,
+                              int32_t *scratch, hipStream_t st);
+hipError_t launch_key_finish(int32_t *d, int32_t *keys, int n, int64_t ld, int64_t ldk,
+                             int32_t *scratch, hipStream_t st);
+// Number of gated 64-bit predecessor sweeps that ran on the current device
+// (synchronises the device).
+int64_t pred_fallbacks();
 // Vertices with d_ii < 0, ascending, into list (NULL: not written) and their
 // number into *count (device memory).
 hipError_t launch_negcycle(int dtype, const void *d, int n, int64_t ld, int32_t *list,

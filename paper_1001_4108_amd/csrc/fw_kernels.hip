@@ -54,13 +54,19 @@
 namespace fw {
 namespace {
 
+// A gated launch (gate != NULL) does nothing unless *gate != 0: the 64-bit
+// predecessor sweep queued behind a keyed one runs only when the keyed one
+// gave up.  The gate is uniform, so the whole workgroup leaves at once.
+__device__ __forceinline__ bool gated_off(const int32_t *gate) { return gate && *gate == 0; }
+
 // Phase 1: closure of the diagonal tile (b, b) -- one workgroup.
 template <typename T, int S, int TM, bool PRED, class A>
 __global__ void __launch_bounds__((S / TM) * (S / TM))
 diag_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64_t ldp,
-            int b) {
+            int b, int32_t *flag, const int32_t *gate) {
     __shared__ __align__(16) char smem[closure_smem_bytes<T, S, PRED>()];
-    closure_tile<T, S, TM, PRED, A>(d, P, n, ld, ldp, b * S, smem);
+    if (gated_off(gate)) return;
+    closure_tile<T, S, TM, PRED, A>(d, P, n, ld, ldp, b * S, smem, flag);
 }
 
 // Phases 2 and 3: one tile per workgroup.
@@ -94,8 +100,9 @@ constexpr bool tile_can_close() {
 template <typename T, int S, int BK, int TM, int TN, bool VEC, bool PRED, class A>
 __global__ void __launch_bounds__((S / TM) * (S / TN))
 tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64_t ldp, int b,
-            int nb, int mode, int close_next) {
+            int nb, int mode, int close_next, int32_t *flag, const int32_t *gate) {
     __shared__ __align__(16) char smem[tile_smem_bytes<T, S, BK, PRED, A>()];
+    if (gated_off(gate)) return;
     int idx = blockIdx.x, bi, bj;
     bool close = false;
     if constexpr (tile_can_close<S, TM, TN, PRED>()) {
@@ -114,11 +121,11 @@ tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
     if constexpr (keyed_tile<T, S, BK, PRED, A>())
         product_tile_key<S, BK, TM, TN, VEC>(d, P, n, ld, ldp, bi, bj, b, smem);
     else
-        product_tile<T, S, BK, TM, TN, VEC, PRED, A>(d, P, n, ld, ldp, bi, bj, b, smem);
+        product_tile<T, S, BK, TM, TN, VEC, PRED, A>(d, P, n, ld, ldp, bi, bj, b, smem, flag);
     if constexpr (tile_can_close<S, TM, TN, PRED>()) {
         if (close) {
             __syncthreads();  // the tile's stores before its reloads
-            closure_tile<T, S, TM, PRED, A>(d, P, n, ld, ldp, (b + 1) * S, smem);
+            closure_tile<T, S, TM, PRED, A>(d, P, n, ld, ldp, (b + 1) * S, smem, flag);
         }
     }
 }
@@ -136,13 +143,14 @@ tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
 // dispatched early and its longer run overlaps the rest of the bulk.
 template <typename T, class A>
 __global__ void __launch_bounds__(256, FW_BULK_DMA_WAVES)
-bulk_dma_kernel(T *__restrict__ d, int n, int64_t ld, int b, int mf, int close_next) {
+bulk_dma_kernel(T *__restrict__ d, int n, int64_t ld, int b, int mf, int close_next,
+                int32_t *flag) {
     int idx = blockIdx.x;
     const int dix = b * mf + b;  // enumeration index of tile (b+1, b+1)
     if (close_next) idx = idx == 0 ? dix : idx == dix ? 0 : idx;
     int bi, bj;
     bulk_coords(idx, b, mf, bi, bj);
-    bulk_tile_dma<T, A>(d, n, ld, bi, bj, b, close_next && idx == dix);
+    bulk_tile_dma<T, A>(d, n, ld, bi, bj, b, close_next && idx == dix, flag);
 }
 
 // Phase 2 for 128-wide tiles without predecessors: each panel tile as four
@@ -151,7 +159,7 @@ bulk_dma_kernel(T *__restrict__ d, int n, int64_t ld, int b, int mf, int close_n
 // (i, b) into 32-row strips.
 template <typename T, bool VEC, class A>
 __global__ void __launch_bounds__(256)
-panel_strip_kernel(T *__restrict__ d, int n, int64_t ld, int b, int nb) {
+panel_strip_kernel(T *__restrict__ d, int n, int64_t ld, int b, int nb, int32_t *flag) {
     constexpr int S = 128, W = 32;
     __shared__ __align__(16) char smem[strip_smem_bytes<T, S, W, S, 16>()];  // R + CW = 160 either way
     const int m = nb - 1;
@@ -159,9 +167,11 @@ panel_strip_kernel(T *__restrict__ d, int n, int64_t ld, int b, int nb) {
     int bi, bj;
     panel_coords(t, b, m, bi, bj);
     if (t < m)  // row panel: rows of block b, a 32-column strip of block bj
-        strip_tile<T, S, W, S, 16, 4, 4, VEC, A>(d, n, ld, b * S, bj * S + q * W, b * S, smem);
+        strip_tile<T, S, W, S, 16, 4, 4, VEC, A>(d, n, ld, b * S, bj * S + q * W, b * S, smem,
+                                                 flag);
     else        // column panel: a 32-row strip of block bi, columns of block b
-        strip_tile<T, W, S, S, 16, 4, 4, VEC, A>(d, n, ld, bi * S + q * W, b * S, b * S, smem);
+        strip_tile<T, W, S, S, 16, 4, 4, VEC, A>(d, n, ld, bi * S + q * W, b * S, b * S, smem,
+                                                 flag);
 }
 
 // ---------------------------------------------------------------------------
@@ -170,7 +180,8 @@ panel_strip_kernel(T *__restrict__ d, int n, int64_t ld, int b, int nb) {
 template <typename T>
 __global__ void __launch_bounds__(256)
 pred_init_kernel(const T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld,
-                 int64_t ldp) {
+                 int64_t ldp, const int32_t *gate) {
+    if (gated_off(gate)) return;
     for (int i = blockIdx.y; i < n; i += gridDim.y)
         for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
             const T w = d[(int64_t)i * ld + j];
@@ -178,15 +189,122 @@ pred_init_kernel(const T *__restrict__ d, int32_t *__restrict__ P, int n, int64_
         }
 }
 
+// gated 64-bit sweeps that ran (one count per solve, from its fix-up)
+__device__ unsigned long long g_pred_fallbacks;
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 pred_fix_kernel(const T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld,
-                int64_t ldp) {
+                int64_t ldp, const int32_t *gate) {
+    if (gated_off(gate)) return;
+    if (gate && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+        atomicAdd(&g_pred_fallbacks, 1ull);
     for (int i = blockIdx.y; i < n; i += gridDim.y)
         for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
             int32_t &p = P[(int64_t)i * ldp + j];
             p = final_pred<T>(i, j, d[(int64_t)i * ld + j], p);
         }
+}
+
+// ---------------------------------------------------------------------------
+// The keyed int32 predecessor solve (keys as in fw_internal.h).
+// ---------------------------------------------------------------------------
+// Zero the scratch: the flag, and the row and column minima, which start at
+// 0 -- the empty path from a vertex to itself.
+__global__ void __launch_bounds__(256)
+key_zero_kernel(int32_t *__restrict__ scratch, int64_t words) {
+    for (int64_t w = blockIdx.x * 256 + threadIdx.x; w < words; w += (int64_t)gridDim.x * 256)
+        scratch[w] = 0;
+}
+
+// key_ij = d_ij * 2^kKeyBits + (last hop of the edge: i; none on the
+// diagonal), kKeyInf for an absent pair -- the keyed form of the predecessor
+// initialisation.  A real entry with |d_ij| >= 2^14 raises the flag.
+__global__ void __launch_bounds__(256)
+key_pack_kernel(const int32_t *__restrict__ d, int32_t *__restrict__ keys, int n, int64_t ld,
+                int64_t ldk, int32_t *__restrict__ flag) {
+    bool bad = false;
+    for (int i = blockIdx.y; i < n; i += gridDim.y)
+        for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
+            const int32_t w = d[(int64_t)i * ld + j];
+            int32_t key = kKeyInf;
+            if (w != kI32Inf) {
+                bad |= w <= -(1 << kKeyBits) || w >= (1 << kKeyBits);
+                key = (int32_t)((uint32_t)w << kKeyBits) + (i == j ? kKeyHop : i);
+            }
+            keys[(int64_t)i * ldk + j] = key;
+        }
+    if (bad) *flag = 1;
+}
+
+// Row and column minima of the finite distances (min with 0, their start),
+// and the flag for a negative diagonal (a negative cycle: the 64-bit sweep
+// then gives its documented result).  A workgroup covers 256 columns of
+// kMinRows rows: a column's minimum is kept per thread, a row's by a
+// butterfly over the wave; both are folded in with atomicMin.
+constexpr int kMinRows = 64;
+
+__device__ __forceinline__ int32_t wave_min(int32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int32_t u = __shfl_xor(v, o, 64);
+        v = u < v ? u : v;
+    }
+    return v;
+}
+
+__global__ void __launch_bounds__(256)
+key_minima_kernel(const int32_t *__restrict__ keys, int n, int64_t ldk,
+                  int32_t *__restrict__ scratch) {
+    int32_t *rowmin = scratch + 4, *colmin = scratch + 4 + n;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int r0 = blockIdx.y * kMinRows;
+    const int r1 = r0 + kMinRows < n ? r0 + kMinRows : n;
+    int32_t cmin = 0;
+    bool bad = false;
+    for (int i = r0; i < r1; ++i) {
+        int32_t v = 0;
+        if (j < n) {
+            const int32_t key = keys[(int64_t)i * ldk + j];
+            if (key < kKeyInfFloor) v = key >> kKeyBits;
+            bad |= i == j && v < 0;
+        }
+        cmin = v < cmin ? v : cmin;
+        const int32_t rmin = wave_min(v);
+        if ((threadIdx.x & 63) == 0 && rmin < 0) atomicMin(rowmin + i, rmin);
+    }
+    if (j < n && cmin < 0) atomicMin(colmin + j, cmin);
+    if (bad) scratch[0] = 1;
+}
+
+// Unless the flag is set: d_ij = key >> kKeyBits for a finite key, and for
+// an infinite one (j unreachable from i) the value the int32 sweep over the
+// complete graph reaches, FW_I32_INF + (row i's minimum) + (column j's
+// minimum) -- the cheapest path with one absent edge, i -> u absent-edge
+// v -> j, splits into independent best prefix and suffix.  The key matrix
+// becomes the predecessor matrix as pred_fix_kernel leaves it.
+__global__ void __launch_bounds__(256)
+key_unpack_kernel(int32_t *__restrict__ d, int32_t *__restrict__ keys, int n, int64_t ld,
+                  int64_t ldk, const int32_t *__restrict__ scratch) {
+    if (scratch[0] != 0) return;
+    const int32_t *rowmin = scratch + 4, *colmin = scratch + 4 + n;
+    for (int i = blockIdx.y; i < n; i += gridDim.y) {
+        const int32_t rm = rowmin[i];
+        for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
+            int32_t &k = keys[(int64_t)i * ldk + j];
+            const int32_t key = k;
+            int32_t dist, hop = -1;
+            if (key < kKeyInfFloor) {
+                dist = key >> kKeyBits;
+                const int32_t h = key & kKeyHop;
+                if (i != j && h != kKeyHop) hop = h;
+            } else {
+                dist = kI32Inf + rm + colmin[j];
+            }
+            d[(int64_t)i * ld + j] = dist;
+            k = hop;
+        }
+    }
 }
 
 // The vertices i with d_ii < 0 after a solve, in ascending order, and their
@@ -235,11 +353,17 @@ dim3 elementwise_grid(int n) {
 // ---------------------------------------------------------------------------
 template <typename T, bool PRED, class A>
 hipError_t diag_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b,
-                  hipStream_t st) {
+                  hipStream_t st, int32_t *flag, const int32_t *gate) {
     switch (tile) {
-    case 128: diag_kernel<T, 128, 4, PRED, A><<<1, 1024, 0, st>>>(d, p, n, ld, ldp, b); break;
-    case 64: diag_kernel<T, 64, 4, PRED, A><<<1, 256, 0, st>>>(d, p, n, ld, ldp, b); break;
-    case 32: diag_kernel<T, 32, 2, PRED, A><<<1, 256, 0, st>>>(d, p, n, ld, ldp, b); break;
+    case 128:
+        diag_kernel<T, 128, 4, PRED, A><<<1, 1024, 0, st>>>(d, p, n, ld, ldp, b, flag, gate);
+        break;
+    case 64:
+        diag_kernel<T, 64, 4, PRED, A><<<1, 256, 0, st>>>(d, p, n, ld, ldp, b, flag, gate);
+        break;
+    case 32:
+        diag_kernel<T, 32, 2, PRED, A><<<1, 256, 0, st>>>(d, p, n, ld, ldp, b, flag, gate);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -254,7 +378,8 @@ hipError_t diag_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, in
 
 template <typename T, bool VEC, bool PRED, class A>
 hipError_t tile_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b, int nb,
-                  int mode, unsigned grid, hipStream_t st, int close_next = 0) {
+                  int mode, unsigned grid, hipStream_t st, int close_next, int32_t *flag,
+                  const int32_t *gate) {
     switch (tile) {
     case 128:
         if constexpr (PRED) {
@@ -263,19 +388,19 @@ hipError_t tile_t(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, in
             constexpr int TMP = FW_PRED128_TM, TNP = FW_PRED128_TN;
             tile_kernel<T, 128, FW_PRED128_BK, TMP, TNP, VEC, PRED, A>
                 <<<grid, (128 / TMP) * (128 / TNP), 0, st>>>(d, p, n, ld, ldp, b, nb, mode,
-                                                             close_next);
+                                                             close_next, flag, gate);
         } else {
-            tile_kernel<T, 128, 16, 8, 8, VEC, PRED, A><<<grid, 256, 0, st>>>(d, p, n, ld, ldp,
-                                                                             b, nb, mode, 0);
+            tile_kernel<T, 128, 16, 8, 8, VEC, PRED, A><<<grid, 256, 0, st>>>(
+                d, p, n, ld, ldp, b, nb, mode, 0, flag, gate);
         }
         break;
     case 64:
-        tile_kernel<T, 64, 16, 4, 4, VEC, PRED, A><<<grid, 256, 0, st>>>(d, p, n, ld, ldp, b, nb,
-                                                                        mode, close_next);
+        tile_kernel<T, 64, 16, 4, 4, VEC, PRED, A><<<grid, 256, 0, st>>>(
+            d, p, n, ld, ldp, b, nb, mode, close_next, flag, gate);
         break;
     case 32:
-        tile_kernel<T, 32, 16, 4, 4, VEC, PRED, A><<<grid, 64, 0, st>>>(d, p, n, ld, ldp, b, nb,
-                                                                       mode, 0);
+        tile_kernel<T, 32, 16, 4, 4, VEC, PRED, A><<<grid, 64, 0, st>>>(
+            d, p, n, ld, ldp, b, nb, mode, 0, flag, gate);
         break;
     default: return hipErrorInvalidValue;
     }
@@ -296,7 +421,10 @@ bool bulk_copy_path(int tile, bool vec, int n, int64_t ld, int b) {
 
 template <typename T, class A, bool ALLOW_PRED>
 hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b,
-                         int nb, int mode, bool close_next, hipStream_t st) {
+                         int nb, int mode, bool close_next, hipStream_t st, int32_t *flag,
+                         const int32_t *gate) {
+    // only the predecessor forms take a gate (the 64-bit sweep behind a keyed one)
+    if (gate && !p) return hipErrorInvalidValue;
     const int64_t m = nb - 1;
     const int64_t grid = mode == 0 ? 2 * m : m * m;
     if (grid <= 0) return close_next ? hipErrorInvalidValue : hipSuccess;
@@ -313,25 +441,27 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
     if constexpr (ALLOW_PRED) {
         if (p) {
             return vec ? tile_t<T, true, true, A>(tile, d, p, n, ld, ldp, b, nb, mode,
-                                                  (unsigned)grid, st, c)
+                                                  (unsigned)grid, st, c, flag, gate)
                        : tile_t<T, false, true, A>(tile, d, p, n, ld, ldp, b, nb, mode,
-                                                   (unsigned)grid, st, c);
+                                                   (unsigned)grid, st, c, flag, gate);
         }
     } else {
         if (p) return hipErrorInvalidValue;
     }
     if (tile == 64)
         return vec ? tile_t<T, true, false, A>(tile, d, p, n, ld, ldp, b, nb, mode,
-                                               (unsigned)grid, st, c)
+                                               (unsigned)grid, st, c, flag, nullptr)
                    : tile_t<T, false, false, A>(tile, d, p, n, ld, ldp, b, nb, mode,
-                                                (unsigned)grid, st, c);
+                                                (unsigned)grid, st, c, flag, nullptr);
 #if FW_PANEL_STRIPS
     if (mode == 0 && tile == 128) {
         if (4 * grid > 0x7fffffffLL) return hipErrorInvalidValue;
         if (vec)
-            panel_strip_kernel<T, true, A><<<(unsigned)(4 * grid), 256, 0, st>>>(d, n, ld, b, nb);
+            panel_strip_kernel<T, true, A><<<(unsigned)(4 * grid), 256, 0, st>>>(d, n, ld, b, nb,
+                                                                                flag);
         else
-            panel_strip_kernel<T, false, A><<<(unsigned)(4 * grid), 256, 0, st>>>(d, n, ld, b, nb);
+            panel_strip_kernel<T, false, A><<<(unsigned)(4 * grid), 256, 0, st>>>(d, n, ld, b,
+                                                                                 nb, flag);
         return hipGetLastError();
     }
 #endif
@@ -343,53 +473,78 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
         if (close_next && b + 1 >= nf) return hipErrorInvalidValue;
         if (mf > 0) {
             bulk_dma_kernel<T, A><<<(unsigned)(mf * mf), 256, 0, st>>>(d, n, ld, b, (int)mf,
-                                                                      close_next ? 1 : 0);
+                                                                      close_next ? 1 : 0, flag);
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
         if (nf < nb)
             return tile_t<T, true, false, A>(tile, d, p, n, ld, ldp, b, nb, 2,
-                                             (unsigned)(2 * m - 1), st);
+                                             (unsigned)(2 * m - 1), st, 0, flag, nullptr);
         return hipSuccess;
     }
     if (close_next) return hipErrorInvalidValue;  // every closing form is handled above
-    return vec ? tile_t<T, true, false, A>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid, st)
+    return vec ? tile_t<T, true, false, A>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid, st,
+                                           0, flag, nullptr)
                : tile_t<T, false, false, A>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid,
-                                            st);
+                                            st, 0, flag, nullptr);
 }
 
 template <typename T>
 hipError_t tile_any(int sr, int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b,
-                    int nb, int mode, bool close_next, hipStream_t st) {
+                    int nb, int mode, bool close_next, hipStream_t st, int32_t *flag,
+                    const int32_t *gate) {
     if (sr == kMaxMin)
         return tile_dispatch<T, ArMaxMin<T>, false>(tile, d, p, n, ld, ldp, b, nb, mode,
-                                                     close_next, st);
-    return tile_dispatch<T, Ar<T>, true>(tile, d, p, n, ld, ldp, b, nb, mode, close_next, st);
+                                                     close_next, st, nullptr, gate);
+    if (sr == kKey) {
+        if constexpr (std::is_same<T, int32_t>::value) {
+            if (!flag) return hipErrorInvalidValue;
+            return tile_dispatch<int32_t, ArKey, false>(tile, d, p, n, ld, ldp, b, nb, mode,
+                                                        close_next, st, flag, gate);
+        }
+        return hipErrorInvalidValue;
+    }
+    return tile_dispatch<T, Ar<T>, true>(tile, d, p, n, ld, ldp, b, nb, mode, close_next, st,
+                                         nullptr, gate);
 }
 
 }  // namespace
 
 hipError_t launch_diag(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
-                       int64_t ldp, int b, hipStream_t st) {
+                       int64_t ldp, int b, hipStream_t st, int32_t *flag, const int32_t *gate) {
+    if (gate && !p) return hipErrorInvalidValue;
     if (sr == kMaxMin) {
         if (p) return hipErrorInvalidValue;
         if (dtype == 0)
-            return diag_t<float, false, ArMaxMin<float>>(tile, (float *)d, p, n, ld, ldp, b, st);
+            return diag_t<float, false, ArMaxMin<float>>(tile, (float *)d, p, n, ld, ldp, b, st,
+                                                         nullptr, nullptr);
         return diag_t<int32_t, false, ArMaxMin<int32_t>>(tile, (int32_t *)d, p, n, ld, ldp, b,
-                                                         st);
+                                                         st, nullptr, nullptr);
+    }
+    if (sr == kKey) {
+        if (p || dtype != 1 || !flag) return hipErrorInvalidValue;
+        return diag_t<int32_t, false, ArKey>(tile, (int32_t *)d, p, n, ld, ldp, b, st, flag,
+                                             nullptr);
     }
     if (dtype == 0)
-        return p ? diag_t<float, true, Ar<float>>(tile, (float *)d, p, n, ld, ldp, b, st)
-                 : diag_t<float, false, Ar<float>>(tile, (float *)d, p, n, ld, ldp, b, st);
-    return p ? diag_t<int32_t, true, Ar<int32_t>>(tile, (int32_t *)d, p, n, ld, ldp, b, st)
-             : diag_t<int32_t, false, Ar<int32_t>>(tile, (int32_t *)d, p, n, ld, ldp, b, st);
+        return p ? diag_t<float, true, Ar<float>>(tile, (float *)d, p, n, ld, ldp, b, st, nullptr,
+                                                  gate)
+                 : diag_t<float, false, Ar<float>>(tile, (float *)d, p, n, ld, ldp, b, st,
+                                                   nullptr, nullptr);
+    return p ? diag_t<int32_t, true, Ar<int32_t>>(tile, (int32_t *)d, p, n, ld, ldp, b, st,
+                                                  nullptr, gate)
+             : diag_t<int32_t, false, Ar<int32_t>>(tile, (int32_t *)d, p, n, ld, ldp, b, st,
+                                                   nullptr, nullptr);
 }
 
 hipError_t launch_panels(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
-                         int64_t ldp, int b, int nb, hipStream_t st) {
+                         int64_t ldp, int b, int nb, hipStream_t st, int32_t *flag,
+                         const int32_t *gate) {
     if (dtype == 0)
-        return tile_any<float>(sr, tile, (float *)d, p, n, ld, ldp, b, nb, 0, false, st);
-    return tile_any<int32_t>(sr, tile, (int32_t *)d, p, n, ld, ldp, b, nb, 0, false, st);
+        return tile_any<float>(sr, tile, (float *)d, p, n, ld, ldp, b, nb, 0, false, st, flag,
+                               gate);
+    return tile_any<int32_t>(sr, tile, (int32_t *)d, p, n, ld, ldp, b, nb, 0, false, st, flag,
+                             gate);
 }
 
 bool bulk_closes_next_diag(int sr, int tile, const void *d, const int32_t *p, int n, int64_t ld,
@@ -405,30 +560,61 @@ bool bulk_closes_next_diag(int sr, int tile, const void *d, const int32_t *p, in
 }
 
 hipError_t launch_bulk(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
-                       int64_t ldp, int b, int nb, bool close_next, hipStream_t st) {
+                       int64_t ldp, int b, int nb, bool close_next, hipStream_t st, int32_t *flag,
+                       const int32_t *gate) {
     if (dtype == 0)
-        return tile_any<float>(sr, tile, (float *)d, p, n, ld, ldp, b, nb, 1, close_next, st);
-    return tile_any<int32_t>(sr, tile, (int32_t *)d, p, n, ld, ldp, b, nb, 1, close_next, st);
+        return tile_any<float>(sr, tile, (float *)d, p, n, ld, ldp, b, nb, 1, close_next, st,
+                               flag, gate);
+    return tile_any<int32_t>(sr, tile, (int32_t *)d, p, n, ld, ldp, b, nb, 1, close_next, st,
+                             flag, gate);
 }
 
 hipError_t launch_pred_init(int dtype, const void *d, int32_t *p, int n, int64_t ld,
-                            int64_t ldp, hipStream_t st) {
+                            int64_t ldp, hipStream_t st, const int32_t *gate) {
     const dim3 g = elementwise_grid(n);
     if (dtype == 0)
-        pred_init_kernel<float><<<g, 256, 0, st>>>((const float *)d, p, n, ld, ldp);
+        pred_init_kernel<float><<<g, 256, 0, st>>>((const float *)d, p, n, ld, ldp, gate);
     else
-        pred_init_kernel<int32_t><<<g, 256, 0, st>>>((const int32_t *)d, p, n, ld, ldp);
+        pred_init_kernel<int32_t><<<g, 256, 0, st>>>((const int32_t *)d, p, n, ld, ldp, gate);
     return hipGetLastError();
 }
 
 hipError_t launch_pred_fix(int dtype, const void *d, int32_t *p, int n, int64_t ld,
-                           int64_t ldp, hipStream_t st) {
+                           int64_t ldp, hipStream_t st, const int32_t *gate) {
     const dim3 g = elementwise_grid(n);
     if (dtype == 0)
-        pred_fix_kernel<float><<<g, 256, 0, st>>>((const float *)d, p, n, ld, ldp);
+        pred_fix_kernel<float><<<g, 256, 0, st>>>((const float *)d, p, n, ld, ldp, gate);
     else
-        pred_fix_kernel<int32_t><<<g, 256, 0, st>>>((const int32_t *)d, p, n, ld, ldp);
+        pred_fix_kernel<int32_t><<<g, 256, 0, st>>>((const int32_t *)d, p, n, ld, ldp, gate);
     return hipGetLastError();
+}
+
+hipError_t launch_key_prepare(const int32_t *d, int32_t *keys, int n, int64_t ld, int64_t ldk,
+                              int32_t *scratch, hipStream_t st) {
+    const int64_t words = key_scratch_words(n);
+    key_zero_kernel<<<(unsigned)((words + 255) / 256), 256, 0, st>>>(scratch, words);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    key_pack_kernel<<<elementwise_grid(n), 256, 0, st>>>(d, keys, n, ld, ldk, scratch);
+    return hipGetLastError();
+}
+
+hipError_t launch_key_finish(int32_t *d, int32_t *keys, int n, int64_t ld, int64_t ldk,
+                             int32_t *scratch, hipStream_t st) {
+    const dim3 gm((unsigned)((n + 255) / 256), (unsigned)((n + kMinRows - 1) / kMinRows));
+    key_minima_kernel<<<gm, 256, 0, st>>>(keys, n, ldk, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    key_unpack_kernel<<<elementwise_grid(n), 256, 0, st>>>(d, keys, n, ld, ldk, scratch);
+    return hipGetLastError();
+}
+
+int64_t pred_fallbacks() {
+    unsigned long long v = 0;
+    if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_pred_fallbacks), sizeof(v), 0,
+                            hipMemcpyDeviceToHost) != hipSuccess)
+        return -1;
+    return (int64_t)v;
 }
 
 hipError_t launch_negcycle(int dtype, const void *d, int n, int64_t ld, int32_t *list,

@@ -48,7 +48,10 @@ __device__ __forceinline__ float fmax32(float a, float b) {
 #endif
 }
 
+// Every policy says whether its values need settle() before they are stored
+// or handed to other cells as operands (only the keyed policy does).
 template <> struct Ar<float> {
+    static constexpr bool kChecked = false;
     __device__ __forceinline__ static float inf() { return __builtin_inff(); }
     __device__ __forceinline__ static float add(float a, float b) { return a + b; }
     __device__ __forceinline__ static float min2(float a, float b) { return fmin32(a, b); }
@@ -60,6 +63,7 @@ template <> struct Ar<float> {
 };
 
 template <> struct Ar<int32_t> {
+    static constexpr bool kChecked = false;
     __device__ __forceinline__ static int32_t inf() { return kI32Inf; }
     __device__ __forceinline__ static int32_t add(int32_t a, int32_t b) {
         return (int32_t)((uint32_t)a + (uint32_t)b);
@@ -80,6 +84,7 @@ template <> struct Ar<int32_t> {
 template <typename T> struct ArMaxMin;
 
 template <> struct ArMaxMin<float> {
+    static constexpr bool kChecked = false;
     __device__ __forceinline__ static float inf() { return -__builtin_inff(); }
     __device__ __forceinline__ static float add(float a, float b) { return fmin32(a, b); }
     __device__ __forceinline__ static float min2(float a, float b) { return fmax32(a, b); }
@@ -89,6 +94,7 @@ template <> struct ArMaxMin<float> {
 };
 
 template <> struct ArMaxMin<int32_t> {
+    static constexpr bool kChecked = false;
     __device__ __forceinline__ static int32_t inf() { return (int32_t)0x80000000; }
     __device__ __forceinline__ static int32_t add(int32_t a, int32_t b) { return a < b ? a : b; }
     __device__ __forceinline__ static int32_t min2(int32_t a, int32_t b) { return a > b ? a : b; }
@@ -96,6 +102,64 @@ template <> struct ArMaxMin<int32_t> {
         return min2(min2(a, b), c);
     }
 };
+
+// Min-plus over the 32-bit (distance, last hop) keys of fw_internal.h: the
+// int32 form of the lexicographic update below in one add and (for two
+// k-steps) one three-input minimum, the arithmetic of the distances-only
+// sweep.  "add" clears the hop field of its first operand -- always the
+// (i, k) cell, whose last hop the candidate does not inherit -- and adds the
+// (k, j) key.  settle() brings a value back to the key invariant before it is
+// stored or published to other cells: an infinite-class value becomes exactly
+// kKeyInf, and a real value outside [kKeyLow, kKeyReal) (|d| >= 2^14) is
+// recorded in the KeyCheck (the solve is then redone by the 64-bit form).
+//
+// KeyCheck: two running minima instead of a flag, so the check costs a few
+// vector instructions per value and no lane-mask state.  Values that reach
+// settle() lie in (-2^29, 2^29) (real) or [kKeyInf - 2^28, kKeyInf] (infinite
+// class, at or above 3 * 2^28 - 2^14), so a real value is too large exactly
+// when v - kKeyReal, as unsigned, is below kKeyReal, and too small exactly
+// when v < kKeyLow.
+struct KeyCheck {
+    uint32_t hi = 0xffffffffu;  // min over values of (uint32)(v - kKeyReal)
+    int32_t lo = 0;             // min over values
+    __device__ __forceinline__ bool bad() const {
+        return hi < (uint32_t)kKeyReal || lo < kKeyLow;
+    }
+};
+
+struct ArKey {
+    static constexpr bool kChecked = true;
+    __device__ __forceinline__ static int32_t inf() { return kKeyInf; }
+    __device__ __forceinline__ static int32_t add(int32_t a, int32_t b) {
+        return (int32_t)(((uint32_t)a & ~(uint32_t)kKeyHop) + (uint32_t)b);
+    }
+    __device__ __forceinline__ static int32_t min2(int32_t a, int32_t b) { return a < b ? a : b; }
+    __device__ __forceinline__ static int32_t min3(int32_t a, int32_t b, int32_t c) {
+        return min2(min2(a, b), c);
+    }
+    __device__ __forceinline__ static int32_t settle(int32_t v, KeyCheck &c) {
+        const uint32_t up = (uint32_t)v - (uint32_t)kKeyReal;
+        c.hi = up < c.hi ? up : c.hi;
+        c.lo = v < c.lo ? v : c.lo;
+        return v >= kKeyInfFloor ? kKeyInf : v;
+    }
+};
+
+template <class A, typename T>
+__device__ __forceinline__ T settle(T v, KeyCheck &c) {
+    if constexpr (A::kChecked)
+        return A::settle(v, c);
+    else
+        return v;
+}
+
+// Raise the solve's flag from every lane whose check found a bad key.
+template <class A>
+__device__ __forceinline__ void raise_flag(int32_t *flag, const KeyCheck &c) {
+    if constexpr (A::kChecked) {
+        if (c.bad()) *flag = 1;
+    }
+}
 
 // Lexicographic minimum of (distance, last hop): the candidate replaces the
 // current pair when it is strictly shorter, or equally short with a smaller
@@ -195,7 +259,8 @@ constexpr int closure_smem_bytes() {
 // rows (no predecessors); cells move as 16-byte row pieces, no bounds tests.
 template <typename T, int S, int TM, bool PRED, class A = Ar<T>, bool FULL = false>
 __device__ __forceinline__ void closure_tile(T *__restrict__ d, int32_t *__restrict__ P, int n,
-                                             int64_t ld, int64_t ldp, int base, char *smem) {
+                                             int64_t ld, int64_t ldp, int base, char *smem,
+                                             int32_t *flag = nullptr) {
     static_assert(!FULL || (!PRED && TM % 4 == 0), "full-tile form: no predecessors");
     constexpr int G = S / TM;
     T(*rowb)[S] = reinterpret_cast<T(*)[S]>(smem);
@@ -205,6 +270,7 @@ __device__ __forceinline__ void closure_tile(T *__restrict__ d, int32_t *__restr
     const int tx = threadIdx.x % G, ty = threadIdx.x / G;
     T c[TM][TM];
     int32_t pc[TM][TM];
+    KeyCheck bad;
     if constexpr (FULL) {
 #pragma unroll
         for (int r = 0; r < TM; ++r)
@@ -243,13 +309,13 @@ __device__ __forceinline__ void closure_tile(T *__restrict__ d, int32_t *__restr
             if (oty == kb) {
 #pragma unroll
                 for (int q = 0; q < TM; ++q) {
-                    rowb[buf][tx * TM + q] = c[r][q];
+                    rowb[buf][tx * TM + q] = settle<A>(c[r][q], bad);
                     if constexpr (PRED) rowp[buf][tx * TM + q] = pc[r][q];
                 }
             }
             if (otx == kb) {
 #pragma unroll
-                for (int q = 0; q < TM; ++q) colb[buf][ty * TM + q] = c[q][r];
+                for (int q = 0; q < TM; ++q) colb[buf][ty * TM + q] = settle<A>(c[q][r], bad);
             }
             __syncthreads();
             T rk[TM], ck[TM];
@@ -282,6 +348,13 @@ __device__ __forceinline__ void closure_tile(T *__restrict__ d, int32_t *__restr
         }
     }
 
+    if constexpr (A::kChecked) {
+#pragma unroll
+        for (int r = 0; r < TM; ++r)
+#pragma unroll
+            for (int q = 0; q < TM; ++q) c[r][q] = settle<A>(c[r][q], bad);
+        raise_flag<A>(flag, bad);
+    }
     if constexpr (FULL) {
         // addresses recomputed from opaque copies rather than kept live
         // through the k loop
@@ -330,7 +403,7 @@ constexpr int product_smem_bytes() {
 template <typename T, int S, int BK, int TM, int TN, bool VEC, bool PRED, class A = Ar<T>>
 __device__ __forceinline__ void product_tile(T *__restrict__ d, int32_t *__restrict__ P, int n,
                                              int64_t ld, int64_t ldp, int bi, int bj, int b,
-                                             char *smem) {
+                                             char *smem, int32_t *flag = nullptr) {
     constexpr int NT = (S / TM) * (S / TN);
     constexpr int GX = S / TN;       // threads along a tile row
     constexpr int EA = S * BK / NT;  // A-slice elements per thread
@@ -437,6 +510,14 @@ __device__ __forceinline__ void product_tile(T *__restrict__ d, int32_t *__restr
         __syncthreads();
     }
 
+    if constexpr (A::kChecked) {
+        KeyCheck bad;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = settle<A>(acc[i][j], bad);
+        raise_flag<A>(flag, bad);
+    }
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
         row_store<T, TN, VEC>(acc[i], d, row0 + ty * TM + i, col0 + tx * TN, n, ld, full);
@@ -483,7 +564,7 @@ struct Pair<int32_t> {
 
 template <typename T, class A = Ar<T>>
 __device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int n, int64_t ld, int bi,
-                                              int bj, int b, bool close) {
+                                              int bj, int b, bool close, int32_t *flag = nullptr) {
     static_assert(sizeof(T) == 4, "32-bit values");
     constexpr int S = 128, BK = 16, TM = 8, NS = S / BK;
     static_assert(NS % 2 == 0, "slices alternate between two buffers");
@@ -585,6 +666,14 @@ __device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int n, int64_t 
     // through the k loop, 16 VGPRs
     int stx = tx, sty = ty;
     asm volatile("" : "+v"(stx), "+v"(sty));
+    if constexpr (A::kChecked) {
+        KeyCheck bad;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TM; ++j) acc[i][j] = settle<A>(acc[i][j], bad);
+        raise_flag<A>(flag, bad);
+    }
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
         T *row = d + (row0 + sty * TM + i) * ld + col0 + stx * 4;
@@ -604,7 +693,7 @@ __device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int n, int64_t 
         // the product's LDS buffers are free by now
         __syncthreads();
         closure_tile<T, S, TM, false, A, true>(d, nullptr, n, ld, 0, (int)row0,
-                                               reinterpret_cast<char *>(A0));
+                                               reinterpret_cast<char *>(A0), flag);
     }
 }
 
@@ -747,7 +836,8 @@ constexpr int strip_smem_bytes() {
 
 template <typename T, int R, int CW, int K, int BK, int TM, int TN, bool VEC, class A = Ar<T>>
 __device__ __forceinline__ void strip_tile(T *__restrict__ d, int n, int64_t ld, int row0,
-                                           int col0, int k0, char *smem) {
+                                           int col0, int k0, char *smem,
+                                           int32_t *flag = nullptr) {
     constexpr int GX = CW / TN, GY = R / TM, NT = GX * GY;
     constexpr int EA = R * BK / NT, TPA = BK / EA;   // A slice: elements per thread
     constexpr int EB = BK * CW / NT, TPB = CW / EB;  // B slice
@@ -812,6 +902,14 @@ __device__ __forceinline__ void strip_tile(T *__restrict__ d, int n, int64_t ld,
         }
         if (s + 1 < NS) stash(cur ^ 1);
         __syncthreads();
+    }
+    if constexpr (A::kChecked) {
+        KeyCheck bad;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = settle<A>(acc[i][j], bad);
+        raise_flag<A>(flag, bad);
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i)

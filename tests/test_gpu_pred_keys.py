@@ -1,0 +1,206 @@
+"""int32 solves with predecessors: the 32-bit keyed sweep and its fallback.
+
+fw_apsp_pred on int32 first sweeps (distance, last hop) pairs packed into
+32-bit keys and falls back to the 64-bit sweep (queued behind it, gated on a
+device flag) when a distance met during the sweep has |d| >= 2^14 or a
+diagonal entry ends negative.  Both must give the oracle's d and canonical P
+bit for bit; fw.pred_fallbacks() tells which one ran.
+
+* in-range graphs take the keyed path (no fallback) at every tile;
+* the exact range edge: an edge of weight +-(2^14 - 1) stays keyed, +-2^14
+  falls back; on a weight-4 cycle the distances cross 2^14 mid-sweep between
+  n = 4096 (max 16380) and n = 4097 (max 16384);
+* unreachable pairs: the keyed unpack writes the value the int32 sweep over
+  the complete graph reaches (FW_I32_INF + row minimum + column minimum);
+* differential: appending two isolated vertices joined by one edge of weight
+  20000 forces the fallback without changing any result on the original
+  vertices, so keyed and 64-bit results are compared on graphs the oracle's
+  canonical reading does not cover (absent and positive diagonal entries);
+* negative cycles fall back; captured solve plans replay both paths;
+  a side stream gets the same bits.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1001_4108_amd as fw
+from paper_1001_4108_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+INF = gen.I32_INF
+
+
+def _solve(w, tile=None, stream=None):
+    n = w.shape[0]
+    d = torch.from_numpy(np.ascontiguousarray(w)).cuda()
+    P = torch.full((n, n), -77, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()  # inputs in place before another stream reads them
+    if tile is None:
+        fw.fw_apsp_pred(d, P, stream=stream)
+    else:
+        fw.fw_apsp_plan(d, tile, P, stream=stream)
+    torch.cuda.synchronize()
+    return d.cpu().numpy(), P.cpu().numpy()
+
+
+def _check_oracle(w, d, P):
+    ref = oracle.fw(w)
+    assert np.array_equal(d, ref)
+    assert np.array_equal(P, oracle.canonical_pred(ref, w))
+
+
+def _forced(w):
+    """w plus vertices n, n+1 (isolated from w) with the edge n -> n+1 of
+    weight 20000: the keyed sweep gives up, nothing on w's vertices changes."""
+    n = w.shape[0]
+    f = np.full((n + 2, n + 2), INF, dtype=np.int32)
+    f[:n, :n] = w
+    f[n, n] = f[n + 1, n + 1] = 0
+    f[n, n + 1] = 20000
+    return f
+
+
+@pytest.mark.parametrize("n,tile", [(2000, None), (777, None), (300, 32), (300, 64), (300, 128),
+                                    (129, 128), (64, 64)])
+def test_keyed_path_taken_and_exact(n, tile):
+    g = gen.reweighted_graph(n, 0.2, 1, 1000, -500, 500, seed=100 + n)
+    print(f"[pred keys] keyed n={n} tile={tile}", flush=True)
+    before = fw.pred_fallbacks()
+    d, P = _solve(g.w, tile)
+    assert fw.pred_fallbacks() == before
+    _check_oracle(g.w, d, P)
+
+
+def test_large_weights_fall_back_exact():
+    g = gen.reweighted_graph(700, 0.1, 1, 30000, -500, 500, seed=7)
+    print("[pred keys] large weights n=700", flush=True)
+    before = fw.pred_fallbacks()
+    d, P = _solve(g.w)
+    assert fw.pred_fallbacks() == before + 1
+    _check_oracle(g.w, d, P)
+
+
+@pytest.mark.parametrize("wt,falls", [(16383, False), (16384, True), (-16383, False),
+                                      (-16384, True)])
+def test_range_edge_on_one_edge(wt, falls):
+    n = 300
+    w = gen.dense_graph(n, 0.3, 1, 100, seed=11, dtype=np.int32)
+    a, b = 5, 200
+    w[:, a] = INF          # nothing enters a: no cycle through the heavy edge
+    w[a, a] = 0
+    w[a, b] = wt
+    print(f"[pred keys] edge weight {wt}", flush=True)
+    before = fw.pred_fallbacks()
+    d, P = _solve(w)
+    assert fw.pred_fallbacks() == before + (1 if falls else 0)
+    _check_oracle(w, d, P)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("n,falls", [(4096, False), (4097, True)])
+def test_range_crossed_mid_sweep(n, falls):
+    # weight-4 cycle over a seeded permutation: d_ij = 4 ((pos_j - pos_i) mod n),
+    # built up stage by stage; n = 4097 reaches 16384 only on the longest paths
+    perm = gen.cycle_permutation(n, seed=n)
+    pos = np.empty(n, np.int64)
+    pos[perm] = np.arange(n)
+    w = np.full((n, n), INF, dtype=np.int32)
+    np.fill_diagonal(w, 0)
+    w[perm, np.roll(perm, -1)] = 4
+    print(f"[pred keys] weight-4 cycle n={n}", flush=True)
+    before = fw.pred_fallbacks()
+    d, P = _solve(w)
+    assert fw.pred_fallbacks() == before + (1 if falls else 0)
+    dist = 4 * ((pos[None, :] - pos[:, None]) % n)
+    assert np.array_equal(d, dist.astype(np.int32))
+    last = np.broadcast_to(perm[(pos - 1) % n].astype(np.int32), (n, n)).copy()
+    np.fill_diagonal(last, -1)
+    assert np.array_equal(P, last)
+
+
+@pytest.mark.parametrize("n,p,seed", [(1500, 0.003, 1), (600, 0.01, 2), (333, 0.0, 3)])
+def test_unreachable_pairs_keyed(n, p, seed):
+    # small weights: long sparse paths stay far inside |d| < 2^14
+    g = gen.reweighted_graph(n, p, 1, 100, -100, 100, seed=seed)
+    print(f"[pred keys] sparse n={n} p={p}", flush=True)
+    before = fw.pred_fallbacks()
+    d, P = _solve(g.w)
+    assert fw.pred_fallbacks() == before
+    ref = oracle.fw(g.w)
+    assert (ref > INF // 2).any()          # the case under test is there
+    assert np.array_equal(d, ref)
+    assert np.array_equal(P, oracle.canonical_pred(ref, g.w))
+
+
+def _differential(w):
+    n = w.shape[0]
+    before = fw.pred_fallbacks()
+    d, P = _solve(w)
+    mid = fw.pred_fallbacks()
+    fd, fP = _solve(_forced(w))
+    assert fw.pred_fallbacks() == mid + 1
+    assert mid == before                   # the graph itself stays keyed
+    assert np.array_equal(d, fd[:n, :n])
+    assert np.array_equal(P, fP[:n, :n])
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_keyed_equals_fallback_random(seed):
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(40, 900))
+    p = float(rng.choice([0.002, 0.02, 0.2, 0.6]))
+    # edges of at most 300: a path needs over 50 hops to reach |d| = 2^14
+    g = gen.reweighted_graph(n, p, 1, int(rng.integers(2, 100)), -100, 100, seed=seed)
+    w = g.w
+    # some absent and some positive diagonal entries (allowed by the contract)
+    k = rng.choice(n, size=min(n, 7), replace=False)
+    w[k[:3], k[:3]] = INF
+    w[k[3:], k[3:]] = rng.integers(1, 50, size=len(k[3:]))
+    print(f"[pred keys] differential seed={seed} n={n} p={p}", flush=True)
+    _differential(w)
+
+
+def test_negative_cycle_falls_back():
+    w, cyc = gen.planted_negative_cycle(400, 0.2, 5, seed=21)
+    print("[pred keys] planted negative cycle", flush=True)
+    before = fw.pred_fallbacks()
+    d, P = _solve(w)
+    assert fw.pred_fallbacks() == before + 1
+    neg = np.flatnonzero(np.diag(d) < 0)
+    assert set(neg.tolist()) == set(int(c) for c in cyc)
+
+
+@pytest.mark.parametrize("heavy", [False, True])
+def test_solve_plan_replays(heavy):
+    hi = 30000 if heavy else 1000
+    g = gen.reweighted_graph(1000, 0.2, 1, hi, -500, 500, seed=33)
+    n = g.w.shape[0]
+    print(f"[pred keys] solve plan heavy={heavy}", flush=True)
+    ref_d, ref_P = _solve(g.w)
+    src = torch.from_numpy(g.w).cuda()
+    d = src.clone()
+    P = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    plan = fw.SolvePlan(d, P)
+    try:
+        for rep in range(3):
+            d.copy_(src)
+            P.fill_(-77)
+            before = fw.pred_fallbacks()
+            plan.launch("graph")
+            torch.cuda.synchronize()
+            assert fw.pred_fallbacks() == before + (1 if heavy else 0), rep
+            assert np.array_equal(d.cpu().numpy(), ref_d), rep
+            assert np.array_equal(P.cpu().numpy(), ref_P), rep
+    finally:
+        plan.destroy()
+
+
+def test_side_stream_same_bits():
+    g = gen.reweighted_graph(900, 0.2, 1, 1000, -500, 500, seed=44)
+    print("[pred keys] side stream", flush=True)
+    ref_d, ref_P = _solve(g.w)
+    s = torch.cuda.Stream()
+    d, P = _solve(g.w, stream=s)
+    assert np.array_equal(d, ref_d) and np.array_equal(P, ref_P)
