@@ -48,13 +48,24 @@ void default_plan_locked() {
         // fills the GPU too few times and the 128-step diagonal closure
         // weighs more, and tile 64 solves faster (n=1024: 1.7x, n=4096:
         // 1.15x); above, tile 128's lower traffic per update wins (n=12288:
-        // 1.4x).  With predecessors tile 128 never won (int32 n=8192: 69 vs
-        // 82 ms at tile 64), and tile 32 wins below ~2k (fp32) / ~1k (int32)
-        // vertices (fp32 n~1448: 4.0 vs 4.6 ms; int32 n~724: 0.78 vs 0.83).
+        // 1.4x).  With the (distance, last hop) pair forms tile 128 never won
+        // (int32 with 64-bit keys at n=8192: 69 vs 82 ms at tile 64), and
+        // tile 32 wins below ~2k (fp32) / ~1k (int32) vertices (fp32 n~1448:
+        // 4.0 vs 4.6 ms; int32 n~724: 0.78 vs 0.83) -- the forms batched
+        // solves with predecessors still use.  A single int32 solve with
+        // predecessors runs the 32-bit keyed sweep, i.e. the distances-only
+        // kernels, so above 1k vertices it takes their tiles (its gated 64-bit
+        // sweep takes the same tile; at 128 it has half the launches to skip).
         if (key & FW_PLAN_PRED) {
-            const int64_t hi32 = (key & 1) == FW_F32 ? 2048 : 1024;
+            const bool i32 = (key & 1) == FW_I32;
+            const int64_t hi32 = i32 ? 1024 : 2048;
             t.push_back({129, hi32, 32});
-            t.push_back({hi32 + 1, INT64_MAX, 64});
+            if (i32) {
+                t.push_back({hi32 + 1, 4096, 64});
+                t.push_back({4097, INT64_MAX, 128});
+            } else {
+                t.push_back({hi32 + 1, INT64_MAX, 64});
+            }
         } else {
             const int64_t hi64 = (key & 1) == FW_F32 ? 4608 : 4096;
             t.push_back({129, hi64, 64});
@@ -226,15 +237,15 @@ int enqueue_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t 
 
 // int32 with predecessors as a keyed sweep (fw_internal.h): the pairs packed
 // into 32-bit keys in the predecessor matrix, the distances-only schedule and
-// arithmetic over them with tile `key_tile`, the keys unpacked into d and P.
-// If a real key leaves its range or a diagonal entry ends negative, the
-// unpack leaves d untouched and the 64-bit sweep queued behind it (tile
-// `tile`, every launch gated on the flag) solves from the original d; the
-// results are the same either way.  Scratch: `scratch` (a solve plan's), else
+// arithmetic over them, the keys unpacked into d and P.  If a real key
+// leaves its range or a diagonal entry ends negative, the unpack leaves d
+// untouched and the 64-bit sweep queued behind it (same tile, every launch
+// gated on the flag) solves from the original d; the results are the same
+// either way.  Scratch: `scratch` (a solve plan's), else
 // stream-ordered memory of this call.  Returns FW_ERR_UNSUPPORTED, nothing
 // enqueued, when no scratch can be had (the caller then runs the 64-bit sweep).
 int enqueue_solve_keyed(int32_t *d, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
-                        int key_tile, hipStream_t st, bool capturing, int32_t *scratch) {
+                        hipStream_t st, bool capturing, int32_t *scratch) {
     bool own = false;
     if (!scratch) {
         if (capturing) return FW_ERR_UNSUPPORTED;
@@ -255,8 +266,8 @@ int enqueue_solve_keyed(int32_t *d, int n, int64_t ld, int32_t *pred, int64_t ld
         run(kPredFix, [&] { return launch_key_prepare(d, pred, n, ld, ldp, scratch, st); });
     if (e != hipSuccess) s = status_of(e);
     if (s == FW_OK)
-        s = enqueue_solve(pred, FW_I32, n, ldp, nullptr, 0, key_tile, st, capturing, kKey,
-                          scratch, nullptr);
+        s = enqueue_solve(pred, FW_I32, n, ldp, nullptr, 0, tile, st, capturing, kKey, scratch,
+                          nullptr);
     if (s == FW_OK) {
         e = run(kPredFix, [&] { return launch_key_finish(d, pred, n, ld, ldp, scratch, st); });
         if (e != hipSuccess) s = status_of(e);
@@ -272,12 +283,10 @@ bool keyed_solve(int dtype, const int32_t *pred, int n, int sr) {
     return dtype == FW_I32 && pred && sr == kMinPlus && n > 1 && n <= kKeyMaxN;
 }
 
-// Enqueue the whole solve for one graph.  Arguments already valid.  `tile`
-// is the tile of the solve (for int32 with predecessors: of the 64-bit
-// sweep); `key_tile` that of a keyed sweep (0: `tile`); `key_scratch` a solve
-// plan's scratch for it.
+// Enqueue the whole solve for one graph.  Arguments already valid.
+// `key_scratch`: a solve plan's scratch for a keyed sweep.
 int solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
-          hipStream_t st, bool capturing = false, int sr = kMinPlus, int key_tile = 0,
+          hipStream_t st, bool capturing = false, int sr = kMinPlus,
           int32_t *key_scratch = nullptr) {
     if (n <= 1) {
         if (pred && n == 1) {
@@ -291,19 +300,11 @@ int solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int
     }
     if (!tile_supported(tile)) return FW_ERR_INVALID;
     if (keyed_solve(dtype, pred, n, sr)) {
-        if (key_tile == 0) key_tile = tile;
-        if (!tile_supported(key_tile)) return FW_ERR_INVALID;
-        const int s = enqueue_solve_keyed((int32_t *)d, n, ld, pred, ldp, tile, key_tile, st,
-                                          capturing, key_scratch);
+        const int s = enqueue_solve_keyed((int32_t *)d, n, ld, pred, ldp, tile, st, capturing,
+                                          key_scratch);
         if (s != FW_ERR_UNSUPPORTED) return s;
     }
     return enqueue_solve(d, dtype, n, ld, pred, ldp, tile, st, capturing, sr);
-}
-
-// The keyed sweep's tile from the plan table: the distances-only entry (the
-// keyed sweep runs the distances-only kernels).
-int key_tile_for(int dtype, const int32_t *pred, int64_t n) {
-    return dtype == FW_I32 && pred ? plan_tile(FW_I32, n) : 0;
 }
 
 }  // namespace
@@ -314,8 +315,7 @@ int plan_tile_for(int dtype, int64_t n, bool pred) {
 
 int solve_single(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64_t ldp,
                  hipStream_t st) {
-    return solve(d, dtype, (int)n, ld, pred, ldp, plan_tile(plan_key(dtype, pred), n), st, false,
-                 kMinPlus, key_tile_for(dtype, pred, n));
+    return solve(d, dtype, (int)n, ld, pred, ldp, plan_tile(plan_key(dtype, pred), n), st);
 }
 
 int solve_with_tile(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
@@ -377,7 +377,7 @@ int fw_apsp_pred(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64
     int s = validate(d, dtype, n, ld, pred, ld_pred);
     if (s != FW_OK) return s;
     return solve(d, dtype, (int)n, ld, pred, ld_pred, plan_tile(plan_key(dtype, pred), n),
-                 (hipStream_t)stream, false, kMinPlus, key_tile_for(dtype, pred, n));
+                 (hipStream_t)stream);
 }
 
 int fw_apsp_plan(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64_t ld_pred,
@@ -602,7 +602,7 @@ struct fw_solve_plan_s {
     int n = 0;
     int64_t ld = 0, ldp = 0;
     int32_t *pred = nullptr;
-    int tile = 0, key_tile = 0;
+    int tile = 0;
     int32_t *key_scratch = nullptr;  // the keyed int32 predecessor sweep's
     int device = 0;
     // the capture stream lives as long as the plan (and with it the graph
@@ -639,7 +639,6 @@ int fw_solve_plan_create(void *d, int dtype, int64_t n, int64_t ld, int32_t *pre
     pl->pred = pred;
     pl->ldp = pred ? ld_pred : 0;
     pl->tile = n <= 1 ? 32 : tile ? tile : plan_tile(plan_key(dtype, pred), n);
-    pl->key_tile = n <= 1 ? 0 : tile ? tile : key_tile_for(dtype, pred, n);
     if (hipGetDevice(&pl->device) != hipSuccess) {
         delete pl;
         return FW_ERR_HIP;
@@ -662,7 +661,7 @@ int fw_solve_plan_launch(fw_solve_plan pl, int mode, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     if (mode == 0 || pl->n <= 1)
         return solve(pl->d, pl->dtype, pl->n, pl->ld, pl->pred, pl->ldp, pl->tile, st, false,
-                     kMinPlus, pl->key_tile, pl->key_scratch);
+                     kMinPlus, pl->key_scratch);
     if (!pl->exec) {
         hipError_t e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
         if (e != hipSuccess) {
@@ -672,7 +671,7 @@ int fw_solve_plan_launch(fw_solve_plan pl, int mode, void *stream) {
         e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return status_of(e);
         int s = solve(pl->d, pl->dtype, pl->n, pl->ld, pl->pred, pl->ldp, pl->tile,
-                      pl->cap_stream, true, kMinPlus, pl->key_tile, pl->key_scratch);
+                      pl->cap_stream, true, kMinPlus, pl->key_scratch);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(pl->cap_stream, &g);
         if (s != FW_OK) {

@@ -29,9 +29,13 @@ constexpr int32_t kKeyLow = -kKeyReal + (1 << kKeyBits);
 constexpr int32_t kKeyInfFloor = 1 << 29;
 constexpr int kKeyMaxN = kKeyHop;
 // Scratch of one keyed solve, int32 words: [0] the fallback flag (set when a
-// real key left its range or a diagonal went negative), [1..3] unused, then
-// the row minima and the column minima of the finite distances (n each).
-constexpr int64_t key_scratch_words(int64_t n) { return 4 + 2 * n; }
+// real key left its range or a diagonal went negative), [1] set when some
+// pair is unreachable, [2..3] unused, then the row minima and the column
+// minima of the finite distances (n each); from the 64-word (256-byte)
+// boundary after them, the current stage's column panel with the hop fields
+// cleared (n rows of 128), the A operand of the 128-wide keyed bulk.
+constexpr int64_t key_acol_offset(int64_t n) { return (4 + 2 * n + 63) / 64 * 64; }
+constexpr int64_t key_scratch_words(int64_t n) { return key_acol_offset(n) + 128 * n; }
 
 enum PhaseKind {
     kDiag = 0,

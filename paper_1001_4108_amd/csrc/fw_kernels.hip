@@ -144,13 +144,13 @@ tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
 template <typename T, class A>
 __global__ void __launch_bounds__(256, FW_BULK_DMA_WAVES)
 bulk_dma_kernel(T *__restrict__ d, int n, int64_t ld, int b, int mf, int close_next,
-                int32_t *flag) {
+                int32_t *flag, const T *acol) {
     int idx = blockIdx.x;
     const int dix = b * mf + b;  // enumeration index of tile (b+1, b+1)
     if (close_next) idx = idx == 0 ? dix : idx == dix ? 0 : idx;
     int bi, bj;
     bulk_coords(idx, b, mf, bi, bj);
-    bulk_tile_dma<T, A>(d, n, ld, bi, bj, b, close_next && idx == dix, flag);
+    bulk_tile_dma<T, A>(d, n, ld, bi, bj, b, close_next && idx == dix, flag, acol);
 }
 
 // Phase 2 for 128-wide tiles without predecessors: each panel tile as four
@@ -159,7 +159,8 @@ bulk_dma_kernel(T *__restrict__ d, int n, int64_t ld, int b, int mf, int close_n
 // (i, b) into 32-row strips.
 template <typename T, bool VEC, class A>
 __global__ void __launch_bounds__(256)
-panel_strip_kernel(T *__restrict__ d, int n, int64_t ld, int b, int nb, int32_t *flag) {
+panel_strip_kernel(T *__restrict__ d, int n, int64_t ld, int b, int nb, int32_t *flag,
+                   T *acol) {
     constexpr int S = 128, W = 32;
     __shared__ __align__(16) char smem[strip_smem_bytes<T, S, W, S, 16>()];  // R + CW = 160 either way
     const int m = nb - 1;
@@ -171,7 +172,7 @@ panel_strip_kernel(T *__restrict__ d, int n, int64_t ld, int b, int nb, int32_t 
                                                  flag);
     else        // column panel: a 32-row strip of block bi, columns of block b
         strip_tile<T, W, S, S, 16, 4, 4, VEC, A>(d, n, ld, bi * S + q * W, b * S, b * S, smem,
-                                                 flag);
+                                                 flag, acol);
 }
 
 // ---------------------------------------------------------------------------
@@ -237,12 +238,17 @@ key_pack_kernel(const int32_t *__restrict__ d, int32_t *__restrict__ keys, int n
     if (bad) *flag = 1;
 }
 
-// Row and column minima of the finite distances (min with 0, their start),
-// and the flag for a negative diagonal (a negative cycle: the 64-bit sweep
-// then gives its documented result).  A workgroup covers 256 columns of
-// kMinRows rows: a column's minimum is kept per thread, a row's by a
-// butterfly over the wave; both are folded in with atomicMin.
-constexpr int kMinRows = 64;
+// A negative diagonal entry after the keyed sweep (a negative cycle: the
+// 64-bit sweep then gives its documented result) raises the flag.
+__global__ void __launch_bounds__(256)
+key_diag_kernel(const int32_t *__restrict__ keys, int n, int64_t ldk, int32_t *__restrict__ flag) {
+    bool bad = false;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const int32_t key = keys[(int64_t)i * ldk + i];
+        bad |= key < kKeyInfFloor && (key >> kKeyBits) < 0;
+    }
+    if (bad) *flag = 1;
+}
 
 __device__ __forceinline__ int32_t wave_min(int32_t v) {
 #pragma unroll
@@ -253,56 +259,76 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
     return v;
 }
 
-__global__ void __launch_bounds__(256)
-key_minima_kernel(const int32_t *__restrict__ keys, int n, int64_t ldk,
-                  int32_t *__restrict__ scratch) {
-    int32_t *rowmin = scratch + 4, *colmin = scratch + 4 + n;
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    const int r0 = blockIdx.y * kMinRows;
-    const int r1 = r0 + kMinRows < n ? r0 + kMinRows : n;
-    int32_t cmin = 0;
-    bool bad = false;
-    for (int i = r0; i < r1; ++i) {
-        int32_t v = 0;
-        if (j < n) {
-            const int32_t key = keys[(int64_t)i * ldk + j];
-            if (key < kKeyInfFloor) v = key >> kKeyBits;
-            bad |= i == j && v < 0;
-        }
-        cmin = v < cmin ? v : cmin;
-        const int32_t rmin = wave_min(v);
-        if ((threadIdx.x & 63) == 0 && rmin < 0) atomicMin(rowmin + i, rmin);
-    }
-    if (j < n && cmin < 0) atomicMin(colmin + j, cmin);
-    if (bad) scratch[0] = 1;
-}
+// Unless the flag is set: every key becomes its distance in d and its last
+// hop in the key matrix, now the predecessor matrix as pred_fix_kernel
+// leaves it (-1 on the diagonal and for an infinite key).  An infinite key
+// (j not reachable from i) leaves FW_I32_INF in d, for key_inf_kernel, and
+// raises the "some pair unreachable" word.  On the way, the row and column
+// minima of the finite distances (starting at 0): a workgroup covers 256
+// columns of kMinRows rows, a column's minimum kept per thread, a row's
+// reduced over each wave and then over the four waves in LDS, both folded in
+// with atomicMin.
+constexpr int kMinRows = 64;
 
-// Unless the flag is set: d_ij = key >> kKeyBits for a finite key, and for
-// an infinite one (j unreachable from i) the value the int32 sweep over the
-// complete graph reaches, FW_I32_INF + (row i's minimum) + (column j's
-// minimum) -- the cheapest path with one absent edge, i -> u absent-edge
-// v -> j, splits into independent best prefix and suffix.  The key matrix
-// becomes the predecessor matrix as pred_fix_kernel leaves it.
 __global__ void __launch_bounds__(256)
 key_unpack_kernel(int32_t *__restrict__ d, int32_t *__restrict__ keys, int n, int64_t ld,
-                  int64_t ldk, const int32_t *__restrict__ scratch) {
+                  int64_t ldk, int32_t *__restrict__ scratch) {
+    __shared__ int32_t wmin[4][kMinRows];
     if (scratch[0] != 0) return;
+    int32_t *rowmin = scratch + 4, *colmin = scratch + 4 + n;
+    const int j = blockIdx.x * 256 + threadIdx.x, wave = threadIdx.x >> 6;
+    const int r0 = blockIdx.y * kMinRows;
+    const int rows = n - r0 < kMinRows ? n - r0 : kMinRows;
+    int32_t cmin = 0;
+    bool unreachable = false;
+    for (int r = 0; r < rows; ++r) {
+        const int i = r0 + r;
+        int32_t v = 0;
+        if (j < n) {
+            int32_t &k = keys[(int64_t)i * ldk + j];
+            const int32_t key = k;
+            int32_t dist = kI32Inf, hop = -1;
+            if (key < kKeyInfFloor) {
+                dist = v = key >> kKeyBits;
+                const int32_t h = key & kKeyHop;
+                if (i != j && h != kKeyHop) hop = h;
+            } else {
+                unreachable = true;
+            }
+            d[(int64_t)i * ld + j] = dist;
+            k = hop;
+        }
+        cmin = v < cmin ? v : cmin;
+        const int32_t rm = wave_min(v);
+        if ((threadIdx.x & 63) == 0) wmin[wave][r] = rm;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < rows) {
+        const int t = threadIdx.x;
+        int32_t m = wmin[0][t];
+        m = wmin[1][t] < m ? wmin[1][t] : m;
+        m = wmin[2][t] < m ? wmin[2][t] : m;
+        m = wmin[3][t] < m ? wmin[3][t] : m;
+        if (m < 0) atomicMin(rowmin + r0 + t, m);
+    }
+    if (j < n && cmin < 0) atomicMin(colmin + j, cmin);
+    if (unreachable) scratch[1] = 1;
+}
+
+// Where j is not reachable from i: the value the int32 sweep over the
+// complete graph reaches, FW_I32_INF + (row i's minimum) + (column j's
+// minimum) -- the cheapest path i ~> u -> v ~> j through one absent edge
+// u -> v splits into independent best prefix and suffix, every such (u, v)
+// pair being absent.  Runs only if the unpack found such a pair.
+__global__ void __launch_bounds__(256)
+key_inf_kernel(int32_t *__restrict__ d, int n, int64_t ld, const int32_t *__restrict__ scratch) {
+    if (scratch[0] != 0 || scratch[1] == 0) return;
     const int32_t *rowmin = scratch + 4, *colmin = scratch + 4 + n;
     for (int i = blockIdx.y; i < n; i += gridDim.y) {
         const int32_t rm = rowmin[i];
         for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
-            int32_t &k = keys[(int64_t)i * ldk + j];
-            const int32_t key = k;
-            int32_t dist, hop = -1;
-            if (key < kKeyInfFloor) {
-                dist = key >> kKeyBits;
-                const int32_t h = key & kKeyHop;
-                if (i != j && h != kKeyHop) hop = h;
-            } else {
-                dist = kI32Inf + rm + colmin[j];
-            }
-            d[(int64_t)i * ld + j] = dist;
-            k = hop;
+            int32_t &v = d[(int64_t)i * ld + j];
+            if (v == kI32Inf) v = kI32Inf + rm + colmin[j];
         }
     }
 }
@@ -338,10 +364,14 @@ negcycle_kernel(const T *__restrict__ d, int n, int64_t ld, int32_t *__restrict_
     if (threadIdx.x == 0 && count) *count = total;
 }
 
+// About 8K workgroups whatever n: enough to stream the matrix, and cheap to
+// dispatch when a gated launch finds its gate closed.
 dim3 elementwise_grid(int n) {
-    const int gx = (n + 255) / 256 < 64 ? (n + 255) / 256 : 64;
-    const int gy = n < 16384 ? n : 16384;
-    return dim3(gx > 0 ? gx : 1, gy > 0 ? gy : 1);
+    int gx = (n + 255) / 256 < 64 ? (n + 255) / 256 : 64;
+    gx = gx > 0 ? gx : 1;
+    int gy = 8192 / gx;
+    gy = n < gy ? n : gy;
+    return dim3(gx, gy > 0 ? gy : 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -438,6 +468,9 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
           (p ? (!ALLOW_PRED || tile != 128) : !bulk_copy_path(tile, vec, n, ld, b)))))
         return hipErrorInvalidValue;
     const int c = close_next ? 1 : 0;
+    // the keyed 128-wide sweep's cleared column panel (in the solve's scratch)
+    T *acol = nullptr;
+    if constexpr (A::kChecked) acol = reinterpret_cast<T *>(flag + key_acol_offset(n));
     if constexpr (ALLOW_PRED) {
         if (p) {
             return vec ? tile_t<T, true, true, A>(tile, d, p, n, ld, ldp, b, nb, mode,
@@ -458,22 +491,23 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
         if (4 * grid > 0x7fffffffLL) return hipErrorInvalidValue;
         if (vec)
             panel_strip_kernel<T, true, A><<<(unsigned)(4 * grid), 256, 0, st>>>(d, n, ld, b, nb,
-                                                                                flag);
+                                                                                flag, acol);
         else
-            panel_strip_kernel<T, false, A><<<(unsigned)(4 * grid), 256, 0, st>>>(d, n, ld, b,
-                                                                                 nb, flag);
+            panel_strip_kernel<T, false, A><<<(unsigned)(4 * grid), 256, 0, st>>>(
+                d, n, ld, b, nb, flag, acol);
         return hipGetLastError();
     }
 #endif
     // Stage with a full k-block: full tiles through bulk_dma_kernel, the
     // tiles of a partial last block (if any) through tile_kernel mode 4.
     const int nf = n / 128;
-    if (mode == 1 && bulk_copy_path(tile, vec, n, ld, b)) {
+    // the keyed copy path reads the cleared column panel the strips write
+    if (mode == 1 && bulk_copy_path(tile, vec, n, ld, b) && (!A::kChecked || FW_PANEL_STRIPS)) {
         const int64_t mf = nf - 1;
         if (close_next && b + 1 >= nf) return hipErrorInvalidValue;
         if (mf > 0) {
-            bulk_dma_kernel<T, A><<<(unsigned)(mf * mf), 256, 0, st>>>(d, n, ld, b, (int)mf,
-                                                                      close_next ? 1 : 0, flag);
+            bulk_dma_kernel<T, A><<<(unsigned)(mf * mf), 256, 0, st>>>(
+                d, n, ld, b, (int)mf, close_next ? 1 : 0, flag, acol);
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -552,6 +586,7 @@ bool bulk_closes_next_diag(int sr, int tile, const void *d, const int32_t *p, in
 #if FW_FUSE_DIAG
     if (tile == 64) return (!p || sr == kMinPlus) && b + 1 < (n + 63) / 64;
     if (p) return sr == kMinPlus && tile == 128 && b + 1 < (n + 127) / 128;
+    if (sr == kKey && !FW_PANEL_STRIPS) return false;
     return bulk_copy_path(tile, vec_ok(d, ld), n, ld, b) && b + 1 < n / 128;
 #else
     (void)sr, (void)tile, (void)d, (void)p, (void)n, (void)ld, (void)b;
@@ -601,11 +636,14 @@ hipError_t launch_key_prepare(const int32_t *d, int32_t *keys, int n, int64_t ld
 
 hipError_t launch_key_finish(int32_t *d, int32_t *keys, int n, int64_t ld, int64_t ldk,
                              int32_t *scratch, hipStream_t st) {
-    const dim3 gm((unsigned)((n + 255) / 256), (unsigned)((n + kMinRows - 1) / kMinRows));
-    key_minima_kernel<<<gm, 256, 0, st>>>(keys, n, ldk, scratch);
+    key_diag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(keys, n, ldk, scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    key_unpack_kernel<<<elementwise_grid(n), 256, 0, st>>>(d, keys, n, ld, ldk, scratch);
+    const dim3 gu((unsigned)((n + 255) / 256), (unsigned)((n + kMinRows - 1) / kMinRows));
+    key_unpack_kernel<<<gu, 256, 0, st>>>(d, keys, n, ld, ldk, scratch);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    key_inf_kernel<<<elementwise_grid(n), 256, 0, st>>>(d, n, ld, scratch);
     return hipGetLastError();
 }
 

@@ -133,6 +133,13 @@ struct ArKey {
     __device__ __forceinline__ static int32_t add(int32_t a, int32_t b) {
         return (int32_t)(((uint32_t)a & ~(uint32_t)kKeyHop) + (uint32_t)b);
     }
+    // add for a first operand whose hop field is already clear
+    __device__ __forceinline__ static int32_t add_cleared(int32_t a, int32_t b) {
+        return (int32_t)((uint32_t)a + (uint32_t)b);
+    }
+    __device__ __forceinline__ static int32_t clear_hop(int32_t a) {
+        return (int32_t)((uint32_t)a & ~(uint32_t)kKeyHop);
+    }
     __device__ __forceinline__ static int32_t min2(int32_t a, int32_t b) { return a < b ? a : b; }
     __device__ __forceinline__ static int32_t min3(int32_t a, int32_t b, int32_t c) {
         return min2(min2(a, b), c);
@@ -562,9 +569,13 @@ struct Pair<int32_t> {
     using type = int2;
 };
 
+// With the keyed policy the A slices come from `acol` (the stage's column
+// panel with the hop fields cleared, 128 values per row, written by the
+// panel launch), so the k loop adds without clearing.
 template <typename T, class A = Ar<T>>
 __device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int n, int64_t ld, int bi,
-                                              int bj, int b, bool close, int32_t *flag = nullptr) {
+                                              int bj, int b, bool close, int32_t *flag = nullptr,
+                                              const T *__restrict__ acol = nullptr) {
     static_assert(sizeof(T) == 4, "32-bit values");
     constexpr int S = 128, BK = 16, TM = 8, NS = S / BK;
     static_assert(NS % 2 == 0, "slices alternate between two buffers");
@@ -599,12 +610,14 @@ __device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int n, int64_t 
     // Copy sources: wave-uniform bases plus 32-bit per-lane offsets.  The
     // wave copies A rows 32*wave + lane/4 (and +16) and B k-rows
     // 4*wave + lane/32 (and +2) of each slice.
-    const T *a_base = d + (row0 + wave * 32) * ld + k0;
+    const int64_t lda = A::kChecked ? (int64_t)S : ld;
+    const T *a_base = A::kChecked ? acol + (row0 + wave * 32) * S
+                                  : d + (row0 + wave * 32) * ld + k0;
     const T *b_base = d + (k0 + wave * 4) * ld + col0;
     const int ar = wave * 32 + (lane >> 2);
-    const uint32_t a_off0 = (uint32_t)((lane >> 2) * ld) + (((lane & 3) ^ ((ar >> 3) & 3)) << 2);
+    const uint32_t a_off0 = (uint32_t)((lane >> 2) * lda) + (((lane & 3) ^ ((ar >> 3) & 3)) << 2);
     const uint32_t a_off1 =
-        (uint32_t)(((lane >> 2) + 16) * ld) + (((lane & 3) ^ (((ar + 16) >> 3) & 3)) << 2);
+        (uint32_t)(((lane >> 2) + 16) * lda) + (((lane & 3) ^ (((ar + 16) >> 3) & 3)) << 2);
     const uint32_t b_off0 = (uint32_t)((lane >> 5) * ld) + ((lane & 31) << 2);
     const uint32_t b_off1 = b_off0 + (uint32_t)(2 * ld);
     auto issue = [&](int s, T *Ad, T *Bd) {
@@ -639,8 +652,13 @@ __device__ __forceinline__ void bulk_tile_dma(T *__restrict__ d, int n, int64_t 
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < TM; ++j)
-                    acc[i][j] = A::min3(acc[i][j], A::add(a0[i], b0[j]), A::add(a1[i], b1[j]));
+                for (int j = 0; j < TM; ++j) {
+                    if constexpr (A::kChecked)
+                        acc[i][j] = A::min3(acc[i][j], A::add_cleared(a0[i], b0[j]),
+                                            A::add_cleared(a1[i], b1[j]));
+                    else
+                        acc[i][j] = A::min3(acc[i][j], A::add(a0[i], b0[j]), A::add(a1[i], b1[j]));
+                }
         }
     };
 
@@ -834,10 +852,14 @@ constexpr int strip_smem_bytes() {
     return 2 * BK * (R + CW) * (int)sizeof(T);
 }
 
+// With the keyed policy and `acol` non-NULL (a column-panel strip of a 128-
+// wide sweep), the strip also writes its cells with the hop field cleared to
+// acol (row r, column c - col0 at acol[r * CW + c - col0]): the bulk's A
+// operand, ready to be added.
 template <typename T, int R, int CW, int K, int BK, int TM, int TN, bool VEC, class A = Ar<T>>
 __device__ __forceinline__ void strip_tile(T *__restrict__ d, int n, int64_t ld, int row0,
                                            int col0, int k0, char *smem,
-                                           int32_t *flag = nullptr) {
+                                           int32_t *flag = nullptr, T *acol = nullptr) {
     constexpr int GX = CW / TN, GY = R / TM, NT = GX * GY;
     constexpr int EA = R * BK / NT, TPA = BK / EA;   // A slice: elements per thread
     constexpr int EB = BK * CW / NT, TPB = CW / EB;  // B slice
@@ -910,6 +932,29 @@ __device__ __forceinline__ void strip_tile(T *__restrict__ d, int n, int64_t ld,
 #pragma unroll
             for (int j = 0; j < TN; ++j) acc[i][j] = settle<A>(acc[i][j], bad);
         raise_flag<A>(flag, bad);
+        if (acol) {
+            static_assert(TN % 4 == 0, "16-byte pieces");
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int r = row0 + ty * TM + i;
+                T *dst = acol + (int64_t)r * CW + tx * TN;
+                if (full) {
+#pragma unroll
+                    for (int j = 0; j < TN; j += 4) {
+                        typename Vec4<T>::type x;
+                        x[0] = A::clear_hop(acc[i][j]);
+                        x[1] = A::clear_hop(acc[i][j + 1]);
+                        x[2] = A::clear_hop(acc[i][j + 2]);
+                        x[3] = A::clear_hop(acc[i][j + 3]);
+                        *reinterpret_cast<typename Vec4<T>::type *>(dst + j) = x;
+                    }
+                } else if (r < n) {
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        if (col0 + tx * TN + j < n) dst[j] = A::clear_hop(acc[i][j]);
+                }
+            }
+        }
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i)

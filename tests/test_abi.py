@@ -99,8 +99,10 @@ def test_plan_table_predecessor_key():
             assert B.plan_tile(dt, n, pred=True) == B.lib().fw_plan_tile(code | 2, n)
             assert B.plan_tile(dt, n, pred=True) in B.plan_tiles()
     # built-in defaults: with predecessors tile 32 for small blocked solves and
-    # 64 above, without 64 then 128 for large solves
-    assert B.plan_tile("i32", 8192, pred=True) == 64
+    # 64 above (int32 above 4096: 128, the keyed sweep's tile), without 64 then
+    # 128 for large solves
+    assert B.plan_tile("i32", 8192, pred=True) == 128  # the keyed sweep's tile
+    assert B.plan_tile("i32", 3000, pred=True) == 64
     assert B.plan_tile("i32", 500, pred=True) == 32 and B.plan_tile("f32", 1500, pred=True) == 32
     assert B.plan_tile("f32", 16384) == 128 and B.plan_tile("i32", 8192) == 128
     assert B.plan_tile("f32", 1024) == 64
