@@ -128,7 +128,8 @@ def log(msg):
 
 PROBE_FORMS = {0: "v_add_f32", 1: "fp32 min-plus (2 v_add_f32 + v_minimum3_f32)",
                2: "int32 min-plus (2 v_add_u32 + v_min3_i32)", 3: "v_fma_f32",
-               4: "v_and_or_b32"}
+               4: "v_and_or_b32", 5: "v_add_u32", 6: "v_min3_i32", 7: "v_minimum3_f32",
+               8: "2 v_add_u32 + v_minimum3_f32"}
 
 
 def bench_valu_probe(torch, dev):

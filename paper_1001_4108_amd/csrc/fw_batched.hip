@@ -484,6 +484,10 @@ struct fw_batch_plan_s {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // fork / join of the independent launch sequences (see enqueue_plan),
+    // created at the first launch that has more than one
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace {
@@ -670,31 +674,84 @@ int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t coun
     return status_of(e);
 }
 
+// The tile group whose stage-batched launch sequence is longest (the plan's
+// critical path), or 0 when the plan has no stage-batched part.
+int main_tile(const fw_batch_plan_s *pl) {
+    std::map<int, int> launches;
+    for (const StagedLaunch &l : pl->staged) ++launches[l.tile];
+    int best = 0, most = 0;
+    for (auto &kv : launches)
+        if (kv.second > most) best = kv.first, most = kv.second;
+    return best;
+}
+
+// True when the plan has launch sequences that depend on nothing in each
+// other: several tile groups, or stage-batched and persistent parts.
+bool has_independent_parts(const fw_batch_plan_s *pl) {
+    const int main = main_tile(pl);
+    for (const StagedLaunch &l : pl->staged)
+        if (l.tile != main) return true;
+    return main != 0 && pl->count > pl->n_staged;
+}
+
 // Enqueue: the stage-batched launches, then (if the plan has a persistent
 // part) the reset of its work counter and the persistent kernel.  All are
 // kernel launches (no copy or memset node), so the same sequence can be
 // captured into a graph and replayed.  `untimed`: no phase events (a capture
-// is running, or the caller must not create events).
-int enqueue_plan(fw_batch_plan_s *pl, hipStream_t st, bool untimed) {
+// is running, or the caller must not create events).  With `side` (a stream
+// of the plan, and its `fork` / `join` events), the sequences of different
+// graphs run side by side: the longest tile group's stages on `st`, the other
+// tile groups and the persistent part on `side`, forked from and joined back
+// into `st` by the events (in a capture: parallel branches of the graph).
+int enqueue_plan(fw_batch_plan_s *pl, hipStream_t st, bool untimed, hipStream_t side = nullptr,
+                 hipEvent_t fork = nullptr, hipEvent_t join = nullptr) {
     if (pl->count == 0) return FW_OK;
     hipError_t e = hipSuccess;
     auto *hdr = static_cast<BatchHeader *>(pl->dev);
     auto *items =
         reinterpret_cast<const BatchItem *>(static_cast<char *>(pl->dev) + sizeof(BatchHeader));
-    for (const StagedLaunch &l : pl->staged) {
-        e = launch_staged(pl->dtype, pl->pred, l.tile, items, pl->work + l.offset, l.kind, l.b,
-                          (unsigned)l.count, st);
-        if (e != hipSuccess) return status_of(e);
+    const bool split = side && has_independent_parts(pl);
+    const int main = split ? main_tile(pl) : 0;
+    hipStream_t other = split ? side : st;
+    if (split) {
+        if ((e = hipEventRecord(fork, st)) != hipSuccess) return status_of(e);
+        if ((e = hipStreamWaitEvent(side, fork, 0)) != hipSuccess) return status_of(e);
     }
-    if (pl->count == pl->n_staged) return FW_OK;
-    batch_reset_kernel<<<1, 64, 0, st>>>(hdr);
-    if ((e = hipGetLastError()) != hipSuccess) return status_of(e);
-    const BatchItem *rest = items + pl->n_staged;
-    if (untimed)
-        return status_of(
-            launch_batched_raw(pl->dtype, pl->pred, hdr, rest, pl->grid, st, pl->big));
-    return status_of(timed_launch_batched(pl->updates, st, pl->dtype, pl->pred, pl->big, hdr,
-                                          rest, pl->grid));
+    // the side stream's sequences first, so they start with the main chain
+    for (int pass = split ? 0 : 1; pass < 2; ++pass) {
+        for (const StagedLaunch &l : pl->staged) {
+            if (split && (pass == 0) == (l.tile == main)) continue;
+            e = launch_staged(pl->dtype, pl->pred, l.tile, items, pl->work + l.offset, l.kind,
+                              l.b, (unsigned)l.count, pass == 0 ? other : st);
+            if (e != hipSuccess) return status_of(e);
+        }
+        if (pass == 0 || !split) {
+            if (pl->count > pl->n_staged) {
+                batch_reset_kernel<<<1, 64, 0, other>>>(hdr);
+                if ((e = hipGetLastError()) != hipSuccess) return status_of(e);
+                const BatchItem *rest = items + pl->n_staged;
+                e = untimed ? launch_batched_raw(pl->dtype, pl->pred, hdr, rest, pl->grid, other,
+                                                 pl->big)
+                            : timed_launch_batched(pl->updates, other, pl->dtype, pl->pred,
+                                                   pl->big, hdr, rest, pl->grid);
+                if (e != hipSuccess) return status_of(e);
+            }
+        }
+    }
+    if (split) {
+        if ((e = hipEventRecord(join, side)) != hipSuccess) return status_of(e);
+        if ((e = hipStreamWaitEvent(st, join, 0)) != hipSuccess) return status_of(e);
+    }
+    return FW_OK;
+}
+
+// The plan's side stream and fork / join events, created on first use.
+hipError_t plan_side(fw_batch_plan_s *pl) {
+    if (pl->side) return hipSuccess;
+    hipError_t e = hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->join, hipEventDisableTiming);
+    return e;
 }
 
 void free_plan(fw_batch_plan_s *pl) {
@@ -702,6 +759,9 @@ void free_plan(fw_batch_plan_s *pl) {
     if (pl->exec) hipGraphExecDestroy(pl->exec);
     if (pl->graph) hipGraphDestroy(pl->graph);
     if (pl->cap_stream) hipStreamDestroy(pl->cap_stream);
+    if (pl->side) hipStreamDestroy(pl->side);
+    if (pl->fork) hipEventDestroy(pl->fork);
+    if (pl->join) hipEventDestroy(pl->join);
     if (pl->dev) hipFree(pl->dev);
     if (pl->host) hipHostFree(pl->host);
     delete pl;
@@ -838,13 +898,18 @@ int fw_batch_plan_launch(fw_batch_plan plan, int mode, void *stream) {
         }
         return FW_OK;
     }
-    if (mode == 0 || plan->count == 0) return enqueue_plan(plan, st, false);
+    if (plan->count && has_independent_parts(plan)) {
+        hipError_t e = plan_side(plan);
+        if (e != hipSuccess) return status_of(e);
+    }
+    if (mode == 0 || plan->count == 0)
+        return enqueue_plan(plan, st, false, plan->side, plan->fork, plan->join);
     if (!plan->exec) {
         hipError_t e = hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking);
         if (e != hipSuccess) return status_of(e);
         e = hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return status_of(e);
-        int s = enqueue_plan(plan, plan->cap_stream, true);
+        int s = enqueue_plan(plan, plan->cap_stream, true, plan->side, plan->fork, plan->join);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(plan->cap_stream, &g);
         if (s != FW_OK) {

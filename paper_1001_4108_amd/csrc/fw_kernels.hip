@@ -210,8 +210,10 @@ pred_fix_kernel(const T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t
 // ---------------------------------------------------------------------------
 // The keyed int32 predecessor solve (keys as in fw_internal.h).
 // ---------------------------------------------------------------------------
-// Zero the scratch: the flag, and the row and column minima, which start at
-// 0 -- the empty path from a vertex to itself.
+// Zero the head of the scratch: the flags, and the row and column minima,
+// which start at 0 -- the empty path from a vertex to itself.  (The cleared
+// column panel after them is written by each stage's panel launch before
+// its bulk reads it.)
 __global__ void __launch_bounds__(256)
 key_zero_kernel(int32_t *__restrict__ scratch, int64_t words) {
     for (int64_t w = blockIdx.x * 256 + threadIdx.x; w < words; w += (int64_t)gridDim.x * 256)
@@ -626,7 +628,7 @@ hipError_t launch_pred_fix(int dtype, const void *d, int32_t *p, int n, int64_t 
 
 hipError_t launch_key_prepare(const int32_t *d, int32_t *keys, int n, int64_t ld, int64_t ldk,
                               int32_t *scratch, hipStream_t st) {
-    const int64_t words = key_scratch_words(n);
+    const int64_t words = key_acol_offset(n);
     key_zero_kernel<<<(unsigned)((words + 255) / 256), 256, 0, st>>>(scratch, words);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

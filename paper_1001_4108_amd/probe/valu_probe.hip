@@ -11,7 +11,13 @@
 //   form 2  int32 min-plus, two k-steps fused      (2 v_add_u32 + 1 v_min3_i32)
 //   form 3  v_fma_f32                              (c = a * b + c)
 //   form 4  bit-packed reachability                (v_and_or_b32 per word)
-// Instructions per step and thread: 64 (forms 0, 3, 4) or 192 (forms 1, 2).
+// and single instructions of the int32 mix, to see which part sets its rate:
+//   form 5  v_add_u32 alone                        (c = c + a)
+//   form 6  v_min3_i32 alone                       (c = min(c, a, b))
+//   form 7  v_minimum3_f32 alone                   (c = minimum(c, a, b))
+//   form 8  2 v_add_u32 + 1 v_minimum3_f32         (form 2 with the fp32
+//                                                   minimum on the sums' bits)
+// Instructions per step and thread: 192 (forms 1, 2, 8), else 64.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -53,6 +59,23 @@ __global__ void __launch_bounds__(256) valu_kernel(const float *__restrict__ src
                     c[i][j] = __int_as_float(m);
                 } else if constexpr (FORM == 3) {
                     c[i][j] = __builtin_fmaf(a[i], b[j], c[i][j]);
+                } else if constexpr (FORM == 5) {
+                    c[i][j] = __int_as_float(__float_as_int(c[i][j]) + __float_as_int(a[i]));
+                } else if constexpr (FORM == 6) {
+                    const int x = __float_as_int(c[i][j]), y = __float_as_int(a[i]);
+                    const int z = __float_as_int(b[j]);
+                    int m = x < y ? x : y;
+                    m = m < z ? m : z;
+                    c[i][j] = __int_as_float(m);
+                } else if constexpr (FORM == 7) {
+                    c[i][j] = __builtin_elementwise_minimum(
+                        __builtin_elementwise_minimum(c[i][j], a[i]), b[j]);
+                } else if constexpr (FORM == 8) {
+                    const int s0 = __float_as_int(a[i]) + __float_as_int(b[j]);
+                    const int s1 = __float_as_int(a1[i]) + __float_as_int(b1[j]);
+                    c[i][j] = __builtin_elementwise_minimum(
+                        __builtin_elementwise_minimum(c[i][j], __int_as_float(s0)),
+                        __int_as_float(s1));
                 } else {
                     const uint32_t x = __float_as_uint(c[i][j]);
                     c[i][j] = __uint_as_float((x & __float_as_uint(a[i])) | __float_as_uint(b[j]));
@@ -74,7 +97,7 @@ extern "C" {
 
 // Instructions per loop step and thread of each form (the counts above).
 int fw_probe_valu_instr_per_step(int form) {
-    return (form == 1 || form == 2) ? 192 : 64;
+    return (form == 1 || form == 2 || form == 8) ? 192 : 64;
 }
 
 // Runs `form` on `blocks` x 256 threads for `iters` steps on `stream` after
@@ -82,7 +105,7 @@ int fw_probe_valu_instr_per_step(int form) {
 // floats of device memory; dst: blocks * 256 * 64 floats.  0 on success.
 int fw_probe_valu(int form, int blocks, int iters, const float *src, float *dst, void *stream,
                   float *ms) {
-    if (form < 0 || form > 4 || blocks <= 0 || iters <= 0 || !src || !dst || !ms) return 1;
+    if (form < 0 || form > 8 || blocks <= 0 || iters <= 0 || !src || !dst || !ms) return 1;
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return 2;
@@ -93,7 +116,11 @@ int fw_probe_valu(int form, int blocks, int iters, const float *src, float *dst,
         case 1: valu_kernel<1><<<blocks, 256, 0, st>>>(src, dst, n); break;
         case 2: valu_kernel<2><<<blocks, 256, 0, st>>>(src, dst, n); break;
         case 3: valu_kernel<3><<<blocks, 256, 0, st>>>(src, dst, n); break;
-        default: valu_kernel<4><<<blocks, 256, 0, st>>>(src, dst, n); break;
+        case 4: valu_kernel<4><<<blocks, 256, 0, st>>>(src, dst, n); break;
+        case 5: valu_kernel<5><<<blocks, 256, 0, st>>>(src, dst, n); break;
+        case 6: valu_kernel<6><<<blocks, 256, 0, st>>>(src, dst, n); break;
+        case 7: valu_kernel<7><<<blocks, 256, 0, st>>>(src, dst, n); break;
+        default: valu_kernel<8><<<blocks, 256, 0, st>>>(src, dst, n); break;
         }
     };
     go(iters);
