@@ -88,6 +88,8 @@ def parse():
     ap.add_argument("--cpu-ksteps-one-core", type=int, default=96,
                     help="k-iterations of the oracle timed on one thread")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-pred-f32", action="store_true",
+                    help="skip the fp32 n=8192 solve with predecessors")
     ap.add_argument("--no-captured", action="store_true",
                     help="skip timing the solve as one captured-graph launch")
     ap.add_argument("--no-probe", action="store_true",
@@ -508,6 +510,51 @@ def bench_negative(torch, fw, gen, dev, reps=3):
     return out
 
 
+def bench_pred_f32(torch, fw, gen, dev, reps=3):
+    """n=8192 fp32 (edge prob 0.3, integer weights [1,1000]) with predecessors:
+    the keyed sweep (integer weights), and for contrast the same graph with
+    every weight raised by 0.5, which takes the fp32 compare form.  Each timed
+    solve on its own pre-filled copy; rows checked against the oracle."""
+    import numpy as np
+    import oracle
+    n = 8192
+    W = gen.single_graph_16384(n)
+    Wh = W.copy()
+    Wh[np.isfinite(Wh)] += 0.5
+    np.fill_diagonal(Wh, 0)
+    P = torch.empty((n, n), dtype=torch.int32, device=dev)
+    srcs = np.array([5, 4097, 8000])
+    out = {"workload": "single graph n=8192 fp32, edge prob 0.3, integer weights [1,1000], +INF "
+                       "absent, with predecessors; compare form: the same graph + 0.5 per weight",
+           "n": n, "tile": {"keyed_sweep": fw.plan_tile(torch.float32, n),
+                            "compare_form": fw.plan_tile(torch.float32, n, pred=True)}}
+    ok = True
+    for mode, w, r in (("keyed", W, reps), ("compare_form", Wh, 1)):
+        pristine = torch.from_numpy(w).to(dev)
+        bufs = [torch.empty_like(pristine) for _ in range(r)]
+        bufs[0].copy_(pristine)
+        fw.fw_apsp_pred(bufs[0], P)  # warm-up
+        for b in bufs:
+            b.copy_(pristine)
+        fb0 = fw.pred_fallbacks()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for b in bufs:
+            fw.fw_apsp_pred(b, P)
+        torch.cuda.synchronize(dev)
+        ms = (time.perf_counter() - t0) * 1e3 / r
+        out[mode] = {"ms": ms, "updates_per_s": float(n) ** 3 / (ms / 1e3),
+                     "fallbacks": fw.pred_fallbacks() - fb0}
+        idx = torch.from_numpy(srcs).to(dev)
+        rows = bufs[-1][idx].cpu().numpy()
+        ref = oracle.dijkstra_rows(w, srcs).astype(np.float32)
+        ok &= bool(np.array_equal(rows.view(np.uint32), ref.view(np.uint32)))
+        ok &= bool(np.array_equal(P[idx].cpu().numpy(), oracle.canonical_pred(ref, w, rows=srcs)))
+        del bufs, pristine
+    out["check"] = "ok" if ok else "mismatch"
+    return out
+
+
 def bench_batched(torch, fw, gen, dev, reps, modes=("graph", "kernel", "per_graph"), tiles=None):
     """Ragged batch: 4096 graphs, n log-uniform in [16, 512], fp32."""
     import numpy as np
@@ -855,6 +902,13 @@ def main():
         log(f"negative: {negative['with_pred']['ms']:.1f} ms with predecessors, "
             f"{negative['distances_only']['ms']:.1f} ms distances only")
 
+    pred_f32 = None
+    if not args.no_pred_f32:
+        log("fp32 n=8192 with predecessors (keyed, and the compare form)")
+        pred_f32 = bench_pred_f32(torch, fw, gen, dev)
+        log(f"fp32 predecessors: {pred_f32['keyed']['ms']:.1f} ms keyed, "
+            f"{pred_f32['compare_form']['ms']:.1f} ms compare form")
+
     batched = None
     if not args.no_batched:
         log("batched: 4096 ragged graphs")
@@ -894,7 +948,8 @@ def main():
         "check": "ok" if ok else "mismatch",
         "phases": phases, "captured_graph": captured, "roofline": roof, "cpu_baseline": cpu,
         "valu_probe": probe,
-        "small_n512": small, "negative_int32_pred": negative, "maxmin": maxmin,
+        "small_n512": small, "negative_int32_pred": negative, "pred_f32": pred_f32,
+        "maxmin": maxmin,
         "transitive_closure": closure, "ladder": ladder,
         "batched": batched,
         "serving": serving,

@@ -104,15 +104,18 @@ int fw_apsp_i32(int32_t *d, int64_t n, int64_t ld, void *stream);
  *              closed walk that made d_ii negative (see
  *              fw_negative_cycle_find); the other entries are then as
  *              computed.
- * int32 with pred, 2 <= n <= 16383: the (distance, last hop) pairs are first
- * swept as 32-bit keys (distance * 2^14 + last hop) held in `pred`, at the
- * cost of the distances-only sweep; this takes 8n + 16 bytes of
- * stream-ordered device memory (hipMallocAsync on `stream`, freed on it).
- * When some distance met during that sweep has |d| >= 2^14, or a diagonal
- * entry ends negative, the 64-bit form already queued behind it (each launch
- * gated on a device flag) solves again from the untouched d.  The results are
- * the same in every case, so the choice is invisible except in time
- * (fw_pred_fallbacks counts the second sweeps).
+ * With pred and 2 <= n <= 16383 the (distance, last hop) pairs are first
+ * swept as 32-bit integer keys (distance * 2^14 + last hop) held in `pred`,
+ * at the cost of the int32 distances-only sweep; this takes 16 + 8n + 512n
+ * bytes (rounded to 256) of stream-ordered device memory (hipMallocAsync on
+ * `stream`, freed on it).  When an entry of d is not an integer with
+ * |w| < 2^14 (fp32: also a fraction), some distance met during that sweep
+ * has |d| >= 2^14, or a diagonal entry ends negative, the pair form already
+ * queued behind it (64-bit keys for int32, compares for fp32; each launch
+ * gated on a device flag) solves again from the untouched d.  Within that
+ * range fp32 arithmetic on integers is exact, so the results are the same in
+ * every case and the choice is invisible except in time (fw_pred_fallbacks
+ * counts the second sweeps).
  * Errors: as fw_apsp, plus FW_ERR_INVALID for a bad dtype or, with pred
  * non-NULL, ld_pred < n or n*ld_pred overflowing int64.
  */
@@ -482,10 +485,9 @@ int64_t fw_path(const int32_t *pred_host, int64_t n, int64_t ld_pred, int64_t i,
  *                         choice at creation.  Nothing is enqueued; the
  *                         matrices must stay allocated for the plan's
  *                         lifetime and are re-solved in place on every
- *                         launch.  An int32 plan with predecessors allocates
- *                         the keyed sweep's 8n + 16 bytes of scratch here
- *                         (FW_ERR_NOMEM if it cannot); its launches then
- *                         allocate nothing.
+ *                         launch.  A plan with predecessors allocates the
+ *                         keyed sweep's scratch here (FW_ERR_NOMEM if it
+ *                         cannot); its launches then allocate nothing.
  *   fw_solve_plan_launch  mode 0: the solve as eager launches on `stream`
  *                         (fw_apsp_plan); mode 1: on the first call the
  *                         launches are captured into a hipGraph on a stream
@@ -529,8 +531,8 @@ int fw_profile_read(double *ms, int64_t *launches, int cap);
 int fw_profile_updates(double *updates, int cap);
 
 /*
- * fw_pred_fallbacks -- how many int32 solves with predecessors on the current
- * device have run their 64-bit sweep because the 32-bit keyed one gave up
+ * fw_pred_fallbacks -- how many solves with predecessors on the current
+ * device have run their pair-form sweep because the 32-bit keyed one gave up
  * (see fw_apsp_pred), since the library was loaded.  Synchronises the device;
  * -1 when the count cannot be read.
  */

@@ -621,8 +621,8 @@ KINDS = ("diag", "panel", "bulk", "pred", "batched", "bits_diag", "bits_panel", 
 
 
 def pred_fallbacks() -> int:
-    """Number of int32 solves with predecessors on the current device whose
-    32-bit keyed sweep gave up and ran the 64-bit sweep (synchronises)."""
+    """Number of solves with predecessors on the current device whose 32-bit
+    keyed sweep gave up and ran the pair-form sweep (synchronises)."""
     v = lib().fw_pred_fallbacks()
     if v < 0:
         raise FwError(2, "fw_pred_fallbacks")

@@ -51,11 +51,13 @@ void default_plan_locked() {
         // 1.4x).  With the (distance, last hop) pair forms tile 128 never won
         // (int32 with 64-bit keys at n=8192: 69 vs 82 ms at tile 64), and
         // tile 32 wins below ~2k (fp32) / ~1k (int32) vertices (fp32 n~1448:
-        // 4.0 vs 4.6 ms; int32 n~724: 0.78 vs 0.83) -- the forms batched
-        // solves with predecessors still use.  A single int32 solve with
-        // predecessors runs the 32-bit keyed sweep, i.e. the distances-only
-        // kernels, so above 1k vertices it takes their tiles (its gated 64-bit
-        // sweep takes the same tile; at 128 it has half the launches to skip).
+        // 4.0 vs 4.6 ms; int32 n~724: 0.78 vs 0.83).  These entries pick the
+        // pair forms' tile: batched solves with predecessors, and the gated
+        // sweep behind the keyed one of a single solve, whose own tile is the
+        // distances-only entry's (it runs those kernels).  Above 4k int32
+        // vertices the gated 64-bit sweep takes tile 128: when it runs it is
+        // slower than at 64 (82 vs 69 ms at n=8192), but it has half the
+        // launches to skip when its gate stays closed, the usual case.
         if (key & FW_PLAN_PRED) {
             const bool i32 = (key & 1) == FW_I32;
             const int64_t hi32 = i32 ? 1024 : 2048;
@@ -235,17 +237,19 @@ int enqueue_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t 
     return FW_OK;
 }
 
-// int32 with predecessors as a keyed sweep (fw_internal.h): the pairs packed
-// into 32-bit keys in the predecessor matrix, the distances-only schedule and
-// arithmetic over them, the keys unpacked into d and P.  If a real key
-// leaves its range or a diagonal entry ends negative, the unpack leaves d
-// untouched and the 64-bit sweep queued behind it (same tile, every launch
-// gated on the flag) solves from the original d; the results are the same
-// either way.  Scratch: `scratch` (a solve plan's), else
-// stream-ordered memory of this call.  Returns FW_ERR_UNSUPPORTED, nothing
-// enqueued, when no scratch can be had (the caller then runs the 64-bit sweep).
-int enqueue_solve_keyed(int32_t *d, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
-                        hipStream_t st, bool capturing, int32_t *scratch) {
+// A solve with predecessors as a keyed sweep (fw_internal.h): the pairs
+// packed into 32-bit keys in the predecessor matrix, the distances-only
+// schedule and int32 arithmetic over them with tile `key_tile`, the keys
+// unpacked into d (int32 or fp32) and P.  If an entry is not an integer of
+// the key range, a real key leaves its range or a diagonal entry ends
+// negative, the unpack leaves d untouched and the pair-form sweep queued
+// behind it (tile `tile`, every launch gated on the flag) solves from the
+// original d; the results are the same either way.  Scratch: `scratch` (a
+// solve plan's), else stream-ordered memory of this call.  Returns
+// FW_ERR_UNSUPPORTED, nothing enqueued, when no scratch can be had (the
+// caller then runs the pair-form sweep).
+int enqueue_solve_keyed(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp,
+                        int tile, int key_tile, hipStream_t st, bool capturing, int32_t *scratch) {
     bool own = false;
     if (!scratch) {
         if (capturing) return FW_ERR_UNSUPPORTED;
@@ -262,32 +266,37 @@ int enqueue_solve_keyed(int32_t *d, int n, int64_t ld, int32_t *pred, int64_t ld
         return timed(kind, 0.0, st, launch);
     };
     int s = FW_OK;
-    hipError_t e =
-        run(kPredFix, [&] { return launch_key_prepare(d, pred, n, ld, ldp, scratch, st); });
+    hipError_t e = run(kPredFix, [&] {
+        return launch_key_prepare(dtype, d, pred, n, ld, ldp, scratch, st);
+    });
     if (e != hipSuccess) s = status_of(e);
     if (s == FW_OK)
-        s = enqueue_solve(pred, FW_I32, n, ldp, nullptr, 0, tile, st, capturing, kKey, scratch,
-                          nullptr);
+        s = enqueue_solve(pred, FW_I32, n, ldp, nullptr, 0, key_tile, st, capturing, kKey,
+                          scratch, nullptr);
     if (s == FW_OK) {
-        e = run(kPredFix, [&] { return launch_key_finish(d, pred, n, ld, ldp, scratch, st); });
+        e = run(kPredFix, [&] {
+            return launch_key_finish(dtype, d, pred, n, ld, ldp, scratch, st);
+        });
         if (e != hipSuccess) s = status_of(e);
     }
     if (s == FW_OK)
-        s = enqueue_solve(d, FW_I32, n, ld, pred, ldp, tile, st, capturing, kMinPlus, nullptr,
+        s = enqueue_solve(d, dtype, n, ld, pred, ldp, tile, st, capturing, kMinPlus, nullptr,
                           scratch);
     if (own) hipFreeAsync(scratch, st);
     return s;
 }
 
-bool keyed_solve(int dtype, const int32_t *pred, int n, int sr) {
-    return dtype == FW_I32 && pred && sr == kMinPlus && n > 1 && n <= kKeyMaxN;
+bool keyed_solve(const int32_t *pred, int n, int sr) {
+    return pred && sr == kMinPlus && n > 1 && n <= kKeyMaxN;
 }
 
-// Enqueue the whole solve for one graph.  Arguments already valid.
-// `key_scratch`: a solve plan's scratch for a keyed sweep.
+// Enqueue the whole solve for one graph.  Arguments already valid.  `tile`
+// is the tile of the solve (with predecessors: of the pair-form sweep);
+// `key_tile` that of a keyed sweep (0: `tile`); `key_scratch` a solve plan's
+// scratch for it.
 int solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
           hipStream_t st, bool capturing = false, int sr = kMinPlus,
-          int32_t *key_scratch = nullptr) {
+          int32_t *key_scratch = nullptr, int key_tile = 0) {
     if (n <= 1) {
         if (pred && n == 1) {
             hipError_t e = capturing ? launch_pred_fix(dtype, d, pred, n, ld, ldp, st)
@@ -299,12 +308,20 @@ int solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int
         return FW_OK;
     }
     if (!tile_supported(tile)) return FW_ERR_INVALID;
-    if (keyed_solve(dtype, pred, n, sr)) {
-        const int s = enqueue_solve_keyed((int32_t *)d, n, ld, pred, ldp, tile, st, capturing,
-                                          key_scratch);
+    if (keyed_solve(pred, n, sr)) {
+        if (key_tile == 0) key_tile = tile;
+        if (!tile_supported(key_tile)) return FW_ERR_INVALID;
+        const int s = enqueue_solve_keyed(d, dtype, n, ld, pred, ldp, tile, key_tile, st,
+                                          capturing, key_scratch);
         if (s != FW_ERR_UNSUPPORTED) return s;
     }
     return enqueue_solve(d, dtype, n, ld, pred, ldp, tile, st, capturing, sr);
+}
+
+// The plan table's tile for a keyed sweep: the distances-only entry, whose
+// kernels it runs (0 for a solve without predecessors).
+int key_tile_for(int dtype, const int32_t *pred, int64_t n) {
+    return pred ? plan_tile(dtype, n) : 0;
 }
 
 }  // namespace
@@ -315,7 +332,8 @@ int plan_tile_for(int dtype, int64_t n, bool pred) {
 
 int solve_single(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64_t ldp,
                  hipStream_t st) {
-    return solve(d, dtype, (int)n, ld, pred, ldp, plan_tile(plan_key(dtype, pred), n), st);
+    return solve(d, dtype, (int)n, ld, pred, ldp, plan_tile(plan_key(dtype, pred), n), st, false,
+                 kMinPlus, nullptr, key_tile_for(dtype, pred, n));
 }
 
 int solve_with_tile(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
@@ -377,7 +395,7 @@ int fw_apsp_pred(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64
     int s = validate(d, dtype, n, ld, pred, ld_pred);
     if (s != FW_OK) return s;
     return solve(d, dtype, (int)n, ld, pred, ld_pred, plan_tile(plan_key(dtype, pred), n),
-                 (hipStream_t)stream);
+                 (hipStream_t)stream, false, kMinPlus, nullptr, key_tile_for(dtype, pred, n));
 }
 
 int fw_apsp_plan(void *d, int dtype, int64_t n, int64_t ld, int32_t *pred, int64_t ld_pred,
@@ -602,8 +620,8 @@ struct fw_solve_plan_s {
     int n = 0;
     int64_t ld = 0, ldp = 0;
     int32_t *pred = nullptr;
-    int tile = 0;
-    int32_t *key_scratch = nullptr;  // the keyed int32 predecessor sweep's
+    int tile = 0, key_tile = 0;
+    int32_t *key_scratch = nullptr;  // the keyed predecessor sweep's
     int device = 0;
     // the capture stream lives as long as the plan (and with it the graph
     // captured on it); no event is recorded during the capture
@@ -639,11 +657,12 @@ int fw_solve_plan_create(void *d, int dtype, int64_t n, int64_t ld, int32_t *pre
     pl->pred = pred;
     pl->ldp = pred ? ld_pred : 0;
     pl->tile = n <= 1 ? 32 : tile ? tile : plan_tile(plan_key(dtype, pred), n);
+    pl->key_tile = n <= 1 ? 0 : tile ? tile : key_tile_for(dtype, pred, n);
     if (hipGetDevice(&pl->device) != hipSuccess) {
         delete pl;
         return FW_ERR_HIP;
     }
-    if (keyed_solve(dtype, pred, (int)n, kMinPlus)) {
+    if (keyed_solve(pred, (int)n, kMinPlus)) {
         void *mem = nullptr;
         hipError_t e = hipMalloc(&mem, (size_t)key_scratch_words(n) * 4);
         if (e != hipSuccess) {
@@ -661,7 +680,7 @@ int fw_solve_plan_launch(fw_solve_plan pl, int mode, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     if (mode == 0 || pl->n <= 1)
         return solve(pl->d, pl->dtype, pl->n, pl->ld, pl->pred, pl->ldp, pl->tile, st, false,
-                     kMinPlus, pl->key_scratch);
+                     kMinPlus, pl->key_scratch, pl->key_tile);
     if (!pl->exec) {
         hipError_t e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
         if (e != hipSuccess) {
@@ -671,7 +690,7 @@ int fw_solve_plan_launch(fw_solve_plan pl, int mode, void *stream) {
         e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return status_of(e);
         int s = solve(pl->d, pl->dtype, pl->n, pl->ld, pl->pred, pl->ldp, pl->tile,
-                      pl->cap_stream, true, kMinPlus, pl->key_scratch);
+                      pl->cap_stream, true, kMinPlus, pl->key_scratch, pl->key_tile);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(pl->cap_stream, &g);
         if (s != FW_OK) {

@@ -85,14 +85,14 @@ hipError_t launch_pred_init(int dtype, const void *d, int32_t *p, int n, int64_t
 // With a gate, a fix-up that runs also counts one fallback (pred_fallbacks).
 hipError_t launch_pred_fix(int dtype, const void *d, int32_t *p, int n, int64_t ld,
                            int64_t ldp, hipStream_t st, const int32_t *gate = nullptr);
-// The keyed int32 predecessor solve around the sweep (scratch as
+// The keyed predecessor solve around the sweep (d int32 or fp32; scratch as
 // key_scratch_words): key_prepare zeroes the scratch and writes the keys of
 // d into `keys`; key_finish takes the row and column minima, raises the flag
 // on a negative diagonal, and -- unless the flag is set -- writes the
 // distances into d and the predecessors into `keys`, in place.
-hipError_t launch_key_prepare(const int32_t *d, int32_t *keys, int n, int64_t ld, int64_t ldk,
-                              int32_t *scratch, hipStream_t st);
-hipError_t launch_key_finish(int32_t *d, int32_t *keys, int n, int64_t ld, int64_t ldk,
+hipError_t launch_key_prepare(int dtype, const void *d, int32_t *keys, int n, int64_t ld,
+                              int64_t ldk, int32_t *scratch, hipStream_t st);
+hipError_t launch_key_finish(int dtype, void *d, int32_t *keys, int n, int64_t ld, int64_t ldk,
                              int32_t *scratch, hipStream_t st);
 // Number of gated 64-bit predecessor sweeps that ran on the current device
 // (synchronises the device).

@@ -59,13 +59,25 @@ namespace {
 // gave up.  The gate is uniform, so the whole workgroup leaves at once.
 __device__ __forceinline__ bool gated_off(const int32_t *gate) { return gate && *gate == 0; }
 
+// A keyed launch whose solve has already given up (its flag set by an earlier
+// launch or the packing) has nothing useful to do: the 64-bit sweep behind it
+// starts over from the input.  A flag raised during the launch is only seen
+// by later launches.
+template <class A>
+__device__ __forceinline__ bool given_up(const int32_t *flag) {
+    if constexpr (A::kChecked)
+        return *flag != 0;
+    else
+        return false;
+}
+
 // Phase 1: closure of the diagonal tile (b, b) -- one workgroup.
 template <typename T, int S, int TM, bool PRED, class A>
 __global__ void __launch_bounds__((S / TM) * (S / TM))
 diag_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64_t ldp,
             int b, int32_t *flag, const int32_t *gate) {
     __shared__ __align__(16) char smem[closure_smem_bytes<T, S, PRED>()];
-    if (gated_off(gate)) return;
+    if (gated_off(gate) || given_up<A>(flag)) return;
     closure_tile<T, S, TM, PRED, A>(d, P, n, ld, ldp, b * S, smem, flag);
 }
 
@@ -102,7 +114,7 @@ __global__ void __launch_bounds__((S / TM) * (S / TN))
 tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64_t ldp, int b,
             int nb, int mode, int close_next, int32_t *flag, const int32_t *gate) {
     __shared__ __align__(16) char smem[tile_smem_bytes<T, S, BK, PRED, A>()];
-    if (gated_off(gate)) return;
+    if (gated_off(gate) || given_up<A>(flag)) return;
     int idx = blockIdx.x, bi, bj;
     bool close = false;
     if constexpr (tile_can_close<S, TM, TN, PRED>()) {
@@ -145,6 +157,7 @@ template <typename T, class A>
 __global__ void __launch_bounds__(256, FW_BULK_DMA_WAVES)
 bulk_dma_kernel(T *__restrict__ d, int n, int64_t ld, int b, int mf, int close_next,
                 int32_t *flag, const T *acol) {
+    if (given_up<A>(flag)) return;
     int idx = blockIdx.x;
     const int dix = b * mf + b;  // enumeration index of tile (b+1, b+1)
     if (close_next) idx = idx == 0 ? dix : idx == dix ? 0 : idx;
@@ -163,6 +176,7 @@ panel_strip_kernel(T *__restrict__ d, int n, int64_t ld, int b, int nb, int32_t 
                    T *acol) {
     constexpr int S = 128, W = 32;
     __shared__ __align__(16) char smem[strip_smem_bytes<T, S, W, S, 16>()];  // R + CW = 160 either way
+    if (given_up<A>(flag)) return;
     const int m = nb - 1;
     const int t = blockIdx.x >> 2, q = blockIdx.x & 3;
     int bi, bj;
@@ -222,18 +236,29 @@ key_zero_kernel(int32_t *__restrict__ scratch, int64_t words) {
 
 // key_ij = d_ij * 2^kKeyBits + (last hop of the edge: i; none on the
 // diagonal), kKeyInf for an absent pair -- the keyed form of the predecessor
-// initialisation.  A real entry with |d_ij| >= 2^14 raises the flag.
+// initialisation.  An entry that is not an integer with |d_ij| < 2^14 (fp32:
+// also a fraction, a NaN or -INF) raises the flag; within that range fp32
+// sums of integers are exact, so the int32 keys compute what the fp32
+// compare form does.
+template <typename T>
 __global__ void __launch_bounds__(256)
-key_pack_kernel(const int32_t *__restrict__ d, int32_t *__restrict__ keys, int n, int64_t ld,
+key_pack_kernel(const T *__restrict__ d, int32_t *__restrict__ keys, int n, int64_t ld,
                 int64_t ldk, int32_t *__restrict__ flag) {
     bool bad = false;
     for (int i = blockIdx.y; i < n; i += gridDim.y)
         for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
-            const int32_t w = d[(int64_t)i * ld + j];
+            const T w = d[(int64_t)i * ld + j];
             int32_t key = kKeyInf;
-            if (w != kI32Inf) {
-                bad |= w <= -(1 << kKeyBits) || w >= (1 << kKeyBits);
-                key = (int32_t)((uint32_t)w << kKeyBits) + (i == j ? kKeyHop : i);
+            if (!Ar<T>::absent(w)) {
+                int32_t v;
+                if constexpr (std::is_same<T, float>::value) {
+                    bad |= !(w == __builtin_rintf(w)) || !(__builtin_fabsf(w) < (float)(1 << kKeyBits));
+                    v = bad ? 0 : (int32_t)w;
+                } else {
+                    bad |= w <= -(1 << kKeyBits) || w >= (1 << kKeyBits);
+                    v = w;
+                }
+                key = (int32_t)((uint32_t)v << kKeyBits) + (i == j ? kKeyHop : i);
             }
             keys[(int64_t)i * ldk + j] = key;
         }
@@ -263,18 +288,20 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 
 // Unless the flag is set: every key becomes its distance in d and its last
 // hop in the key matrix, now the predecessor matrix as pred_fix_kernel
-// leaves it (-1 on the diagonal and for an infinite key).  An infinite key
-// (j not reachable from i) leaves FW_I32_INF in d, for key_inf_kernel, and
-// raises the "some pair unreachable" word.  On the way, the row and column
-// minima of the finite distances (starting at 0): a workgroup covers 256
-// columns of kMinRows rows, a column's minimum kept per thread, a row's
-// reduced over each wave and then over the four waves in LDS, both folded in
-// with atomicMin.
+// leaves it (-1 on the diagonal and for an infinite key).  fp32: an infinite
+// key (j not reachable from i) is +INF, as in the fp32 sweep.  int32: it
+// leaves FW_I32_INF in d, for key_inf_kernel, and raises the "some pair
+// unreachable" word; on the way, the row and column minima of the finite
+// distances (starting at 0): a workgroup covers 256 columns of kMinRows
+// rows, a column's minimum kept per thread, a row's reduced over each wave
+// and then over the four waves in LDS, both folded in with atomicMin.
 constexpr int kMinRows = 64;
 
+template <typename T>
 __global__ void __launch_bounds__(256)
-key_unpack_kernel(int32_t *__restrict__ d, int32_t *__restrict__ keys, int n, int64_t ld,
-                  int64_t ldk, int32_t *__restrict__ scratch) {
+key_unpack_kernel(T *__restrict__ d, int32_t *__restrict__ keys, int n, int64_t ld, int64_t ldk,
+                  int32_t *__restrict__ scratch) {
+    constexpr bool I32 = std::is_same<T, int32_t>::value;
     __shared__ int32_t wmin[4][kMinRows];
     if (scratch[0] != 0) return;
     int32_t *rowmin = scratch + 4, *colmin = scratch + 4 + n;
@@ -289,9 +316,11 @@ key_unpack_kernel(int32_t *__restrict__ d, int32_t *__restrict__ keys, int n, in
         if (j < n) {
             int32_t &k = keys[(int64_t)i * ldk + j];
             const int32_t key = k;
-            int32_t dist = kI32Inf, hop = -1;
+            T dist = Ar<T>::inf();
+            int32_t hop = -1;
             if (key < kKeyInfFloor) {
-                dist = v = key >> kKeyBits;
+                v = key >> kKeyBits;
+                dist = (T)v;
                 const int32_t h = key & kKeyHop;
                 if (i != j && h != kKeyHop) hop = h;
             } else {
@@ -300,10 +329,13 @@ key_unpack_kernel(int32_t *__restrict__ d, int32_t *__restrict__ keys, int n, in
             d[(int64_t)i * ld + j] = dist;
             k = hop;
         }
-        cmin = v < cmin ? v : cmin;
-        const int32_t rm = wave_min(v);
-        if ((threadIdx.x & 63) == 0) wmin[wave][r] = rm;
+        if constexpr (I32) {
+            cmin = v < cmin ? v : cmin;
+            const int32_t rm = wave_min(v);
+            if ((threadIdx.x & 63) == 0) wmin[wave][r] = rm;
+        }
     }
+    if constexpr (!I32) return;
     __syncthreads();
     if ((int)threadIdx.x < rows) {
         const int t = threadIdx.x;
@@ -626,26 +658,35 @@ hipError_t launch_pred_fix(int dtype, const void *d, int32_t *p, int n, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_key_prepare(const int32_t *d, int32_t *keys, int n, int64_t ld, int64_t ldk,
-                              int32_t *scratch, hipStream_t st) {
+hipError_t launch_key_prepare(int dtype, const void *d, int32_t *keys, int n, int64_t ld,
+                              int64_t ldk, int32_t *scratch, hipStream_t st) {
     const int64_t words = key_acol_offset(n);
     key_zero_kernel<<<(unsigned)((words + 255) / 256), 256, 0, st>>>(scratch, words);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    key_pack_kernel<<<elementwise_grid(n), 256, 0, st>>>(d, keys, n, ld, ldk, scratch);
+    if (dtype == 0)
+        key_pack_kernel<float><<<elementwise_grid(n), 256, 0, st>>>((const float *)d, keys, n, ld,
+                                                                   ldk, scratch);
+    else
+        key_pack_kernel<int32_t><<<elementwise_grid(n), 256, 0, st>>>((const int32_t *)d, keys,
+                                                                     n, ld, ldk, scratch);
     return hipGetLastError();
 }
 
-hipError_t launch_key_finish(int32_t *d, int32_t *keys, int n, int64_t ld, int64_t ldk,
+hipError_t launch_key_finish(int dtype, void *d, int32_t *keys, int n, int64_t ld, int64_t ldk,
                              int32_t *scratch, hipStream_t st) {
     key_diag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(keys, n, ldk, scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 gu((unsigned)((n + 255) / 256), (unsigned)((n + kMinRows - 1) / kMinRows));
-    key_unpack_kernel<<<gu, 256, 0, st>>>(d, keys, n, ld, ldk, scratch);
+    if (dtype == 0) {
+        key_unpack_kernel<float><<<gu, 256, 0, st>>>((float *)d, keys, n, ld, ldk, scratch);
+        return hipGetLastError();
+    }
+    key_unpack_kernel<int32_t><<<gu, 256, 0, st>>>((int32_t *)d, keys, n, ld, ldk, scratch);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    key_inf_kernel<<<elementwise_grid(n), 256, 0, st>>>(d, n, ld, scratch);
+    key_inf_kernel<<<elementwise_grid(n), 256, 0, st>>>((int32_t *)d, n, ld, scratch);
     return hipGetLastError();
 }
 

@@ -1,8 +1,9 @@
-"""int32 solves with predecessors: the 32-bit keyed sweep and its fallback.
+"""Solves with predecessors: the 32-bit keyed sweep and its fallback.
 
-fw_apsp_pred on int32 first sweeps (distance, last hop) pairs packed into
-32-bit keys and falls back to the 64-bit sweep (queued behind it, gated on a
-device flag) when a distance met during the sweep has |d| >= 2^14 or a
+fw_apsp_pred first sweeps (distance, last hop) pairs packed into 32-bit
+integer keys and falls back to the pair form (64-bit keys for int32, compares
+for fp32; queued behind it, gated on a device flag) when an entry is not an
+integer with |w| < 2^14, a distance met during the sweep has |d| >= 2^14 or a
 diagonal entry ends negative.  Both must give the oracle's d and canonical P
 bit for bit; fw.pred_fallbacks() tells which one ran.
 
@@ -17,7 +18,10 @@ bit for bit; fw.pred_fallbacks() tells which one ran.
   vertices, so keyed and 64-bit results are compared on graphs the oracle's
   canonical reading does not cover (absent and positive diagonal entries);
 * negative cycles fall back; captured solve plans replay both paths;
-  a side stream gets the same bits.
+  a side stream gets the same bits;
+* fp32: integer weights keyed (also n=5000, tile 128), fractional and large
+  weights fall back, unreachable pairs stay +INF, keyed vs compare-form
+  differential, plan replays of both paths.
 """
 import numpy as np
 import pytest
@@ -204,3 +208,105 @@ def test_side_stream_same_bits():
     s = torch.cuda.Stream()
     d, P = _solve(g.w, stream=s)
     assert np.array_equal(d, ref_d) and np.array_equal(P, ref_P)
+
+
+# ---------------------------------------------------------------------------
+# fp32: integer weights with |w| < 2^14 take the same keyed sweep (fp32
+# arithmetic on them is exact); anything else falls back to the fp32 compare
+# form.  Unreachable pairs stay +INF.
+# ---------------------------------------------------------------------------
+def _f32(g_w):
+    w = g_w.astype(np.float32)
+    w[g_w == INF] = np.inf
+    return w
+
+
+@pytest.mark.parametrize("n,tile", [(2000, None), (777, None), (300, 32), (300, 64), (300, 128),
+                                    (5000, None)])
+def test_f32_keyed_path_taken_and_exact(n, tile):
+    g = gen.reweighted_graph(n, 0.2, 1, 1000, -500, 500, seed=300 + n)
+    w = _f32(g.w)
+    print(f"[pred keys] f32 keyed n={n} tile={tile}", flush=True)
+    before = fw.pred_fallbacks()
+    d, P = _solve(w, tile)
+    assert fw.pred_fallbacks() == before
+    ref = oracle.fw(w)
+    assert np.array_equal(d.view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(P, oracle.canonical_pred(ref, w))
+
+
+@pytest.mark.parametrize("what", ["half", "large", "sparse"])
+def test_f32_fallbacks_and_unreachable(what):
+    n = 600
+    if what == "half":     # fractional weights: the compare form (exact: multiples of 1/2)
+        w = gen.dense_graph(n, 0.2, 1, 100, seed=31, dtype=np.float32)
+        w[np.isfinite(w)] += 0.5
+        np.fill_diagonal(w, 0)
+        falls = True
+    elif what == "large":  # integer, but beyond the key range
+        w = gen.dense_graph(n, 0.2, 1, 40000, seed=32, dtype=np.float32)
+        falls = True
+    else:                  # unreachable pairs: +INF, keyed
+        w = gen.dense_graph(n, 0.004, 1, 100, seed=33, dtype=np.float32)
+        falls = False
+    print(f"[pred keys] f32 {what}", flush=True)
+    before = fw.pred_fallbacks()
+    d, P = _solve(w)
+    assert fw.pred_fallbacks() == before + (1 if falls else 0)
+    ref = oracle.fw(w)
+    if what == "sparse":
+        assert np.isinf(ref).any()
+    assert np.array_equal(d.view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(P, oracle.canonical_pred(ref, w))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_f32_keyed_equals_fallback_random(seed):
+    rng = np.random.default_rng(700 + seed)
+    n = int(rng.integers(40, 700))
+    p = float(rng.choice([0.003, 0.03, 0.3]))
+    g = gen.reweighted_graph(n, p, 1, int(rng.integers(2, 100)), -100, 100, seed=50 + seed)
+    w = _f32(g.w)
+    k = rng.choice(n, size=min(n, 6), replace=False)
+    w[k[:3], k[:3]] = np.inf
+    w[k[3:], k[3:]] = rng.integers(1, 50, size=len(k[3:]))
+    # forced fallback: two isolated extra vertices joined by an edge of weight 0.5
+    f = np.full((n + 2, n + 2), np.inf, dtype=np.float32)
+    f[:n, :n] = w
+    f[n, n] = f[n + 1, n + 1] = 0
+    f[n, n + 1] = 0.5
+    print(f"[pred keys] f32 differential seed={seed} n={n} p={p}", flush=True)
+    before = fw.pred_fallbacks()
+    d, P = _solve(w)
+    mid = fw.pred_fallbacks()
+    fd, fP = _solve(f)
+    assert mid == before and fw.pred_fallbacks() == mid + 1
+    assert np.array_equal(d.view(np.uint32), fd[:n, :n].view(np.uint32))
+    assert np.array_equal(P, fP[:n, :n])
+
+
+def test_f32_solve_plan_replays_both_paths():
+    n = 800
+    for frac in (False, True):
+        w = gen.dense_graph(n, 0.2, 1, 100, seed=61, dtype=np.float32)
+        if frac:
+            w[np.isfinite(w)] += 0.25
+            np.fill_diagonal(w, 0)
+        print(f"[pred keys] f32 solve plan frac={frac}", flush=True)
+        ref_d, ref_P = _solve(w)
+        src = torch.from_numpy(w).cuda()
+        d = src.clone()
+        P = torch.empty((n, n), dtype=torch.int32, device="cuda")
+        plan = fw.SolvePlan(d, P)
+        try:
+            for rep in range(3):
+                d.copy_(src)
+                P.fill_(-77)
+                before = fw.pred_fallbacks()
+                plan.launch("graph")
+                torch.cuda.synchronize()
+                assert fw.pred_fallbacks() == before + (1 if frac else 0), rep
+                assert np.array_equal(d.cpu().numpy().view(np.uint32), ref_d.view(np.uint32)), rep
+                assert np.array_equal(P.cpu().numpy(), ref_P), rep
+        finally:
+            plan.destroy()
