@@ -175,8 +175,11 @@ void oracle_reach_row(const void *W, int dtype, int64_t n, int64_t ld,
  *   P[r][j] = -1 when j is not reachable from i over the edges of W;
  *   otherwise P[r][j] = min { p : p != j, (p, j) is an edge of W,
  *                                 p reachable from i,
- *                                 D[i][p] + W[p][j] == D[i][j] },
- * the smallest last hop over all shortest i -> j paths.  The sum is taken in
+ *                                 d(i, p) + W[p][j] == D[i][j] },
+ * the smallest last hop over all shortest i -> j paths, where d(i, p) is the
+ * weight of the best i -> p prefix: D[i][p] for p != i, and 0 for p = i (the
+ * empty path -- a path from i does not pass through the diagonal entry, which
+ * holds the best cycle through i, or a non-zero w_ii).  The sum is taken in
  * the matrix's own precision (fp32 round-to-nearest, or exact int64 for
  * int32), and -1 is written if no p qualifies (which cannot happen for exact
  * shortest-path distances).
@@ -280,28 +283,36 @@ void oracle_canonical_pred_rows(const void *D, int64_t ldd, const void *W,
 #pragma omp parallel num_threads(nt)
     {
         uint8_t *reach = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+        void *drow = malloc((size_t)(n > 0 ? n : 1) * 4);  /* d(i, .) of the row */
         uint64_t *seen = (uint64_t *)malloc((size_t)(nw > 0 ? nw : 1) * sizeof(uint64_t));
         int64_t *queue = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
 #pragma omp for schedule(dynamic, 1)
         for (int64_t r = 0; r < nrows; ++r) {
             const int64_t i = rows[r];
             reach_masks(adj, nw, n, i, seen, queue, reach);
+            memcpy(drow, (const char *)D + (size_t)(r * ldd) * 4, (size_t)n * 4);
+            if (dtype == 0)
+                ((float *)drow)[i] = 0.0f;
+            else
+                ((int32_t *)drow)[i] = 0;
             int32_t *Pr = P + r * ldp;
             for (int64_t j = 0; j < n; ++j) {
                 int64_t p = -1;
                 if (j != i && reach[j]) {
                     if (dtype == 0) {
                         const float *Dr = (const float *)D + r * ldd;
-                        p = first_hit_f32(Dr, (const float *)wt + j * n, reach, n, Dr[j]);
+                        p = first_hit_f32((const float *)drow, (const float *)wt + j * n, reach,
+                                          n, Dr[j]);
                     } else {
                         const int32_t *Dr = (const int32_t *)D + r * ldd;
-                        p = first_hit_i32(Dr, (const int32_t *)wt + j * n, reach, n,
-                                          (int64_t)Dr[j]);
+                        p = first_hit_i32((const int32_t *)drow, (const int32_t *)wt + j * n,
+                                          reach, n, (int64_t)Dr[j]);
                     }
                 }
                 Pr[j] = (int32_t)p;
             }
         }
+        free(drow);
         free(queue);
         free(seen);
         free(reach);

@@ -297,6 +297,23 @@ def test_canonical_pred_matches_brute_force(seed):
     assert P.tolist() == last
 
 
+@pytest.mark.parametrize("seed", range(24))
+def test_canonical_pred_brute_force_nonzero_diagonal(seed):
+    """A path from i starts with the empty path: the diagonal entry (a
+    positive w_ii, an absent one, or the best cycle through i that the sweep
+    leaves there) is never a prefix of an i -> j path."""
+    rng = np.random.default_rng(3500 + seed)
+    n = int(rng.integers(2, 8))
+    dtype = np.float32 if seed % 2 else np.int32
+    W = random_tiny(n, float(rng.uniform(0.2, 0.9)), 1, 3, rng, dtype=dtype)
+    inf = np.float32(np.inf) if dtype == np.float32 else np.int32(oracle.I32_INF)
+    for i in rng.choice(n, size=max(1, n // 2), replace=False):
+        W[i, i] = inf if rng.random() < 0.5 else dtype(rng.integers(1, 4))
+    P = oracle.canonical_pred(oracle.fw(W), W)
+    _, last = brute_force(W)
+    assert P.tolist() == last
+
+
 def test_canonical_pred_closed_forms():
     n = 23
     W = np.full((n, n), np.inf, np.float32)
