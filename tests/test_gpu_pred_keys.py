@@ -148,6 +148,7 @@ def _differential(w):
     assert mid == before                   # the graph itself stays keyed
     assert np.array_equal(d, fd[:n, :n])
     assert np.array_equal(P, fP[:n, :n])
+    _check_oracle(w, d, P)
 
 
 @pytest.mark.parametrize("seed", range(8))
@@ -283,6 +284,9 @@ def test_f32_keyed_equals_fallback_random(seed):
     assert mid == before and fw.pred_fallbacks() == mid + 1
     assert np.array_equal(d.view(np.uint32), fd[:n, :n].view(np.uint32))
     assert np.array_equal(P, fP[:n, :n])
+    ref = oracle.fw(w)
+    assert np.array_equal(d.view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(P, oracle.canonical_pred(ref, w))
 
 
 def test_f32_solve_plan_replays_both_paths():
