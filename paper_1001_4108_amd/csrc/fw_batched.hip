@@ -164,7 +164,7 @@ batched_kernel(BatchHeader *hdr, const BatchItem *items) {
 // built on the host when the plan is created.
 // ---------------------------------------------------------------------------
 enum StagedKind { kStagedDiag = 0, kStagedPanel = 1, kStagedBulk = 2, kStagedPredInit = 3,
-                  kStagedPredFix = 4 };
+                  kStagedPredFix = 4, kStagedBulkDma = 5, kStagedPanelDma = 6 };
 
 struct StagedWork {
     int32_t item;   // index into the plan's item array
@@ -317,9 +317,222 @@ staged_diag_kernel(const BatchItem *items, const StagedWork *work, int b) {
         closure_tile<T, S, staged_diag_tm<S>(), false>(d, nullptr, it.n, it.ld, 0, b * S, smem);
 }
 
+// ---------------------------------------------------------------------------
+// Bulk tiles of tile-128 graphs without predecessors whose rows are 16-byte
+// aligned, edge tiles included: the single-graph bulk's 128 x 128 tile with
+// 16-deep k-slices copied global->LDS directly (the same LDS layout, thread
+// geometry and candidates as bulk_tile_dma), generalised to tiles that reach
+// past the graph's last row, column or k.  Every copy source is clamped into
+// the graph -- rows and k-rows to n-1, 16-byte chunks to the one holding
+// column n-1, which lies inside the row's ld -- so the clamps are identities
+// inside the matrix and each copy reads the graph's own rows.  The k loop
+// stops at the last valid k (a single step when an odd count remains); C
+// cells outside the graph are neither loaded nor stored, so rows and columns
+// beyond n compute values from clamped operands that are never stored, and
+// every valid cell gets exactly the candidates of the full form.  With
+// `close` (the tile is (b+1, b+1)) the tile's closure for stage b+1 follows.
+// Element offsets from the graph's base are 32-bit (n * ld < 2^31).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void staged_tile_dma(T *__restrict__ d, int n, int64_t ld, int bi,
+                                                int bj, int b, bool close) {
+    constexpr int S = 128, BK = 16, TM = 8, NS = S / BK;
+    __shared__ __align__(16) T A0[S * BK];
+    __shared__ __align__(16) T A1[S * BK];
+    __shared__ __align__(16) T B0[BK * S];
+    __shared__ __align__(16) T B1[BK * S];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tx = tid & 15, ty = tid >> 4;
+    const int row0 = bi * S, col0 = bj * S, k0 = b * S;
+    const bool inside = row0 + S <= n && col0 + S <= n && k0 + S <= n;  // uniform
+
+    // thread (tx, ty): rows 8*ty .. 8*ty + 7, column groups 4*tx and 64 + 4*tx
+    T acc[TM][TM];
+    if (inside) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const T *row = d + (int64_t)(row0 + ty * TM + i) * ld + col0 + tx * 4;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const typename Vec4<T>::type x =
+                    *reinterpret_cast<const typename Vec4<T>::type *>(row + h * 64);
+                acc[i][4 * h] = x[0];
+                acc[i][4 * h + 1] = x[1];
+                acc[i][4 * h + 2] = x[2];
+                acc[i][4 * h + 3] = x[3];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int gi = row0 + ty * TM + i;
+#pragma unroll
+            for (int e = 0; e < TM; ++e) {
+                const int gj = col0 + tx * 4 + (e >> 2) * 64 + (e & 3);
+                acc[i][e] = (gi < n && gj < n) ? d[(int64_t)gi * ld + gj] : Ar<T>::inf();
+            }
+        }
+    }
+
+    // copy sources: the wave copies A rows 32*wave + lane/4 (and +16), its
+    // 16-byte chunk c at LDS position c ^ ((row / 8) % 4), and B k-rows
+    // 4*wave + lane/32 (and +2), 16-byte chunk lane % 32
+    const int last = n - 1, cap = (n + 3) / 4 * 4 - 4;
+    const uint32_t ldu = (uint32_t)ld;
+    const int ar = wave * 32 + (lane >> 2);
+    const uint32_t a_row0 = (uint32_t)min(row0 + ar, last) * ldu;
+    const uint32_t a_row1 = (uint32_t)min(row0 + ar + 16, last) * ldu;
+    const int a_c0 = ((lane & 3) ^ ((ar >> 3) & 3)) << 2;
+    const int a_c1 = ((lane & 3) ^ (((ar + 16) >> 3) & 3)) << 2;
+    const uint32_t b_col = (uint32_t)min(col0 + ((lane & 31) << 2), cap);
+    const int b_r = wave * 4 + (lane >> 5);
+    auto issue = [&](int s, T *Ad, T *Bd) {
+        const int kc = k0 + s * BK;
+        T *a = Ad + wave * 32 * BK;
+        T *bb = Bd + wave * 4 * S;
+        __builtin_amdgcn_global_load_lds(d + (a_row0 + (uint32_t)min(kc + a_c0, cap)),
+                                         (lds_void_t *)a, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(d + (a_row1 + (uint32_t)min(kc + a_c1, cap)),
+                                         (lds_void_t *)(a + 16 * BK), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(d + ((uint32_t)min(kc + b_r, last) * ldu + b_col),
+                                         (lds_void_t *)bb, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(d + ((uint32_t)min(kc + b_r + 2, last) * ldu + b_col),
+                                         (lds_void_t *)(bb + 2 * S), 16, 0, 0);
+    };
+    // a wave whose 32 rows all lie beyond the graph skips the arithmetic (it
+    // still copies its share of every slice and meets every barrier)
+    const bool idle = row0 + wave * 32 >= n;
+    // kl: the slice's valid k count
+    auto compute = [&](const T *Ab, const T *Bb, int kl) {
+        if (idle) return;
+#pragma unroll 1
+        for (int kk = 0; kk < (kl & ~1); kk += 2) {
+            const int aoff = ty * (TM * BK) + (((kk >> 2) ^ (ty & 3)) << 2) + (kk & 3);
+            T a0[TM], a1[TM], b0[TM], b1[TM];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const typename Pair<T>::type v =
+                    *reinterpret_cast<const typename Pair<T>::type *>(Ab + aoff + i * BK);
+                a0[i] = v.x;
+                a1[i] = v.y;
+            }
+#pragma unroll
+            for (int j = 0; j < TM; ++j) {
+                const int c = (j >> 2) * 64 + tx * 4 + (j & 3);
+                b0[j] = Bb[kk * S + c];
+                b1[j] = Bb[(kk + 1) * S + c];
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TM; ++j)
+                    acc[i][j] = Ar<T>::min3(acc[i][j], Ar<T>::add(a0[i], b0[j]),
+                                            Ar<T>::add(a1[i], b1[j]));
+        }
+        if (kl & 1) {  // the last valid k alone
+            const int kk = kl - 1;
+            const int aoff = ty * (TM * BK) + (((kk >> 2) ^ (ty & 3)) << 2) + (kk & 3);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TM; ++j) {
+                    const T c =
+                        Ar<T>::add(Ab[aoff + i * BK], Bb[kk * S + (j >> 2) * 64 + tx * 4 + (j & 3)]);
+                    acc[i][j] = Ar<T>::min3(acc[i][j], c, c);
+                }
+        }
+    };
+    auto slice_k = [&](int s) { return max(0, min(BK, n - (k0 + s * BK))); };
+
+    // as bulk_tile_dma: vmcnt(0) and a barrier before each slice is read and
+    // before its buffer is refilled
+    constexpr int kWaitVm0 = 0x0F70;
+    issue(0, A0, B0);
+#pragma unroll 1
+    for (int s = 0; s < NS; s += 2) {
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        __syncthreads();
+        issue(s + 1, A1, B1);
+        compute(A0, B0, slice_k(s));
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        __syncthreads();
+        if (s + 2 < NS) issue(s + 2, A0, B0);
+        compute(A1, B1, slice_k(s + 1));
+    }
+
+    if (inside) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            T *row = d + (int64_t)(row0 + ty * TM + i) * ld + col0 + tx * 4;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                typename Vec4<T>::type x;
+                x[0] = acc[i][4 * h];
+                x[1] = acc[i][4 * h + 1];
+                x[2] = acc[i][4 * h + 2];
+                x[3] = acc[i][4 * h + 3];
+                *reinterpret_cast<typename Vec4<T>::type *>(row + h * 64) = x;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int gi = row0 + ty * TM + i;
+#pragma unroll
+            for (int e = 0; e < TM; ++e) {
+                const int gj = col0 + tx * 4 + (e >> 2) * 64 + (e & 3);
+                if (gi < n && gj < n) d[(int64_t)gi * ld + gj] = acc[i][e];
+            }
+        }
+    }
+    if (close) {
+        // the next stage's diagonal tile, reread by the same workgroup after
+        // the barrier and closed in place in the product's free LDS
+        __syncthreads();
+        if (row0 + S <= n)
+            closure_tile<T, S, TM, false, Ar<T>, true>(d, nullptr, n, ld, 0, row0,
+                                                       reinterpret_cast<char *>(A0));
+        else
+            closure_tile<T, S, TM, false, Ar<T>, false>(d, nullptr, n, ld, 0, row0,
+                                                        reinterpret_cast<char *>(A0));
+    }
+}
+
+// Panel or bulk launch of stage b for tile-128 graphs whose rows are 16-byte
+// aligned (staged_tile_dma).  A panel tile is the same product with the
+// closed diagonal tile as one operand and the tile itself as the other (row
+// panel (b, j): D(b,b) x D(b,j); column panel (i, b): D(i,b) x D(b,b)), its
+// operand slices copied before its cells are stored.  In a bulk launch the
+// closing entries -- tile (b+1, b+1) of each graph with a next stage -- are
+// listed first.
+#ifndef FW_STAGED_DMA_WAVES
+#define FW_STAGED_DMA_WAVES 4
+#endif
+template <typename T>
+__global__ void __launch_bounds__(256, FW_STAGED_DMA_WAVES)
+staged_dma_kernel(const BatchItem *__restrict__ items, const StagedWork *__restrict__ work,
+                  int kind, int b) {
+    const StagedWork w = work[blockIdx.x];
+    const BatchItem &it = items[w.item];
+    const int m = (it.n + 127) / 128 - 1;
+    int bi, bj;
+    if (kind == kStagedPanelDma)
+        panel_coords(w.local & ~kStagedClose, b, m, bi, bj);
+    else
+        bulk_coords(w.local & ~kStagedClose, b, m, bi, bj);
+    staged_tile_dma<T>(as_global(static_cast<T *>(it.d)), it.n, it.ld, bi, bj, b,
+                       (w.local & kStagedClose) != 0);
+}
+
 template <typename T, bool PRED>
 hipError_t launch_staged_t(int tile, const BatchItem *items, const StagedWork *work, int kind,
                            int b, unsigned grid, hipStream_t st) {
+    if (kind == kStagedBulkDma || kind == kStagedPanelDma) {
+        if (PRED || tile != 128) return hipErrorInvalidValue;
+        staged_dma_kernel<T><<<grid, 256, 0, st>>>(items, work, kind, b);
+        return hipGetLastError();
+    }
     if (kind == kStagedDiag) {
         switch (tile) {
         case 32: staged_diag_kernel<T, 32, PRED><<<grid, 256, 0, st>>>(items, work, b); break;
@@ -500,6 +713,9 @@ namespace {
 // with the fewest entries so far, largest first; each group keeps the
 // launch's order (closing entries first), and the groups are interleaved
 // until the shortest runs out, the rest then following in turn.
+#ifndef FW_STAGED_DMA
+#define FW_STAGED_DMA 1
+#endif
 #ifndef FW_STAGED_XCD_GROUPS
 #define FW_STAGED_XCD_GROUPS 8
 #endif
@@ -609,7 +825,15 @@ int build_host_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t
         add_launch(kStagedPredInit, tile, 0, first);
         const int nb_max = blocks(gs.front());
         // the bulk launch of stage b closes each graph's tile (b+1, b+1)
-        const bool fuse = tile <= 64 || (tile == 128 && any_pred);
+        // tile 128 without predecessors: the bulk runs bulk_tile_dma (rows
+        // 16-byte aligned in every graph of the group), which closes the
+        // next diagonal tile as the smaller tiles' kernels do
+        bool dma = tile == 128 && !any_pred && FW_STAGED_DMA;
+        for (int32_t g : gs) {
+            const BatchItem &it = items[(size_t)g];
+            dma = dma && it.vec && (int64_t)it.n * it.ld < (int64_t(1) << 31);
+        }
+        const bool fuse = tile <= 64 || (tile == 128 && (any_pred || dma));
         for (int b = 0; b < nb_max; ++b) {
             first = (int64_t)work.size();
             for (int32_t g : gs)
@@ -621,7 +845,7 @@ int build_host_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t
                 if (blocks(g) > b)
                     for (int t = 0; t < 2 * m; ++t) work.push_back({g, t});
             }
-            add_launch(kStagedPanel, tile, b, first);
+            add_launch(dma ? kStagedPanelDma : kStagedPanel, tile, b, first);
             first = (int64_t)work.size();
             if (fuse)  // the closing workgroups first: they run longest
                 for (int32_t g : gs)
@@ -636,7 +860,7 @@ int build_host_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t
                         if (!(fuse && blocks(g) > b + 1 && t == b * m + b))
                             work.push_back({g, t});
             }
-            add_launch(kStagedBulk, tile, b, first);
+            add_launch(dma ? kStagedBulkDma : kStagedBulk, tile, b, first);
         }
         first = (int64_t)work.size();
         for (int32_t g : gs)

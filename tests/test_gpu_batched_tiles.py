@@ -1,6 +1,8 @@
-"""Stage-batched tile-64 graphs without predecessors, many per launch: 24
-graphs of 512 vertices (every tile full) beside ragged sizes (partial last
-blocks), rows padded or not, both dtypes.  Each graph is checked bit for bit
+"""Stage-batched graphs without predecessors at tiles 64 and 128, many per
+launch: 24 graphs of 512 vertices (every tile inside the graph) beside ragged
+sizes (partial last blocks, so edge tiles, partial k-blocks and edge
+closures), rows padded or not (16-byte aligned, so the 128-wide bulk runs on
+direct global->LDS copies), both dtypes.  Each graph is checked bit for bit
 against the oracle in an eager launch and two graph replays (with unrelated
 eager work between), the padding between rows is checked untouched, and the
 batch is checked against single-graph solves."""
@@ -16,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 # multiples of 64 (all tiles full), ragged edges (partial last block), and
 # leading dimensions padded to 16 bytes
-SIZES = [512] * 24 + [448, 500, 384, 257, 320, 190, 129, 640, 700, 1000]
+SIZES = [512] * 24 + [448, 500, 384, 257, 320, 190, 129, 640, 700, 1000, 301, 130]
 
 
 def bits(a):
@@ -29,11 +31,11 @@ def graph(n, dtype, seed):
     return gen.reweighted_graph(n, 0.3, 1, 60, -25, 25, seed).w
 
 
-@pytest.fixture(autouse=True)
-def tile64():
+@pytest.fixture(params=[64, 128], autouse=True)
+def tile(request):
     for dt in ("f32", "i32"):
-        fw.plan_set(dt, 33, 4096, 64)
-    yield
+        fw.plan_set(dt, 33, 4096, request.param)
+    yield request.param
     fw.plan_reset()
 
 
@@ -52,7 +54,7 @@ def pack(graphs, dtype, pad):
 
 @pytest.mark.parametrize("dtype", [np.float32, np.int32])
 @pytest.mark.parametrize("pad", [0, 4])
-def test_tile64_batch_matches_oracle(dtype, pad):
+def test_batch_matches_oracle(dtype, pad):
     graphs = [graph(n, dtype, 500 + g) for g, n in enumerate(SIZES)]
     refs = [oracle.fw(w) for w in graphs]
     pool, views = pack(graphs, dtype, pad)
@@ -80,7 +82,7 @@ def test_tile64_batch_matches_oracle(dtype, pad):
         plan.destroy()
 
 
-def test_tile64_batch_matches_single_solves():
+def test_batch_matches_single_solves():
     graphs = [graph(n, np.float32, 700 + g) for g, n in enumerate(SIZES[20:])]
     pool, views = pack(graphs, np.float32, 0)
     singles = [torch.from_numpy(w).cuda() for w in graphs]
