@@ -564,8 +564,13 @@ def bench_batched(torch, fw, gen, dev, reps, modes=("graph", "kernel", "per_grap
     # tile per size bucket, picked by the library's autotuner for the batched
     # launch (installed into the plan table the batch plan reads)
     buckets = [(16, 32), (33, 64), (65, 128), (129, 256), (257, 512)]
+    counts = {(lo, hi): int(((sizes >= lo) & (sizes <= hi)).sum()) for lo, hi in buckets}
     if tiles is None:
-        tuned = fw.autotune(torch.float32, buckets, objective="batched", batch=256, reps=3)
+        # each bucket tuned on as many graphs as this batch holds in it
+        tuned = {}
+        for lo, hi in buckets:
+            tuned.update(fw.autotune(torch.float32, [(lo, hi)], objective="batched",
+                                     batch=max(counts[(lo, hi)], 16), reps=3))
     else:  # given tiles (profiling runs: counters distort the autotuner's timings)
         tuned = {}
         for (lo, hi), t in zip(buckets, tiles):
@@ -577,7 +582,7 @@ def bench_batched(torch, fw, gen, dev, reps, modes=("graph", "kernel", "per_grap
     out = {"workload": "ragged batch of 4096 fp32 graphs, n log-uniform in [16,512], edge "
                        "prob 0.4, integer weights [1,100]",
            "graphs": len(graphs), "updates": float((sizes ** 3).sum()), "grid": plan.grid,
-           "autotuned_tiles": {f"{lo}-{hi}": {"tile": v["tile"],
+           "autotuned_tiles": {f"{lo}-{hi}": {"tile": v["tile"], "graphs": counts[(lo, hi)],
                                               "ms_by_tile": {str(t): round(m, 4)
                                                              for t, m in v["ms"].items()}}
                                for (lo, hi), v in tuned.items()}}

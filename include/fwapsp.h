@@ -239,10 +239,11 @@ int fw_apsp_ladder(void *d, int dtype, int64_t n, int64_t ld, int rung, void *st
  * fw_autotune -- the plan table's autotuner (dtype: a plan key; with
  * FW_PLAN_PRED the timed solves compute predecessors).  For each size bucket
  * [lo[k], hi[k]] (2 <= lo <= hi <= 65536) it times every tile of
- * fw_plan_tiles() at the bucket's geometric-middle size n and installs the
- * fastest with fw_plan_set.  objective 0 times one single-graph solve,
- * objective 1 one eager launch of a batch plan of `batch` graphs of size n
- * (persistent or stage-batched, as batch plans run that size; plans read the
+ * fw_plan_tiles() and installs the fastest with fw_plan_set.  objective 0
+ * times one single-graph solve of the bucket's geometric-middle size,
+ * objective 1 one eager launch of a batch plan of `batch` graphs whose sizes
+ * spread log-uniformly over the bucket (graph g at quantile (g + 1/2) / batch;
+ * persistent or stage-batched, as batch plans run those sizes; plans read the
  * same table).  While a candidate is timed it is installed for its bucket, so
  * concurrent solves may see it.  Each (bucket, tile) is run reps + 1
  * times, the first as a warm-up, and scored by the median.  Writes the chosen

@@ -7,10 +7,12 @@
 // the solves compute predecessors too and the table of such solves is tuned.
 // Two objectives:
 //   0  one single-graph solve of the bucket's representative size;
-//   1  one batch-plan launch of `batch` graphs of that size (persistent or
-//      stage-batched, whichever the plan uses for that size; batch plans read
-//      the same table).
-// The representative size is the geometric middle of the bucket.
+//   1  one batch-plan launch of `batch` graphs whose sizes spread
+//      log-uniformly over the bucket (persistent or stage-batched, whichever
+//      the plan uses for those sizes; batch plans read the same table): in a
+//      ragged batch a bucket's graphs span it, and a tile's padding of the
+//      last block and its stage count vary across the bucket.
+// The single solve takes the geometric middle of the bucket.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -70,20 +72,32 @@ extern "C" int fw_autotune(int dtype, const int64_t *lo, const int64_t *hi, int 
         const int n = (int)std::llround(std::sqrt((double)lo[k] * (double)hi[k]));
         const int64_t ld = (n + 3) / 4 * 4;
         const int count = objective == 1 ? batch : 1;
-        const size_t per = (size_t)n * (size_t)ld * 4;
-        const size_t total = per * (size_t)count * (pred ? 2 : 1);  // distances [, predecessors]
+        // graph sizes: the middle for a single solve, else log-uniform over
+        // the bucket (graph g at quantile (g + 1/2) / count)
+        std::vector<int64_t> ns((size_t)count, n), lds((size_t)count, ld);
+        std::vector<size_t> offs((size_t)count + 1, 0);
+        for (int g = 0; g < count; ++g) {
+            if (objective == 1) {
+                const double q = (g + 0.5) / count;
+                ns[(size_t)g] = std::min<int64_t>(
+                    hi[k], std::max<int64_t>(lo[k], std::llround(lo[k] * std::pow((double)hi[k] / lo[k], q))));
+                lds[(size_t)g] = (ns[(size_t)g] + 3) / 4 * 4;
+            }
+            offs[(size_t)g + 1] = offs[(size_t)g] + (size_t)ns[(size_t)g] * (size_t)lds[(size_t)g] * 4;
+        }
+        const size_t per_set = offs[(size_t)count];
+        const size_t total = per_set * (pred ? 2 : 1);  // distances [, predecessors]
         if (sc.mat) hipFree(sc.mat);
         sc.mat = nullptr;
         if ((e = hipMalloc(&sc.mat, total)) != hipSuccess) return status_of(e);
         if ((e = hipMemsetAsync(sc.mat, 0, total, sc.st)) != hipSuccess) return status_of(e);
         std::vector<void *> ptrs((size_t)count);
         std::vector<int32_t *> preds((size_t)count, nullptr);
-        std::vector<int64_t> ns((size_t)count, n), lds((size_t)count, ld);
         for (int g = 0; g < count; ++g) {
-            ptrs[(size_t)g] = static_cast<char *>(sc.mat) + per * (size_t)g;
+            ptrs[(size_t)g] = static_cast<char *>(sc.mat) + offs[(size_t)g];
             if (pred)
                 preds[(size_t)g] = reinterpret_cast<int32_t *>(static_cast<char *>(sc.mat) +
-                                                               per * (size_t)(count + g));
+                                                               per_set + offs[(size_t)g]);
         }
         double best = 1e300;
         int best_tile = tiles[0];
