@@ -417,11 +417,19 @@ __device__ __forceinline__ void staged_tile_dma(T *__restrict__ d, int n, int64_
                 a0[i] = v.x;
                 a1[i] = v.y;
             }
+            // B: the thread's two 4-column groups of rows kk and kk+1, as
+            // 16-byte reads
 #pragma unroll
-            for (int j = 0; j < TM; ++j) {
-                const int c = (j >> 2) * 64 + tx * 4 + (j & 3);
-                b0[j] = Bb[kk * S + c];
-                b1[j] = Bb[(kk + 1) * S + c];
+            for (int h = 0; h < 2; ++h) {
+                const typename Vec4<T>::type u0 =
+                    *reinterpret_cast<const typename Vec4<T>::type *>(Bb + kk * S + h * 64 + tx * 4);
+                const typename Vec4<T>::type u1 = *reinterpret_cast<const typename Vec4<T>::type *>(
+                    Bb + (kk + 1) * S + h * 64 + tx * 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    b0[4 * h + e] = u0[e];
+                    b1[4 * h + e] = u1[e];
+                }
             }
 #pragma unroll
             for (int i = 0; i < TM; ++i)
