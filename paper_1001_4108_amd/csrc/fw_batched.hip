@@ -329,13 +329,12 @@ staged_diag_kernel(const BatchItem *items, const StagedWork *work, int b) {
 // stops at the last valid k (a single step when an odd count remains); C
 // cells outside the graph are neither loaded nor stored, so rows and columns
 // beyond n compute values from clamped operands that are never stored, and
-// every valid cell gets exactly the candidates of the full form.  With
-// `close` (the tile is (b+1, b+1)) the tile's closure for stage b+1 follows.
-// Element offsets from the graph's base are 32-bit (n * ld < 2^31).
+// every valid cell gets exactly the candidates of the full form.  Element
+// offsets from the graph's base are 32-bit (n * ld < 2^31).
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void staged_tile_dma(T *__restrict__ d, int n, int64_t ld, int bi,
-                                                int bj, int b, bool close) {
+                                                int bj, int b) {
     constexpr int S = 128, BK = 16, TM = 8, NS = S / BK;
     __shared__ __align__(16) T A0[S * BK];
     __shared__ __align__(16) T A1[S * BK];
@@ -494,26 +493,13 @@ __device__ __forceinline__ void staged_tile_dma(T *__restrict__ d, int n, int64_
             }
         }
     }
-    if (close) {
-        // the next stage's diagonal tile, reread by the same workgroup after
-        // the barrier and closed in place in the product's free LDS
-        __syncthreads();
-        if (row0 + S <= n)
-            closure_tile<T, S, TM, false, Ar<T>, true>(d, nullptr, n, ld, 0, row0,
-                                                       reinterpret_cast<char *>(A0));
-        else
-            closure_tile<T, S, TM, false, Ar<T>, false>(d, nullptr, n, ld, 0, row0,
-                                                        reinterpret_cast<char *>(A0));
-    }
 }
 
 // Panel or bulk launch of stage b for tile-128 graphs whose rows are 16-byte
 // aligned (staged_tile_dma).  A panel tile is the same product with the
 // closed diagonal tile as one operand and the tile itself as the other (row
 // panel (b, j): D(b,b) x D(b,j); column panel (i, b): D(i,b) x D(b,b)), its
-// operand slices copied before its cells are stored.  In a bulk launch the
-// closing entries -- tile (b+1, b+1) of each graph with a next stage -- are
-// listed first.
+// operand slices copied before its cells are stored.
 #ifndef FW_STAGED_DMA_WAVES
 #define FW_STAGED_DMA_WAVES 4
 #endif
@@ -526,11 +512,10 @@ staged_dma_kernel(const BatchItem *__restrict__ items, const StagedWork *__restr
     const int m = (it.n + 127) / 128 - 1;
     int bi, bj;
     if (kind == kStagedPanelDma)
-        panel_coords(w.local & ~kStagedClose, b, m, bi, bj);
+        panel_coords(w.local, b, m, bi, bj);
     else
-        bulk_coords(w.local & ~kStagedClose, b, m, bi, bj);
-    staged_tile_dma<T>(as_global(static_cast<T *>(it.d)), it.n, it.ld, bi, bj, b,
-                       (w.local & kStagedClose) != 0);
+        bulk_coords(w.local, b, m, bi, bj);
+    staged_tile_dma<T>(as_global(static_cast<T *>(it.d)), it.n, it.ld, bi, bj, b);
 }
 
 template <typename T, bool PRED>
@@ -833,15 +818,16 @@ int build_host_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t
         add_launch(kStagedPredInit, tile, 0, first);
         const int nb_max = blocks(gs.front());
         // the bulk launch of stage b closes each graph's tile (b+1, b+1)
-        // tile 128 without predecessors: the bulk runs bulk_tile_dma (rows
-        // 16-byte aligned in every graph of the group), which closes the
-        // next diagonal tile as the smaller tiles' kernels do
+        // tile 128 without predecessors: panels and bulk run staged_tile_dma
+        // (rows 16-byte aligned in every graph of the group); each stage
+        // keeps its diagonal launch, whose 1024-thread workgroups close a
+        // tile sooner than a 256-thread bulk workgroup would after its product
         bool dma = tile == 128 && !any_pred && FW_STAGED_DMA;
         for (int32_t g : gs) {
             const BatchItem &it = items[(size_t)g];
             dma = dma && it.vec && (int64_t)it.n * it.ld < (int64_t(1) << 31);
         }
-        const bool fuse = tile <= 64 || (tile == 128 && (any_pred || dma));
+        const bool fuse = tile <= 64 || (tile == 128 && any_pred);
         for (int b = 0; b < nb_max; ++b) {
             first = (int64_t)work.size();
             for (int32_t g : gs)
