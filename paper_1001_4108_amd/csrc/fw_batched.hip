@@ -671,6 +671,10 @@ using namespace fw;
 struct StagedLaunch {
     int kind, tile, b;
     int64_t offset, count;  // slice of the work table
+    // launches of one group depend on each other in plan order; different
+    // groups on nothing in each other: the tile size, or minus it for the
+    // one-launch closures of a tile group's single-block graphs
+    int group;
 };
 
 struct fw_batch_plan_s {
@@ -708,6 +712,12 @@ namespace {
 // until the shortest runs out, the rest then following in turn.
 #ifndef FW_STAGED_DMA
 #define FW_STAGED_DMA 1
+#endif
+#ifndef FW_STAGED_SINGLE_APART
+#define FW_STAGED_SINGLE_APART 1
+#endif
+#ifndef FW_PLAN_MAIN_FIRST
+#define FW_PLAN_MAIN_FIRST 1
 #endif
 #ifndef FW_STAGED_XCD_GROUPS
 #define FW_STAGED_XCD_GROUPS 8
@@ -802,10 +812,11 @@ int build_host_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t
     std::vector<StagedWork> &work = hp.work;
     std::map<int, std::vector<int32_t>> groups;
     for (int64_t g = 0; g < n_staged; ++g) groups[items[(size_t)g].tile].push_back((int32_t)g);
-    auto add_launch = [&](int kind, int tile, int b, int64_t first) {
+    auto add_launch = [&](int kind, int tile, int b, int64_t first, int group = 0) {
         if ((int64_t)work.size() > first) {
             if (FW_STAGED_XCD_GROUPS > 1) xcd_group(work, first, FW_STAGED_XCD_GROUPS);
-            hp.staged.push_back({kind, tile, b, first, (int64_t)work.size() - first});
+            hp.staged.push_back(
+                {kind, tile, b, first, (int64_t)work.size() - first, group ? group : tile});
         }
     };
     for (auto &kv : groups) {
@@ -830,9 +841,20 @@ int build_host_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t
         const bool fuse = tile <= 64 || (tile == 128 && any_pred);
         for (int b = 0; b < nb_max; ++b) {
             first = (int64_t)work.size();
+            // without predecessors (no set-up / fix-up launches around them),
+            // the single-block graphs' closures -- their whole solve -- form a
+            // launch of their own, off the stage chain
+            const bool single_apart = !any_pred && FW_STAGED_SINGLE_APART;
             for (int32_t g : gs)
-                if (blocks(g) > b && !(fuse && b > 0)) work.push_back({g, 0});
+                if (blocks(g) > (single_apart ? std::max(b, 1) : b) && !(fuse && b > 0))
+                    work.push_back({g, 0});
             add_launch(kStagedDiag, tile, b, first);
+            if (single_apart && b == 0) {
+                first = (int64_t)work.size();
+                for (int32_t g : gs)
+                    if (blocks(g) == 1) work.push_back({g, 0});
+                add_launch(kStagedDiag, tile, 0, first, -tile);
+            }
             first = (int64_t)work.size();
             for (int32_t g : gs) {
                 const int m = blocks(g) - 1;
@@ -892,11 +914,11 @@ int build_plan(void *const *d, const int64_t *n, const int64_t *ld, int64_t coun
     return status_of(e);
 }
 
-// The tile group whose stage-batched launch sequence is longest (the plan's
-// critical path), or 0 when the plan has no stage-batched part.
-int main_tile(const fw_batch_plan_s *pl) {
+// The launch group whose sequence is longest (the plan's critical path), or
+// 0 when the plan has no stage-batched part.
+int main_group(const fw_batch_plan_s *pl) {
     std::map<int, int> launches;
-    for (const StagedLaunch &l : pl->staged) ++launches[l.tile];
+    for (const StagedLaunch &l : pl->staged) ++launches[l.group];
     int best = 0, most = 0;
     for (auto &kv : launches)
         if (kv.second > most) best = kv.first, most = kv.second;
@@ -906,9 +928,9 @@ int main_tile(const fw_batch_plan_s *pl) {
 // True when the plan has launch sequences that depend on nothing in each
 // other: several tile groups, or stage-batched and persistent parts.
 bool has_independent_parts(const fw_batch_plan_s *pl) {
-    const int main = main_tile(pl);
+    const int main = main_group(pl);
     for (const StagedLaunch &l : pl->staged)
-        if (l.tile != main) return true;
+        if (l.group != main) return true;
     return main != 0 && pl->count > pl->n_staged;
 }
 
@@ -929,16 +951,18 @@ int enqueue_plan(fw_batch_plan_s *pl, hipStream_t st, bool untimed, hipStream_t 
     auto *items =
         reinterpret_cast<const BatchItem *>(static_cast<char *>(pl->dev) + sizeof(BatchHeader));
     const bool split = side && has_independent_parts(pl);
-    const int main = split ? main_tile(pl) : 0;
+    const int main = split ? main_group(pl) : 0;
     hipStream_t other = split ? side : st;
     if (split) {
         if ((e = hipEventRecord(fork, st)) != hipSuccess) return status_of(e);
         if ((e = hipStreamWaitEvent(side, fork, 0)) != hipSuccess) return status_of(e);
     }
-    // the side stream's sequences first, so they start with the main chain
-    for (int pass = split ? 0 : 1; pass < 2; ++pass) {
+    // pass 0: the side stream's sequences, pass 1: the main chain
+    const int order[2] = {FW_PLAN_MAIN_FIRST ? 1 : 0, FW_PLAN_MAIN_FIRST ? 0 : 1};
+    for (int oi = split ? 0 : 1; oi < 2; ++oi) {
+        const int pass = split ? order[oi] : 1;
         for (const StagedLaunch &l : pl->staged) {
-            if (split && (pass == 0) == (l.tile == main)) continue;
+            if (split && (pass == 0) == (l.group == main)) continue;
             e = launch_staged(pl->dtype, pl->pred, l.tile, items, pl->work + l.offset, l.kind,
                               l.b, (unsigned)l.count, pass == 0 ? other : st);
             if (e != hipSuccess) return status_of(e);
