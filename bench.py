@@ -120,7 +120,8 @@ def parse():
                     help="batch-plan launch modes to time (comma-separated)")
     ap.add_argument("--batched-tiles", default="",
                     help="tiles of the size buckets 16-32,33-64,65-128,129-256,257-512 "
-                         "(comma-separated) instead of autotuning them")
+                         "(comma-separated) instead of autotuning them; 9 values split "
+                         "129-512 into buckets 64 vertices wide")
     return ap.parse_args()
 
 
@@ -564,13 +565,25 @@ def bench_batched(torch, fw, gen, dev, reps, modes=("graph", "kernel", "per_grap
     # tile per size bucket, picked by the library's autotuner for the batched
     # launch (installed into the plan table the batch plan reads)
     buckets = [(16, 32), (33, 64), (65, 128), (129, 256), (257, 512)]
+    if tiles is not None and len(tiles) == 9:  # buckets 64 vertices wide above 128
+        buckets = buckets[:3] + [(lo + 1, lo + 64) for lo in range(128, 512, 64)]
+    if tiles is not None and len(tiles) != len(buckets):
+        raise SystemExit("--batched-tiles takes 5 tiles (or 9: 16-32, 33-64, 65-128, then "
+                         "129-512 in buckets 64 vertices wide)")
     counts = {(lo, hi): int(((sizes >= lo) & (sizes <= hi)).sum()) for lo, hi in buckets}
+    batch_tuned = None
     if tiles is None:
-        # each bucket tuned on as many graphs as this batch holds in it
+        # each bucket tuned on as many graphs as this batch holds in it, then
+        # the whole batch's plan launch tuned over buckets 64 vertices wide
+        # above 128 (the tile groups share the GPU, which per-bucket timing
+        # cannot see)
         tuned = {}
         for lo, hi in buckets:
             tuned.update(fw.autotune(torch.float32, [(lo, hi)], objective="batched",
                                      batch=max(counts[(lo, hi)], 16), reps=3))
+        fine = buckets[:3] + [(lo + 1, lo + 64) for lo in range(128, 512, 64)]
+        batch_tuned = fw.autotune_batch(torch.float32, [int(v) for v in sizes], fine, reps=9,
+                                        passes=2)
     else:  # given tiles (profiling runs: counters distort the autotuner's timings)
         tuned = {}
         for (lo, hi), t in zip(buckets, tiles):
@@ -586,6 +599,11 @@ def bench_batched(torch, fw, gen, dev, reps, modes=("graph", "kernel", "per_grap
                                               "ms_by_tile": {str(t): round(m, 4)
                                                              for t, m in v["ms"].items()}}
                                for (lo, hi), v in tuned.items()}}
+    if batch_tuned is not None:
+        out["batch_tuned_tiles"] = {f"{lo}-{hi}": {"tile": v["tile"],
+                                                   "ms_by_tile": {str(t): round(m, 4)
+                                                                  for t, m in v["ms"].items()}}
+                                    for (lo, hi), v in batch_tuned.items()}
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     # warm-up launches per mode: the first replays of a fresh graph run a few

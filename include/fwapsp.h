@@ -256,6 +256,30 @@ int fw_autotune(int dtype, const int64_t *lo, const int64_t *hi, int nbuckets, i
                 int batch, int reps, int *tile_out, double *ms_out);
 
 /*
+ * fw_autotune_batch -- tunes the plan table for one batch as a whole (dtype:
+ * a plan key, as for fw_autotune).  n[0..count) are the batch's graph sizes
+ * (0 <= n[g] <= fw_batched_max_n, 1 <= count <= 2^20); buckets [lo[k], hi[k]]
+ * as for fw_autotune (a bucket may lie inside a wider one installed before:
+ * the most recent entry covering a size wins).  The tiles of different
+ * buckets interact inside one batch plan (each tile size is its own chain of
+ * stage launches, and the chains share the GPU), so the objective is the
+ * eager launch of a batch plan over zero matrices of exactly these sizes:
+ * starting from the table's current tile at each bucket's geometric middle,
+ * `passes` rounds of coordinate descent, in which every bucket that holds
+ * some of the graphs times every tile of fw_plan_tiles() (reps + 1 launches,
+ * the first a warm-up, scored by the median) with the other buckets fixed,
+ * and installs the fastest with fw_plan_set.  Writes the chosen tiles to
+ * tile_out[k] and, if ms_out is non-NULL, the last pass's median ms of tile t
+ * for bucket k to ms_out[k * ntiles + t] (0 for buckets skipped).
+ * Synchronous; allocates and frees its own scratch matrices.  Errors:
+ * FW_ERR_INVALID for bad arguments, FW_ERR_UNSUPPORTED for a size above
+ * fw_batched_max_n, FW_ERR_NOMEM/FW_ERR_HIP.
+ */
+int fw_autotune_batch(int dtype, const int64_t *n, int64_t count, const int64_t *lo,
+                      const int64_t *hi, int nbuckets, int reps, int passes, int *tile_out,
+                      double *ms_out);
+
+/*
  * fw_apsp_batched -- many independent graphs in one call.  Graphs of 33
  * vertices and more are stage-batched: for each tile size (from the plan
  * table: a graph with a predecessor matrix reads the FW_PLAN_PRED part),

@@ -15,7 +15,8 @@ _EXPORTS = {
     "fw_negative_cycle", "fw_negative_cycle_vertices", "fw_negative_cycle_find",
     "fw_apsp_semiring", "fw_apsp_ladder", "LADDER_RUNGS", "fw_transitive_closure",
     "fw_transitive_closure_bits", "pack_bits", "unpack_bits", "words_per_row", "fw_path",
-    "plan_tiles", "plan_tile", "plan_set", "plan_reset", "autotune", "save_plan", "load_plan",
+    "plan_tiles", "plan_tile", "plan_set", "plan_reset", "autotune", "autotune_batch",
+    "save_plan", "load_plan",
     "batched_max_n", "BatchPlan", "SolvePlan", "Server", "profile_enable", "profile_read",
     "pred_fallbacks",
     "FwError", "lib", "LIB_PATH",

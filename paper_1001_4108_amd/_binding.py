@@ -92,6 +92,8 @@ def _declare(L):
         "fw_plan_reset": ([], None),
         "fw_autotune": ([ci, P64, P64, ci, ci, ci, ci, ctypes.POINTER(ci),
                          ctypes.POINTER(ctypes.c_double)], ci),
+        "fw_autotune_batch": ([ci, P64, i64, P64, P64, ci, ci, ci, ctypes.POINTER(ci),
+                               ctypes.POINTER(ctypes.c_double)], ci),
         "fw_apsp_batched": ([ctypes.POINTER(vp), P64, P64, i64, ci, ctypes.POINTER(vp), P64, vp],
                             ci),
         "fw_batched_max_n": ([ci, ci], i64),
@@ -383,6 +385,34 @@ def autotune(dtype, buckets, objective: str = "single", batch: int = 256, reps: 
                                  int(reps), out, ms), "fw_autotune")
     return {(int(buckets[i][0]), int(buckets[i][1])):
             {"tile": out[i], "ms": {t: ms[i * len(tiles) + j] for j, t in enumerate(tiles)}}
+            for i in range(k)}
+
+
+def autotune_batch(dtype, sizes, buckets, reps: int = 5, passes: int = 2, device=None,
+                   pred: bool = False) -> dict:
+    """Tune the plan table for one batch as a whole (``fw_autotune_batch``).
+
+    ``sizes`` are the batch's graph sizes, ``buckets`` a list of (lo, hi);
+    each pass times every tile of every bucket that holds some of the graphs
+    on the whole batch plan, the other buckets fixed, and installs the
+    fastest.  Returns {(lo, hi): {"tile": t, "ms": {tile: median_ms}}} (the
+    last pass's times; empty for buckets the batch does not use).
+    """
+    code = _plan_key(dtype, pred)
+    k = len(buckets)
+    ns = (ctypes.c_int64 * max(len(sizes), 1))(*[int(v) for v in sizes])
+    lo = (ctypes.c_int64 * k)(*[int(b[0]) for b in buckets])
+    hi = (ctypes.c_int64 * k)(*[int(b[1]) for b in buckets])
+    tiles = plan_tiles()
+    out = (ctypes.c_int * k)()
+    ms = (ctypes.c_double * (k * len(tiles)))()
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    with torch.cuda.device(dev):
+        _check(lib().fw_autotune_batch(code, ns, len(sizes), lo, hi, k, int(reps), int(passes),
+                                       out, ms), "fw_autotune_batch")
+    return {(int(buckets[i][0]), int(buckets[i][1])):
+            {"tile": out[i], "ms": {t: ms[i * len(tiles) + j] for j, t in enumerate(tiles)
+                                    if ms[i * len(tiles) + j] > 0}}
             for i in range(k)}
 
 
