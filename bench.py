@@ -582,8 +582,8 @@ def bench_batched(torch, fw, gen, dev, reps, modes=("graph", "kernel", "per_grap
             tuned.update(fw.autotune(torch.float32, [(lo, hi)], objective="batched",
                                      batch=max(counts[(lo, hi)], 16), reps=3))
         fine = buckets[:3] + [(lo + 1, lo + 64) for lo in range(128, 512, 64)]
-        batch_tuned = fw.autotune_batch(torch.float32, [int(v) for v in sizes], fine, reps=9,
-                                        passes=2)
+        batch_tuned = fw.autotune_batch(torch.float32, [int(v) for v in sizes], fine,
+                                        mode="graph", reps=9, passes=2)
     else:  # given tiles (profiling runs: counters distort the autotuner's timings)
         tuned = {}
         for (lo, hi), t in zip(buckets, tiles):

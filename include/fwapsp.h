@@ -262,8 +262,10 @@ int fw_autotune(int dtype, const int64_t *lo, const int64_t *hi, int nbuckets, i
  * as for fw_autotune (a bucket may lie inside a wider one installed before:
  * the most recent entry covering a size wins).  The tiles of different
  * buckets interact inside one batch plan (each tile size is its own chain of
- * stage launches, and the chains share the GPU), so the objective is the
- * eager launch of a batch plan over zero matrices of exactly these sizes:
+ * stage launches, and the chains share the GPU), so the objective is a
+ * launch of a batch plan over zero matrices of exactly these sizes, in `mode`
+ * as for fw_batch_plan_launch (0: eager kernel launches, 1: a replay of the
+ * plan's captured graph; the two can favour different tiles):
  * starting from the table's current tile at each bucket's geometric middle,
  * `passes` rounds of coordinate descent, in which every bucket that holds
  * some of the graphs times every tile of fw_plan_tiles() (reps + 1 launches,
@@ -276,8 +278,8 @@ int fw_autotune(int dtype, const int64_t *lo, const int64_t *hi, int nbuckets, i
  * fw_batched_max_n, FW_ERR_NOMEM/FW_ERR_HIP.
  */
 int fw_autotune_batch(int dtype, const int64_t *n, int64_t count, const int64_t *lo,
-                      const int64_t *hi, int nbuckets, int reps, int passes, int *tile_out,
-                      double *ms_out);
+                      const int64_t *hi, int nbuckets, int mode, int reps, int passes,
+                      int *tile_out, double *ms_out);
 
 /*
  * fw_apsp_batched -- many independent graphs in one call.  Graphs of 33

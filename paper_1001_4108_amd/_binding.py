@@ -92,7 +92,7 @@ def _declare(L):
         "fw_plan_reset": ([], None),
         "fw_autotune": ([ci, P64, P64, ci, ci, ci, ci, ctypes.POINTER(ci),
                          ctypes.POINTER(ctypes.c_double)], ci),
-        "fw_autotune_batch": ([ci, P64, i64, P64, P64, ci, ci, ci, ctypes.POINTER(ci),
+        "fw_autotune_batch": ([ci, P64, i64, P64, P64, ci, ci, ci, ci, ctypes.POINTER(ci),
                                ctypes.POINTER(ctypes.c_double)], ci),
         "fw_apsp_batched": ([ctypes.POINTER(vp), P64, P64, i64, ci, ctypes.POINTER(vp), P64, vp],
                             ci),
@@ -388,14 +388,15 @@ def autotune(dtype, buckets, objective: str = "single", batch: int = 256, reps: 
             for i in range(k)}
 
 
-def autotune_batch(dtype, sizes, buckets, reps: int = 5, passes: int = 2, device=None,
-                   pred: bool = False) -> dict:
+def autotune_batch(dtype, sizes, buckets, mode: str = "graph", reps: int = 5, passes: int = 2,
+                   device=None, pred: bool = False) -> dict:
     """Tune the plan table for one batch as a whole (``fw_autotune_batch``).
 
-    ``sizes`` are the batch's graph sizes, ``buckets`` a list of (lo, hi);
-    each pass times every tile of every bucket that holds some of the graphs
-    on the whole batch plan, the other buckets fixed, and installs the
-    fastest.  Returns {(lo, hi): {"tile": t, "ms": {tile: median_ms}}} (the
+    ``sizes`` are the batch's graph sizes, ``buckets`` a list of (lo, hi),
+    ``mode`` the launch mode to tune for ("graph" or "kernel", as
+    ``BatchPlan.launch``); each pass times every tile of every bucket that
+    holds some of the graphs on the whole batch plan, the other buckets
+    fixed, and installs the fastest.  Returns {(lo, hi): {"tile": t, "ms": {tile: median_ms}}} (the
     last pass's times; empty for buckets the batch does not use).
     """
     code = _plan_key(dtype, pred)
@@ -408,8 +409,11 @@ def autotune_batch(dtype, sizes, buckets, reps: int = 5, passes: int = 2, device
     ms = (ctypes.c_double * (k * len(tiles)))()
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     with torch.cuda.device(dev):
-        _check(lib().fw_autotune_batch(code, ns, len(sizes), lo, hi, k, int(reps), int(passes),
-                                       out, ms), "fw_autotune_batch")
+        if mode not in ("graph", "kernel"):
+            raise ValueError("mode is 'graph' or 'kernel'")
+        _check(lib().fw_autotune_batch(code, ns, len(sizes), lo, hi, k,
+                                       1 if mode == "graph" else 0, int(reps), int(passes), out,
+                                       ms), "fw_autotune_batch")
     return {(int(buckets[i][0]), int(buckets[i][1])):
             {"tile": out[i], "ms": {t: ms[i * len(tiles) + j] for j, t in enumerate(tiles)
                                     if ms[i * len(tiles) + j] > 0}}

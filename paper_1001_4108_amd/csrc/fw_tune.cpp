@@ -152,14 +152,17 @@ extern "C" int fw_autotune(int dtype, const int64_t *lo, const int64_t *hi, int 
 // is slower for the batch.  Coordinate descent on the plan launch of a batch
 // of the given sizes: in each pass, every bucket that holds some of the
 // batch's graphs tries every tile with the others fixed and keeps the
-// fastest.  Zero matrices again (the sweep is data-oblivious).
+// fastest, timing plan launches as the caller will run them (eager launches,
+// or replays of the captured graph: the two can favour different tiles, as
+// the graph's parallel branches are ordered by the runtime rather than by the
+// order of enqueueing).  Zero matrices again (the sweep is data-oblivious).
 extern "C" int fw_autotune_batch(int dtype, const int64_t *n, int64_t count, const int64_t *lo,
-                                 const int64_t *hi, int nbuckets, int reps, int passes,
+                                 const int64_t *hi, int nbuckets, int mode, int reps, int passes,
                                  int *tile_out, double *ms_out) {
     const int base = dtype & ~FW_PLAN_PRED;
     const bool pred = (dtype & FW_PLAN_PRED) != 0;
     if ((base != FW_F32 && base != FW_I32) || !n || count < 1 || count > (1 << 20) || !lo ||
-        !hi || nbuckets < 1 || !tile_out || reps < 1 || passes < 1)
+        !hi || nbuckets < 1 || !tile_out || reps < 1 || passes < 1 || (mode != 0 && mode != 1))
         return FW_ERR_INVALID;
     for (int k = 0; k < nbuckets; ++k)
         if (lo[k] < 2 || hi[k] < lo[k] || hi[k] > 65536) return FW_ERR_INVALID;
@@ -194,7 +197,8 @@ extern "C" int fw_autotune_batch(int dtype, const int64_t *n, int64_t count, con
             preds[(size_t)g] =
                 reinterpret_cast<int32_t *>(static_cast<char *>(sc.mat) + per_set + offs[(size_t)g]);
     }
-    // the median time of one eager plan launch with the table as it stands
+    // the median time of one plan launch in `mode` with the table as it stands
+    // (a graph launch replays the graph the first launch captured)
     auto time_batch = [&](double &out) -> int {
         fw_batch_plan plan = nullptr;
         int s = fw_batch_plan_create(ptrs.data(), ns.data(), lds.data(), count, base,
@@ -204,7 +208,7 @@ extern "C" int fw_autotune_batch(int dtype, const int64_t *n, int64_t count, con
         std::vector<double> times;
         for (int r = 0; r <= reps && s == FW_OK; ++r) {  // the first launch is a warm-up
             if ((e = hipEventRecord(sc.e0, sc.st)) != hipSuccess) s = status_of(e);
-            if (s == FW_OK) s = fw_batch_plan_launch(plan, 0, sc.st);
+            if (s == FW_OK) s = fw_batch_plan_launch(plan, mode, sc.st);
             if (s == FW_OK && (e = hipEventRecord(sc.e1, sc.st)) != hipSuccess) s = status_of(e);
             if (s == FW_OK && (e = hipEventSynchronize(sc.e1)) != hipSuccess) s = status_of(e);
             float ms = 0.f;

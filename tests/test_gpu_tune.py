@@ -65,21 +65,23 @@ def test_autotune_predecessor_table(objective, tmp_path):
 
 
 def test_autotune_batch_installs_tiles_and_stays_exact():
-    """Whole-batch tuning installs one of the plan's tiles per used bucket,
-    skips the unused one, and batched solves afterwards stay bit-exact."""
+    """Whole-batch tuning (eager and graph launches) installs one of the
+    plan's tiles per used bucket, the fastest it timed, skips the unused
+    bucket, and batched solves afterwards stay bit-exact."""
     rng = np.random.default_rng(11)
     sizes = [int(v) for v in rng.integers(20, 300, size=48)]
     buckets = [(16, 64), (65, 200), (201, 300), (301, 400)]
+    tiles = set(fw.plan_tiles())
     try:
-        res = fw.autotune_batch(torch.float32, sizes, buckets, reps=2, passes=1)
-        tiles = set(fw.plan_tiles())
-        for (lo, hi), v in res.items():
-            assert v["tile"] in tiles
-            used = any(lo <= n <= hi for n in sizes)
-            assert bool(v["ms"]) == used
-            if used:
-                assert fw.plan_tile(torch.float32, (lo + hi) // 2) == v["tile"]
-                assert min(v["ms"], key=v["ms"].get) == v["tile"]
+        for mode in ("kernel", "graph"):
+            res = fw.autotune_batch(torch.float32, sizes, buckets, mode=mode, reps=2, passes=1)
+            for (lo, hi), v in res.items():
+                assert v["tile"] in tiles
+                used = any(lo <= n <= hi for n in sizes)
+                assert bool(v["ms"]) == used
+                if used:
+                    assert fw.plan_tile(torch.float32, (lo + hi) // 2) == v["tile"]
+                    assert min(v["ms"], key=v["ms"].get) == v["tile"]
         graphs = [gen.dense_graph(n, 0.3, 1, 9, 900 + g) for g, n in enumerate(sizes[:12])]
         ts = [torch.from_numpy(w).cuda() for w in graphs]
         fw.fw_apsp_batched(ts)
@@ -97,3 +99,5 @@ def test_autotune_batch_rejects_bad_arguments():
         fw.autotune_batch(torch.float32, [10, 10 ** 6], [(2, 64)])
     with pytest.raises(fw.FwError):
         fw.autotune_batch(torch.float32, [10], [(2, 64)], reps=0)
+    with pytest.raises(ValueError):
+        fw.autotune_batch(torch.float32, [10], [(2, 64)], mode="eager")
