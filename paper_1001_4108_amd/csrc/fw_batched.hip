@@ -67,7 +67,7 @@ __device__ void blocked_in_wg(T *d, int32_t *p, int n, int64_t ld, int64_t ldp, 
     const int nb = (n + S - 1) / S;
     const int m = nb - 1;
     for (int b = 0; b < nb; ++b) {
-        closure_tile<T, S, TMC, PRED>(d, p, n, ld, ldp, b * S, smem);
+        closure_tile_any<T, S, TMC, PRED>(d, p, n, ld, ldp, b * S, smem);
         if (m == 0) break;
         for (int t = 0; t < 2 * m; ++t) {
             int bi, bj;
@@ -283,7 +283,7 @@ staged_kernel(const BatchItem *items, const StagedWork *work, int kind, int b) {
             if (with_pred)
                 closure_tile<T, S, TM, PRED>(d, as_global(it.p), it.n, it.ld, it.ldp, (b + 1) * S, smem);
             else
-                closure_tile<T, S, TM, false>(d, nullptr, it.n, it.ld, 0, (b + 1) * S, smem);
+                closure_tile_any<T, S, TM, false>(d, nullptr, it.n, it.ld, 0, (b + 1) * S, smem);
         }
     }
 }
@@ -301,106 +301,20 @@ template <int S>
 constexpr int staged_diag_tm() {
     return S == 32 ? 2 : 4;
 }
-// Closure of the diagonal tile (base, base) two k-steps per barrier, with the
-// bits of closure_tile (min-plus, no predecessors; TM x TM cells per thread).
-// Before steps k and k+1 (k even) the owners publish rows k, k+1 and columns
-// k, k+1 as they stand.  Every thread then forms row k+1 and column k+1 after
-// step k itself -- c[k+1][j] <- min(c[k+1][j], c[k+1][k] + c[k][j]), and
-// c[i][k+1] <- min(c[i][k+1], c[i][k] + c[k][k+1]) -- and applies both steps
-// at once: c[i][j] <- min(c[i][j], c[i][k] + c[k][j], c[i][k+1]' + c[k+1][j]'),
-// the same sums of the same values as the two steps in turn.  Half the
-// barriers of closure_tile for the same VALU count.  Steps past the graph's
-// last vertex (a padded k rounding the count up to even) change no real cell.
-template <typename T, int S, int TM>
-__device__ __forceinline__ void closure_tile_pairs(T *__restrict__ d, int n, int64_t ld,
-                                                   int base, char *smem) {
-    using A = Ar<T>;
-    constexpr int G = S / TM;
-    static_assert(TM % 2 == 0, "a thread owns both rows (columns) of a step pair");
-    T(*rowb)[2][S] = reinterpret_cast<T(*)[2][S]>(smem);               // [parity][k, k+1][S]
-    T(*colb)[2][S] = reinterpret_cast<T(*)[2][S]>(smem + 4 * S * sizeof(T));
-    const int tx = threadIdx.x % G, ty = threadIdx.x / G;
-    T c[TM][TM];
-#pragma unroll
-    for (int r = 0; r < TM; ++r) {
-        const int gi = base + ty * TM + r;
-#pragma unroll
-        for (int q = 0; q < TM; ++q) {
-            const int gj = base + tx * TM + q;
-            c[r][q] = (gi < n && gj < n) ? d[(int64_t)gi * ld + gj] : A::inf();
-        }
-    }
-    const int kreal = n - base < S ? n - base : S;
-    const int kb_end = (kreal + TM - 1) / TM;
-    for (int kb = 0; kb < kb_end; ++kb) {
-#pragma unroll
-        for (int rp = 0; rp < TM; rp += 2) {
-            const int buf = ((kb * TM + rp) >> 1) & 1;
-            if (ty == kb) {
-#pragma unroll
-                for (int q = 0; q < TM; ++q) {
-                    rowb[buf][0][tx * TM + q] = c[rp][q];
-                    rowb[buf][1][tx * TM + q] = c[rp + 1][q];
-                }
-            }
-            if (tx == kb) {
-#pragma unroll
-                for (int q = 0; q < TM; ++q) {
-                    colb[buf][0][ty * TM + q] = c[q][rp];
-                    colb[buf][1][ty * TM + q] = c[q][rp + 1];
-                }
-            }
-            __syncthreads();
-            const int k = kb * TM + rp;
-            const T a = colb[buf][0][k + 1];  // c[k+1][k]
-            const T e = rowb[buf][0][k + 1];  // c[k][k+1]
-            T r0[TM], r1[TM], c0[TM], c1[TM];
-#pragma unroll
-            for (int q = 0; q < TM; ++q) {
-                r0[q] = rowb[buf][0][tx * TM + q];
-                r1[q] = A::min2(rowb[buf][1][tx * TM + q], A::add(a, r0[q]));
-                c0[q] = colb[buf][0][ty * TM + q];
-                c1[q] = A::min2(colb[buf][1][ty * TM + q], A::add(c0[q], e));
-            }
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TM; ++j)
-                    c[i][j] = A::min3(c[i][j], A::add(c0[i], r0[j]), A::add(c1[i], r1[j]));
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < TM; ++r) {
-        const int gi = base + ty * TM + r;
-#pragma unroll
-        for (int q = 0; q < TM; ++q) {
-            const int gj = base + tx * TM + q;
-            if (gi < n && gj < n) d[(int64_t)gi * ld + gj] = c[r][q];
-        }
-    }
-}
-
-#ifndef FW_STAGED_DIAG_PAIRS
-#define FW_STAGED_DIAG_PAIRS 1
-#endif
 template <typename T, int S, bool PRED>
 __global__ void __launch_bounds__((S / staged_diag_tm<S>()) * (S / staged_diag_tm<S>()))
 staged_diag_kernel(const BatchItem *items, const StagedWork *work, int b) {
     // a plan with predecessors may hold graphs without: room for both forms
-    constexpr int kSmem0 = closure_smem_bytes<T, S, PRED>() > closure_smem_bytes<T, S, false>()
-                               ? closure_smem_bytes<T, S, PRED>()
-                               : closure_smem_bytes<T, S, false>();
-    // the two-step form double-buffers rows and columns k and k+1
-    constexpr int kSmem = kSmem0 > 8 * S * (int)sizeof(T) ? kSmem0 : 8 * S * (int)sizeof(T);
+    constexpr int kSmem = closure_smem_bytes<T, S, PRED>() > closure_smem_bytes<T, S, false>()
+                              ? closure_smem_bytes<T, S, PRED>()
+                              : closure_smem_bytes<T, S, false>();
     __shared__ __align__(16) char smem[kSmem];
     const BatchItem it = items[work[blockIdx.x].item];
     T *d = as_global(static_cast<T *>(it.d));
     if (PRED && it.p != nullptr)
         closure_tile<T, S, staged_diag_tm<S>(), PRED>(d, as_global(it.p), it.n, it.ld, it.ldp, b * S, smem);
-    else if (S == 128 && FW_STAGED_DIAG_PAIRS)
-        closure_tile_pairs<T, S, staged_diag_tm<S>()>(d, it.n, it.ld, b * S, smem);
     else
-        closure_tile<T, S, staged_diag_tm<S>(), false>(d, nullptr, it.n, it.ld, 0, b * S, smem);
+        closure_tile_any<T, S, staged_diag_tm<S>(), false>(d, nullptr, it.n, it.ld, 0, b * S, smem);
 }
 
 // ---------------------------------------------------------------------------

@@ -78,7 +78,7 @@ diag_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
             int b, int32_t *flag, const int32_t *gate) {
     __shared__ __align__(16) char smem[closure_smem_bytes<T, S, PRED>()];
     if (gated_off(gate) || given_up<A>(flag)) return;
-    closure_tile<T, S, TM, PRED, A>(d, P, n, ld, ldp, b * S, smem, flag);
+    closure_tile_any<T, S, TM, PRED, A>(d, P, n, ld, ldp, b * S, smem, flag);
 }
 
 // Phases 2 and 3: one tile per workgroup.
@@ -135,9 +135,11 @@ tile_kernel(T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld, int64
     else
         product_tile<T, S, BK, TM, TN, VEC, PRED, A>(d, P, n, ld, ldp, bi, bj, b, smem, flag);
     if constexpr (tile_can_close<S, TM, TN, PRED>()) {
+        static_assert(tile_smem_bytes<T, S, BK, PRED, A>() >= closure_smem_bytes<T, S, PRED>(),
+                      "the closure runs in the product's LDS");
         if (close) {
             __syncthreads();  // the tile's stores before its reloads
-            closure_tile<T, S, TM, PRED, A>(d, P, n, ld, ldp, (b + 1) * S, smem, flag);
+            closure_tile_any<T, S, TM, PRED, A>(d, P, n, ld, ldp, (b + 1) * S, smem, flag);
         }
     }
 }

@@ -257,9 +257,11 @@ __device__ __forceinline__ void row_store(const T (&v)[E], T *__restrict__ base,
 // suffices.  The TM steps of one register row are unrolled so the owner's
 // register index is a compile-time constant.
 // ---------------------------------------------------------------------------
+// (without predecessors: room for closure_tile_pairs' double-buffered rows
+// and columns k and k+1)
 template <typename T, int S, bool PRED>
 constexpr int closure_smem_bytes() {
-    return 4 * S * (int)sizeof(T) + (PRED ? 2 * S * 4 : 0);
+    return PRED ? 4 * S * (int)sizeof(T) + 2 * S * 4 : 8 * S * (int)sizeof(T);
 }
 
 // FULL: the caller guarantees a tile inside the matrix with 16-byte aligned
@@ -386,6 +388,103 @@ __device__ __forceinline__ void closure_tile(T *__restrict__ d, int32_t *__restr
     }
     // the LDS row/column buffers may be reused by the caller right away
     __syncthreads();
+}
+
+// closure_tile two k-steps per barrier, with closure_tile's bits (no
+// predecessors, no range-checked keys; TM x TM cells per thread, TM even).
+// Before steps k and k+1 (k even) the owners publish rows k, k+1 and columns
+// k, k+1 as they stand.  Every thread then forms row k+1 and column k+1 as
+// step k leaves them -- c[k+1][j] <- c[k+1][j] + (c[k+1][k] x c[k][j]), and
+// c[i][k+1] <- c[i][k+1] + (c[i][k] x c[k][k+1]) in the semiring's (+, x) --
+// and applies both steps at once with one 3-input reduction:
+// c[i][j] <- c[i][j] + c[i][k] x c[k][j] + c'[i][k+1] x c'[k+1][j].  These are
+// the same operations on the same values as the two steps in turn, so the
+// result is bit-identical for any weights.  Half the barriers of closure_tile
+// for the same VALU count.  Steps past the last vertex (the padded k that
+// rounds an odd count up) change no real cell: the padded rows and columns
+// are absent.
+template <typename T, int S, int TM, class A = Ar<T>>
+__device__ __forceinline__ void closure_tile_pairs(T *__restrict__ d, int n, int64_t ld, int base,
+                                                   char *smem) {
+    static_assert(TM % 2 == 0, "a thread owns both rows (columns) of a step pair");
+    static_assert(!A::kChecked, "range-checked keys take closure_tile");
+    constexpr int G = S / TM;
+    T(*rowb)[2][S] = reinterpret_cast<T(*)[2][S]>(smem);  // [parity][k, k+1][S]
+    T(*colb)[2][S] = reinterpret_cast<T(*)[2][S]>(smem + 4 * S * sizeof(T));
+    const int tx = threadIdx.x % G, ty = threadIdx.x / G;
+    T c[TM][TM];
+#pragma unroll
+    for (int r = 0; r < TM; ++r) {
+        const int gi = base + ty * TM + r;
+#pragma unroll
+        for (int q = 0; q < TM; ++q) {
+            const int gj = base + tx * TM + q;
+            c[r][q] = (gi < n && gj < n) ? d[(int64_t)gi * ld + gj] : A::inf();
+        }
+    }
+    const int kreal = n - base < S ? n - base : S;
+    const int kb_end = (kreal + TM - 1) / TM;
+    for (int kb = 0; kb < kb_end; ++kb) {
+#pragma unroll
+        for (int rp = 0; rp < TM; rp += 2) {
+            const int buf = ((kb * TM + rp) >> 1) & 1;
+            if (ty == kb) {
+#pragma unroll
+                for (int q = 0; q < TM; ++q) {
+                    rowb[buf][0][tx * TM + q] = c[rp][q];
+                    rowb[buf][1][tx * TM + q] = c[rp + 1][q];
+                }
+            }
+            if (tx == kb) {
+#pragma unroll
+                for (int q = 0; q < TM; ++q) {
+                    colb[buf][0][ty * TM + q] = c[q][rp];
+                    colb[buf][1][ty * TM + q] = c[q][rp + 1];
+                }
+            }
+            __syncthreads();
+            const int k = kb * TM + rp;
+            const T a = colb[buf][0][k + 1];  // c[k+1][k]
+            const T e = rowb[buf][0][k + 1];  // c[k][k+1]
+            T r0[TM], r1[TM], c0[TM], c1[TM];
+#pragma unroll
+            for (int q = 0; q < TM; ++q) {
+                r0[q] = rowb[buf][0][tx * TM + q];
+                r1[q] = A::min2(rowb[buf][1][tx * TM + q], A::add(a, r0[q]));
+                c0[q] = colb[buf][0][ty * TM + q];
+                c1[q] = A::min2(colb[buf][1][ty * TM + q], A::add(c0[q], e));
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TM; ++j)
+                    c[i][j] = A::min3(c[i][j], A::add(c0[i], r0[j]), A::add(c1[i], r1[j]));
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < TM; ++r) {
+        const int gi = base + ty * TM + r;
+#pragma unroll
+        for (int q = 0; q < TM; ++q) {
+            const int gj = base + tx * TM + q;
+            if (gi < n && gj < n) d[(int64_t)gi * ld + gj] = c[r][q];
+        }
+    }
+}
+
+// The diagonal closure in the form its arguments allow: two k-steps per
+// barrier without predecessors or range-checked keys, else closure_tile.
+#ifndef FW_CLOSURE_PAIRS
+#define FW_CLOSURE_PAIRS 1
+#endif
+template <typename T, int S, int TM, bool PRED, class A = Ar<T>>
+__device__ __forceinline__ void closure_tile_any(T *__restrict__ d, int32_t *__restrict__ P, int n,
+                                                 int64_t ld, int64_t ldp, int base, char *smem,
+                                                 int32_t *flag = nullptr) {
+    if constexpr (FW_CLOSURE_PAIRS && !PRED && !A::kChecked && TM % 2 == 0)
+        closure_tile_pairs<T, S, TM, A>(d, n, ld, base, smem);
+    else
+        closure_tile<T, S, TM, PRED, A>(d, P, n, ld, ldp, base, smem, flag);
 }
 
 // ---------------------------------------------------------------------------
