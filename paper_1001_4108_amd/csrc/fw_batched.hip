@@ -719,6 +719,9 @@ namespace {
 #ifndef FW_PLAN_MAIN_FIRST
 #define FW_PLAN_MAIN_FIRST 1
 #endif
+#ifndef FW_PLAN_FORK_AFTER_FIRST
+#define FW_PLAN_FORK_AFTER_FIRST 1
+#endif
 #ifndef FW_STAGED_XCD_GROUPS
 #define FW_STAGED_XCD_GROUPS 8
 #endif
@@ -953,19 +956,30 @@ int enqueue_plan(fw_batch_plan_s *pl, hipStream_t st, bool untimed, hipStream_t 
     const bool split = side && has_independent_parts(pl);
     const int main = split ? main_group(pl) : 0;
     hipStream_t other = split ? side : st;
-    if (split) {
-        if ((e = hipEventRecord(fork, st)) != hipSuccess) return status_of(e);
-        if ((e = hipStreamWaitEvent(side, fork, 0)) != hipSuccess) return status_of(e);
-    }
+    // The side stream forks from the caller's stream after the main chain's
+    // first launch (with FW_PLAN_FORK_AFTER_FIRST), so that the critical
+    // chain takes the GPU first also where the launches are replayed from a
+    // captured graph, whose parallel branches the runtime orders itself.
+    bool forked = false;
+    auto do_fork = [&]() -> hipError_t {
+        if (!split || forked) return hipSuccess;
+        forked = true;
+        hipError_t r = hipEventRecord(fork, st);
+        return r == hipSuccess ? hipStreamWaitEvent(side, fork, 0) : r;
+    };
+    if (!FW_PLAN_FORK_AFTER_FIRST || !FW_PLAN_MAIN_FIRST)
+        if ((e = do_fork()) != hipSuccess) return status_of(e);
     // pass 0: the side stream's sequences, pass 1: the main chain
     const int order[2] = {FW_PLAN_MAIN_FIRST ? 1 : 0, FW_PLAN_MAIN_FIRST ? 0 : 1};
     for (int oi = split ? 0 : 1; oi < 2; ++oi) {
         const int pass = split ? order[oi] : 1;
+        if (pass == 0 && (e = do_fork()) != hipSuccess) return status_of(e);
         for (const StagedLaunch &l : pl->staged) {
             if (split && (pass == 0) == (l.group == main)) continue;
             e = launch_staged(pl->dtype, pl->pred, l.tile, items, pl->work + l.offset, l.kind,
                               l.b, (unsigned)l.count, pass == 0 ? other : st);
             if (e != hipSuccess) return status_of(e);
+            if (pass == 1 && (e = do_fork()) != hipSuccess) return status_of(e);
         }
         if (pass == 0 || !split) {
             if (pl->count > pl->n_staged) {
