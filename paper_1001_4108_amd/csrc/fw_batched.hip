@@ -6,15 +6,20 @@
 // their panel tiles, all their bulk tiles -- so a large graph is spread over
 // the whole GPU instead of one workgroup.  Where the bulk kernel has the
 // closure's geometry, the workgroup of bulk tile (b+1, b+1) also closes it,
-// and stages after the first need no diagonal launch.  The smaller graphs go through one
+// and stages after the first need no diagonal launch; aligned tile-128 graphs
+// without predecessors run their panels and bulk on a direct-copy tile
+// (staged_tile_dma) and keep a diagonal launch per stage.  The tile groups and
+// the persistent part below depend on nothing in each other and run on two
+// streams of the plan.  The smaller graphs go through one
 // persistent launch in which each workgroup repeatedly takes the next graph
 // from a device work counter (largest first) and solves it alone:
-//   * n <= tile: closure_tile over the whole graph -- the plain algorithm of
-//     section 3.1 with one barrier per k-step;
+//   * n <= tile: the diagonal closure over the whole graph -- the plain
+//     algorithm of section 3.1;
 //   * n >  tile: the blocked schedule run inside the workgroup (diagonal
 //     tile, panel tiles, bulk tiles, workgroup barriers between the phases).
-// The tile comes from the same plan table as single-graph solves and the
-// per-cell work is the same code (fw_tiles.h), so a graph's bits do not
+// The tile comes from the same plan table as single-graph solves, and every
+// cell takes the same candidates in the same order as there (the same code
+// from fw_tiles.h, or staged_tile_dma's same sums), so a graph's bits do not
 // depend on whether it was solved alone or in a batch.
 //
 // No workgroup ever waits for another one, so every grid drains.
@@ -159,7 +164,8 @@ batched_kernel(BatchHeader *hdr, const BatchItem *items) {
 // of all panel tiles and one of all bulk tiles of the graphs that still have
 // a stage b (kernel boundaries order the phases, as in a single solve); the
 // diagonal launch of stage b > 0 is folded into stage b-1's bulk launch where
-// the kernels allow it (staged_can_close).  A
+// the kernels allow it (staged_can_close), and stays a launch of its own for
+// the direct-copy tile-128 path.  A
 // launch's workgroups are listed in a table of (graph, tile number) pairs,
 // built on the host when the plan is created.
 // ---------------------------------------------------------------------------
