@@ -261,6 +261,19 @@ def test_f32_fallbacks_and_unreachable(what):
     assert np.array_equal(P, oracle.canonical_pred(ref, w))
 
 
+def test_f32_nan_entry_leaves_the_keyed_sweep():
+    """A NaN is outside the contract, but the keyed sweep's input check must
+    still see it (a NaN is not an integer) and hand the solve to the
+    compare form."""
+    n = 200
+    w = gen.dense_graph(n, 0.2, 1, 100, seed=71, dtype=np.float32)
+    w[3, 7] = np.nan
+    print("[pred keys] f32 NaN entry", flush=True)
+    before = fw.pred_fallbacks()
+    _solve(w)
+    assert fw.pred_fallbacks() == before + 1
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_f32_keyed_equals_fallback_random(seed):
     rng = np.random.default_rng(700 + seed)
