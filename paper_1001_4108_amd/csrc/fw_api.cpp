@@ -282,7 +282,7 @@ int enqueue_solve_keyed(void *d, int dtype, int n, int64_t ld, int32_t *pred, in
     if (s == FW_OK)
         s = enqueue_solve(d, dtype, n, ld, pred, ldp, tile, st, capturing, kMinPlus, nullptr,
                           scratch);
-    if (own) hipFreeAsync(scratch, st);
+    if (own) (void)hipFreeAsync(scratch, st);
     return s;
 }
 
@@ -632,10 +632,10 @@ struct fw_solve_plan_s {
 
 namespace {
 void free_solve_plan(fw_solve_plan_s *pl) {
-    if (pl->exec) hipGraphExecDestroy(pl->exec);
-    if (pl->graph) hipGraphDestroy(pl->graph);
-    if (pl->cap_stream) hipStreamDestroy(pl->cap_stream);
-    if (pl->key_scratch) hipFree(pl->key_scratch);
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+    if (pl->key_scratch) (void)hipFree(pl->key_scratch);
     delete pl;
 }
 }  // namespace
@@ -694,7 +694,7 @@ int fw_solve_plan_launch(fw_solve_plan pl, int mode, void *stream) {
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(pl->cap_stream, &g);
         if (s != FW_OK) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return s;
         }
         if (e != hipSuccess) return status_of(e);
@@ -713,11 +713,11 @@ int fw_solve_plan_tile(fw_solve_plan pl) { return pl ? pl->tile : -1; }
 int fw_solve_plan_destroy(fw_solve_plan pl) {
     if (!pl) return FW_ERR_INVALID;
     int dev = 0;
-    hipGetDevice(&dev);
-    hipSetDevice(pl->device);
-    hipDeviceSynchronize();
+    (void)hipGetDevice(&dev);
+    (void)hipSetDevice(pl->device);
+    (void)hipDeviceSynchronize();
     free_solve_plan(pl);
-    hipSetDevice(dev);
+    (void)hipSetDevice(dev);
     return FW_OK;
 }
 

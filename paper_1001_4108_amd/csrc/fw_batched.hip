@@ -1017,15 +1017,15 @@ hipError_t plan_side(fw_batch_plan_s *pl) {
 }
 
 void free_plan(fw_batch_plan_s *pl) {
-    if (pl->work) hipFree(pl->work);
-    if (pl->exec) hipGraphExecDestroy(pl->exec);
-    if (pl->graph) hipGraphDestroy(pl->graph);
-    if (pl->cap_stream) hipStreamDestroy(pl->cap_stream);
-    if (pl->side) hipStreamDestroy(pl->side);
-    if (pl->fork) hipEventDestroy(pl->fork);
-    if (pl->join) hipEventDestroy(pl->join);
-    if (pl->dev) hipFree(pl->dev);
-    if (pl->host) hipHostFree(pl->host);
+    if (pl->work) (void)hipFree(pl->work);
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+    if (pl->side) (void)hipStreamDestroy(pl->side);
+    if (pl->fork) (void)hipEventDestroy(pl->fork);
+    if (pl->join) (void)hipEventDestroy(pl->join);
+    if (pl->dev) (void)hipFree(pl->dev);
+    if (pl->host) (void)hipHostFree(pl->host);
     delete pl;
 }
 
@@ -1051,8 +1051,8 @@ void reap_pending(bool all) {
         g_pending.swap(keep);
     }
     for (auto &p : drop) {
-        hipEventSynchronize(p.done);
-        hipEventDestroy(p.done);
+        (void)hipEventSynchronize(p.done);
+        (void)hipEventDestroy(p.done);
         free_plan(p.plan);
     }
 }
@@ -1175,7 +1175,7 @@ int fw_batch_plan_launch(fw_batch_plan plan, int mode, void *stream) {
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(plan->cap_stream, &g);
         if (s != FW_OK) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return s;
         }
         if (e != hipSuccess) return status_of(e);
@@ -1188,7 +1188,7 @@ int fw_batch_plan_launch(fw_batch_plan plan, int mode, void *stream) {
 
 int fw_batch_plan_destroy(fw_batch_plan plan) {
     if (!plan) return FW_ERR_INVALID;
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     free_plan(plan);
     return FW_OK;
 }
@@ -1213,8 +1213,8 @@ int fw_apsp_batched(void *const *d, const int64_t *n, const int64_t *ld, int64_t
     hipEvent_t ev = nullptr;
     if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
         hipEventRecord(ev, st) != hipSuccess) {
-        hipStreamSynchronize(st);
-        if (ev) hipEventDestroy(ev);
+        (void)hipStreamSynchronize(st);
+        if (ev) (void)hipEventDestroy(ev);
         free_plan(pl);
         return s != FW_OK ? s : FW_ERR_HIP;
     }

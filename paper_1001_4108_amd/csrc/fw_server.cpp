@@ -238,7 +238,7 @@ int enqueue_group(fw_server_s *s, Group *g) {
 }
 
 void dispatcher_main(fw_server_s *s) {
-    hipSetDevice(s->device);
+    (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
         if (s->stop) {
@@ -318,13 +318,13 @@ void dispatcher_main(fw_server_s *s) {
         }
         lk.lock();
         if (st != FW_OK) {
-            if (g->done) hipStreamSynchronize(w.st);
+            if (g->done) (void)hipStreamSynchronize(w.st);
             for (Request *r : g->reqs) {
                 r->status = st;
                 r->t_done = now_ns();
                 complete_locked(s, r);
             }
-            if (g->done) hipEventDestroy(g->done);
+            if (g->done) (void)hipEventDestroy(g->done);
             delete g;
             w.busy = false;
             s->cv_done.notify_all();
@@ -337,7 +337,7 @@ void dispatcher_main(fw_server_s *s) {
 }
 
 void completer_main(fw_server_s *s, int idx) {
-    hipSetDevice(s->device);
+    (void)hipSetDevice(s->device);
     Worker &w = s->workers[idx];
     std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
@@ -356,7 +356,7 @@ void completer_main(fw_server_s *s, int idx) {
             r->status = status_of(e);
             complete_locked(s, r);
         }
-        hipEventDestroy(g->done);
+        (void)hipEventDestroy(g->done);
         delete g;
         w.busy = false;
         s->cv_dispatch.notify_all();
@@ -400,13 +400,13 @@ int fw_server_create(const fw_server_config *cfg, fw_server *out) {
     }
     if (status != FW_OK) {
         for (auto &w : s->workers) {
-            if (w.st) hipStreamDestroy(w.st);
-            if (w.host_table) hipHostFree(w.host_table);
-            if (w.dev_table) hipFree(w.dev_table);
-            if (w.host_work) hipHostFree(w.host_work);
-            if (w.dev_work) hipFree(w.dev_work);
+            if (w.st) (void)hipStreamDestroy(w.st);
+            if (w.host_table) (void)hipHostFree(w.host_table);
+            if (w.dev_table) (void)hipFree(w.dev_table);
+            if (w.host_work) (void)hipHostFree(w.host_work);
+            if (w.dev_work) (void)hipFree(w.dev_work);
         }
-        if (s->arena_mem) hipFree(s->arena_mem);
+        if (s->arena_mem) (void)hipFree(s->arena_mem);
         delete s;
         return status;
     }
@@ -537,15 +537,15 @@ int fw_server_destroy(fw_server s) {
     for (auto &w : s->workers)
         if (w.completer.joinable()) w.completer.join();
     for (auto &w : s->workers) {
-        hipStreamSynchronize(w.st);
-        hipStreamDestroy(w.st);
-        hipHostFree(w.host_table);
-        hipFree(w.dev_table);
-        hipHostFree(w.host_work);
-        hipFree(w.dev_work);
+        (void)hipStreamSynchronize(w.st);
+        (void)hipStreamDestroy(w.st);
+        (void)hipHostFree(w.host_table);
+        (void)hipFree(w.dev_table);
+        (void)hipHostFree(w.host_work);
+        (void)hipFree(w.dev_work);
     }
     for (auto &kv : s->live) delete kv.second;
-    hipFree(s->arena_mem);
+    (void)hipFree(s->arena_mem);
     delete s;
     return FW_OK;
 }

@@ -37,11 +37,11 @@ struct TuneScratch {
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     ~TuneScratch() {
-        if (st) hipStreamSynchronize(st);
-        if (mat) hipFree(mat);
-        if (e0) hipEventDestroy(e0);
-        if (e1) hipEventDestroy(e1);
-        if (st) hipStreamDestroy(st);
+        if (st) (void)hipStreamSynchronize(st);
+        if (mat) (void)hipFree(mat);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (st) (void)hipStreamDestroy(st);
     }
 };
 
@@ -87,7 +87,7 @@ extern "C" int fw_autotune(int dtype, const int64_t *lo, const int64_t *hi, int 
         }
         const size_t per_set = offs[(size_t)count];
         const size_t total = per_set * (pred ? 2 : 1);  // distances [, predecessors]
-        if (sc.mat) hipFree(sc.mat);
+        if (sc.mat) (void)hipFree(sc.mat);
         sc.mat = nullptr;
         if ((e = hipMalloc(&sc.mat, total)) != hipSuccess) return status_of(e);
         if ((e = hipMemsetAsync(sc.mat, 0, total, sc.st)) != hipSuccess) return status_of(e);
