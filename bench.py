@@ -132,7 +132,9 @@ def log(msg):
 PROBE_FORMS = {0: "v_add_f32", 1: "fp32 min-plus (2 v_add_f32 + v_minimum3_f32)",
                2: "int32 min-plus (2 v_add_u32 + v_min3_i32)", 3: "v_fma_f32",
                4: "v_and_or_b32", 5: "v_add_u32", 6: "v_min3_i32", 7: "v_minimum3_f32",
-               8: "2 v_add_u32 + v_minimum3_f32"}
+               8: "2 v_add_u32 + v_minimum3_f32",
+               9: "fp32 max-min (2 v_minimum3_f32 as two-input minima + v_maximum3_f32)",
+               10: "v_min_f32", 11: "v_min_i32"}
 
 
 def bench_valu_probe(torch, dev):
@@ -168,6 +170,7 @@ def bench_valu_probe(torch, dev):
     mix = out["forms"][PROBE_FORMS[1]]["lane_instr_per_s"]
     out["fp32_minplus_update_ceiling"] = mix / MIX_INSTR_PER_UPDATE
     out["int32_minplus_update_ceiling"] = out["forms"][PROBE_FORMS[2]]["lane_instr_per_s"] / 1.5
+    out["fp32_maxmin_update_ceiling"] = out["forms"][PROBE_FORMS[9]]["lane_instr_per_s"] / 1.5
     return out
 
 
@@ -905,6 +908,9 @@ def main():
     if not args.no_maxmin:
         log("widest paths (max, min) n=16384")
         maxmin = bench_maxmin(torch, fw, W, dev)
+        if probe is not None:  # the issue-rate ceiling of its own instruction mix
+            maxmin["mix_ceiling_updates_per_s"] = probe["fp32_maxmin_update_ceiling"]
+            maxmin["of_mix_ceiling"] = maxmin["updates_per_s"] / probe["fp32_maxmin_update_ceiling"]
 
     closure = None
     if not args.no_closure:

@@ -17,7 +17,13 @@
 //   form 7  v_minimum3_f32 alone                   (c = minimum(c, a, b))
 //   form 8  2 v_add_u32 + 1 v_minimum3_f32         (form 2 with the fp32
 //                                                   minimum on the sums' bits)
-// Instructions per step and thread: 192 (forms 1, 2, 8), else 64.
+// and the max-min semiring's loop with the two-input minima it is made of:
+//   form 9  fp32 max-min, two k-steps fused        (2 two-input IEEE-2019
+//                                                   minima + 1 v_maximum3_f32)
+//   form 10 v_min_f32 alone                        (c = min(c, a), no operand
+//                                                   quieting)
+//   form 11 v_min_i32 alone                        (c = min(c, a))
+// Instructions per step and thread: 192 (forms 1, 2, 8, 9), else 64.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -70,6 +76,18 @@ __global__ void __launch_bounds__(256) valu_kernel(const float *__restrict__ src
                 } else if constexpr (FORM == 7) {
                     c[i][j] = __builtin_elementwise_minimum(
                         __builtin_elementwise_minimum(c[i][j], a[i]), b[j]);
+                } else if constexpr (FORM == 9) {
+                    c[i][j] = __builtin_elementwise_maximum(
+                        __builtin_elementwise_maximum(
+                            c[i][j], __builtin_elementwise_minimum(a[i], b[j])),
+                        __builtin_elementwise_minimum(a1[i], b1[j]));
+                } else if constexpr (FORM == 10) {
+                    // written out: in IEEE mode the compiler would quiet both
+                    // operands first (v_max_f32 x, x, x); registers only
+                    asm("v_min_f32 %0, %1, %0" : "+v"(c[i][j]) : "v"(a[i]));
+                } else if constexpr (FORM == 11) {
+                    const int x = __float_as_int(c[i][j]), y = __float_as_int(a[i]);
+                    c[i][j] = __int_as_float(x < y ? x : y);
                 } else if constexpr (FORM == 8) {
                     const int s0 = __float_as_int(a[i]) + __float_as_int(b[j]);
                     const int s1 = __float_as_int(a1[i]) + __float_as_int(b1[j]);
@@ -97,7 +115,7 @@ extern "C" {
 
 // Instructions per loop step and thread of each form (the counts above).
 int fw_probe_valu_instr_per_step(int form) {
-    return (form == 1 || form == 2 || form == 8) ? 192 : 64;
+    return (form == 1 || form == 2 || form == 8 || form == 9) ? 192 : 64;
 }
 
 // Runs `form` on `blocks` x 256 threads for `iters` steps on `stream` after
@@ -105,7 +123,7 @@ int fw_probe_valu_instr_per_step(int form) {
 // floats of device memory; dst: blocks * 256 * 64 floats.  0 on success.
 int fw_probe_valu(int form, int blocks, int iters, const float *src, float *dst, void *stream,
                   float *ms) {
-    if (form < 0 || form > 8 || blocks <= 0 || iters <= 0 || !src || !dst || !ms) return 1;
+    if (form < 0 || form > 11 || blocks <= 0 || iters <= 0 || !src || !dst || !ms) return 1;
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return 2;
@@ -120,7 +138,10 @@ int fw_probe_valu(int form, int blocks, int iters, const float *src, float *dst,
         case 5: valu_kernel<5><<<blocks, 256, 0, st>>>(src, dst, n); break;
         case 6: valu_kernel<6><<<blocks, 256, 0, st>>>(src, dst, n); break;
         case 7: valu_kernel<7><<<blocks, 256, 0, st>>>(src, dst, n); break;
-        default: valu_kernel<8><<<blocks, 256, 0, st>>>(src, dst, n); break;
+        case 8: valu_kernel<8><<<blocks, 256, 0, st>>>(src, dst, n); break;
+        case 9: valu_kernel<9><<<blocks, 256, 0, st>>>(src, dst, n); break;
+        case 10: valu_kernel<10><<<blocks, 256, 0, st>>>(src, dst, n); break;
+        default: valu_kernel<11><<<blocks, 256, 0, st>>>(src, dst, n); break;
         }
     };
     go(iters);
