@@ -517,8 +517,10 @@ def bench_negative(torch, fw, gen, dev, reps=3):
 def bench_pred_f32(torch, fw, gen, dev, reps=3):
     """n=8192 fp32 (edge prob 0.3, integer weights [1,1000]) with predecessors:
     the keyed sweep (integer weights), and for contrast the same graph with
-    every weight raised by 0.5, which takes the fp32 compare form.  Each timed
-    solve on its own pre-filled copy; rows checked against the oracle."""
+    every weight raised by 0.5, which the keyed sweep hands to the fp32
+    canonical path (the distances at tile 64, then every last hop from its
+    definition).  Each timed solve on its own pre-filled copy; rows checked
+    against the oracle."""
     import numpy as np
     import oracle
     n = 8192
@@ -529,11 +531,11 @@ def bench_pred_f32(torch, fw, gen, dev, reps=3):
     P = torch.empty((n, n), dtype=torch.int32, device=dev)
     srcs = np.array([5, 4097, 8000])
     out = {"workload": "single graph n=8192 fp32, edge prob 0.3, integer weights [1,1000], +INF "
-                       "absent, with predecessors; compare form: the same graph + 0.5 per weight",
+                       "absent, with predecessors; canonical path: the same graph + 0.5 per weight",
            "n": n, "tile": {"keyed_sweep": fw.plan_tile(torch.float32, n),
-                            "compare_form": fw.plan_tile(torch.float32, n, pred=True)}}
+                            "canonical_path_distances": 64}}
     ok = True
-    for mode, w, r in (("keyed", W, reps), ("compare_form", Wh, 1)):
+    for mode, w, r in (("keyed", W, reps), ("canonical_path", Wh, reps)):
         pristine = torch.from_numpy(w).to(dev)
         bufs = [torch.empty_like(pristine) for _ in range(r)]
         bufs[0].copy_(pristine)
@@ -933,10 +935,10 @@ def main():
 
     pred_f32 = None
     if not args.no_pred_f32:
-        log("fp32 n=8192 with predecessors (keyed, and the compare form)")
+        log("fp32 n=8192 with predecessors (keyed, and the canonical path)")
         pred_f32 = bench_pred_f32(torch, fw, gen, dev)
         log(f"fp32 predecessors: {pred_f32['keyed']['ms']:.1f} ms keyed, "
-            f"{pred_f32['compare_form']['ms']:.1f} ms compare form")
+            f"{pred_f32['canonical_path']['ms']:.1f} ms canonical path")
 
     batched = None
     if not args.no_batched:

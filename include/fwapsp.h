@@ -98,8 +98,9 @@ int fw_apsp_i32(int32_t *d, int64_t n, int64_t ld, void *stream);
  *              computes distances only; this reading is unique, so it is the
  *              same for every tile size and batch composition.)  It is computed
  *              during the sweep by a lexicographic minimum over (distance, last
- *              hop) and requires, besides the distance preconditions, that the
- *              graph has no zero-weight cycle.  Outside the problem statement
+ *              hop) -- fp32 inputs that are not keys (below): after it, from
+ *              the final distances -- and requires, besides the distance
+ *              preconditions, that the graph has no zero-weight cycle.  Outside the problem statement
  *              (a negative cycle), pred[i*ld_pred+i] keeps the last hop of the
  *              closed walk that made d_ii negative (see
  *              fw_negative_cycle_find); the other entries are then as
@@ -107,15 +108,20 @@ int fw_apsp_i32(int32_t *d, int64_t n, int64_t ld, void *stream);
  * With pred and 2 <= n <= 16383 the (distance, last hop) pairs are first
  * swept as 32-bit integer keys (distance * 2^14 + last hop) held in `pred`,
  * at the cost of the int32 distances-only sweep; this takes 16 + 8n + 512n
- * bytes (rounded to 256) of stream-ordered device memory (hipMallocAsync on
- * `stream`, freed on it).  When an entry of d is not an integer with
- * |w| < 2^14 (fp32: also a fraction), some distance met during that sweep
- * has |d| >= 2^14, or a diagonal entry ends negative, the pair form already
- * queued behind it (64-bit keys for int32, compares for fp32; each launch
- * gated on a device flag) solves again from the untouched d.  Within that
- * range fp32 arithmetic on integers is exact, so the results are the same in
- * every case and the choice is invisible except in time (fw_pred_fallbacks
- * counts the second sweeps).
+ * bytes (rounded to 256), and for fp32 another 4 n min(n rounded up to 64,
+ * 1024) bytes, of stream-ordered device memory (hipMallocAsync on `stream`,
+ * freed on it).  When an entry of d is not an integer with |w| < 2^14
+ * (fp32: also a fraction), some distance met during that sweep has
+ * |d| >= 2^14, or a diagonal entry ends negative, a second form already
+ * queued behind it (each launch gated on a device flag) solves again from
+ * the untouched d: int32, the pair form with 64-bit keys; fp32, the
+ * canonical path -- the distances by the distances-only sweep, then every
+ * last hop from the definition above (the smallest q != j with
+ * (q == i ? 0 : d_iq) + w_qj == d_ij in fp32, over the original weights,
+ * held in `pred` meanwhile) -- or, after a negative diagonal, the compare
+ * form, whose pred leads a walk to the cycle.  Within the precondition the
+ * results are the same in every case and the choice is invisible except in
+ * time (fw_pred_fallbacks counts the second forms).
  * Errors: as fw_apsp, plus FW_ERR_INVALID for a bad dtype or, with pred
  * non-NULL, ld_pred < n or n*ld_pred overflowing int64.
  */
@@ -559,9 +565,10 @@ int fw_profile_updates(double *updates, int cap);
 
 /*
  * fw_pred_fallbacks -- how many solves with predecessors on the current
- * device have run their pair-form sweep because the 32-bit keyed one gave up
- * (see fw_apsp_pred), since the library was loaded.  Synchronises the device;
- * -1 when the count cannot be read.
+ * device have run their second form (pair-form sweep, or fp32 canonical
+ * path) because the 32-bit keyed one gave up (see fw_apsp_pred), since the
+ * library was loaded.  Synchronises the device; -1 when the count cannot be
+ * read.
  */
 int64_t fw_pred_fallbacks(void);
 

@@ -237,24 +237,55 @@ int enqueue_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t 
     return FW_OK;
 }
 
+// The fp32 canonical path behind a keyed sweep (fw_internal.h), every launch
+// gated on scratch[3]: the weights saved in P, the distances by the
+// distances-only sweep at tile 64 (the register-staged tiles take a gate),
+// then P strip by strip from the distances and the saved weights.
+int enqueue_canon(float *d, int n, int64_t ld, int32_t *pred, int64_t ldp, hipStream_t st,
+                  bool capturing, int32_t *scratch) {
+    const int32_t *gate = scratch + 3;
+    auto run = [&](auto &&launch) -> hipError_t {
+        if (capturing) return launch();
+        return timed(kPredFallback, 0.0, st, launch);
+    };
+    hipError_t e = run([&] { return launch_canon_gate(scratch, st); });
+    if (e == hipSuccess) e = run([&] { return launch_canon_save(d, pred, n, ld, ldp, gate, st); });
+    if (e != hipSuccess) return status_of(e);
+    int s = enqueue_solve(d, FW_F32, n, ld, nullptr, 0, 64, st, capturing, kMinPlus, nullptr, gate);
+    if (s != FW_OK) return s;
+    float *strip = reinterpret_cast<float *>(scratch + key_scratch_words(n));
+    const int w = canon_strip_cols(n);
+    for (int j0 = 0; j0 < n && e == hipSuccess; j0 += w) {
+        const int wc = std::min(w, n - j0);
+        e = run([&] { return launch_canon_strip(pred, n, ldp, j0, wc, strip, gate, st); });
+        if (e == hipSuccess)
+            e = run([&] {
+                return launch_canon_pred(d, n, ld, strip, j0, wc, pred, ldp, gate, st);
+            });
+    }
+    return status_of(e);
+}
+
 // A solve with predecessors as a keyed sweep (fw_internal.h): the pairs
 // packed into 32-bit keys in the predecessor matrix, the distances-only
 // schedule and int32 arithmetic over them with tile `key_tile`, the keys
 // unpacked into d (int32 or fp32) and P.  If an entry is not an integer of
 // the key range, a real key leaves its range or a diagonal entry ends
-// negative, the unpack leaves d untouched and the pair-form sweep queued
-// behind it (tile `tile`, every launch gated on the flag) solves from the
-// original d; the results are the same either way.  Scratch: `scratch` (a
-// solve plan's), else stream-ordered memory of this call.  Returns
-// FW_ERR_UNSUPPORTED, nothing enqueued, when no scratch can be had (the
-// caller then runs the pair-form sweep).
+// negative, the unpack leaves d untouched and a form queued behind it, gated
+// on the device, solves from the original d; the results are the same either
+// way.  int32: the pair-form sweep (tile `tile`, gated on the flag).  fp32:
+// the canonical path (enqueue_canon), or, where a diagonal went negative,
+// the pair-form sweep (gated on that word), whose predecessors lead a walk to
+// the cycle.  Scratch: `scratch` (a solve plan's), else stream-ordered memory
+// of this call.  Returns FW_ERR_UNSUPPORTED, nothing enqueued, when no
+// scratch can be had (the caller then runs the pair-form sweep).
 int enqueue_solve_keyed(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp,
                         int tile, int key_tile, hipStream_t st, bool capturing, int32_t *scratch) {
     bool own = false;
     if (!scratch) {
         if (capturing) return FW_ERR_UNSUPPORTED;
         void *mem = nullptr;
-        if (hipMallocAsync(&mem, (size_t)key_scratch_words(n) * 4, st) != hipSuccess) {
+        if (hipMallocAsync(&mem, (size_t)key_scratch_words_for(dtype, n) * 4, st) != hipSuccess) {
             (void)hipGetLastError();
             return FW_ERR_UNSUPPORTED;
         }
@@ -279,9 +310,11 @@ int enqueue_solve_keyed(void *d, int dtype, int n, int64_t ld, int32_t *pred, in
         });
         if (e != hipSuccess) s = status_of(e);
     }
+    if (s == FW_OK && dtype == FW_F32)
+        s = enqueue_canon(static_cast<float *>(d), n, ld, pred, ldp, st, capturing, scratch);
     if (s == FW_OK)
         s = enqueue_solve(d, dtype, n, ld, pred, ldp, tile, st, capturing, kMinPlus, nullptr,
-                          scratch);
+                          dtype == FW_F32 ? scratch + 2 : scratch);
     if (own) (void)hipFreeAsync(scratch, st);
     return s;
 }
@@ -664,7 +697,7 @@ int fw_solve_plan_create(void *d, int dtype, int64_t n, int64_t ld, int32_t *pre
     }
     if (keyed_solve(pred, (int)n, kMinPlus)) {
         void *mem = nullptr;
-        hipError_t e = hipMalloc(&mem, (size_t)key_scratch_words(n) * 4);
+        hipError_t e = hipMalloc(&mem, (size_t)key_scratch_words_for(dtype, n) * 4);
         if (e != hipSuccess) {
             delete pl;
             return status_of(e);

@@ -28,14 +28,26 @@ constexpr int32_t kKeyReal = 1 << 28;
 constexpr int32_t kKeyLow = -kKeyReal + (1 << kKeyBits);
 constexpr int32_t kKeyInfFloor = 1 << 29;
 constexpr int kKeyMaxN = kKeyHop;
-// Scratch of one keyed solve, int32 words: [0] the fallback flag (set when a
-// real key left its range or a diagonal went negative), [1] set when some
-// pair is unreachable, [2..3] unused, then the row minima and the column
-// minima of the finite distances (n each); from the 64-word (256-byte)
-// boundary after them, the current stage's column panel with the hop fields
-// cleared (n rows of 128), the A operand of the 128-wide keyed bulk.
+// Scratch of one keyed solve, int32 words: [0] the fallback flag (set when an
+// entry is not a key, a real key left its range or a diagonal went
+// negative), [1] set when some pair is unreachable, [2] set when a diagonal
+// went negative, [3] the gate of the fp32 canonical path (see
+// launch_canon_gate), then the row minima and the column minima of the finite
+// distances (n each); from the 64-word (256-byte) boundary after them, the
+// current stage's column panel with the hop fields cleared (n rows of 128),
+// the A operand of the 128-wide keyed bulk.  fp32 solves add, after that,
+// one strip of the original weights (n rows of canon_strip_cols(n)) for the
+// canonical path.
 constexpr int64_t key_acol_offset(int64_t n) { return (4 + 2 * n + 63) / 64 * 64; }
 constexpr int64_t key_scratch_words(int64_t n) { return key_acol_offset(n) + 128 * n; }
+constexpr int kCanonStripMax = 1024;
+constexpr int canon_strip_cols(int64_t n) {
+    return (int)((n + 63) / 64 * 64 < kCanonStripMax ? (n + 63) / 64 * 64 : kCanonStripMax);
+}
+// dtype: 0 fp32, 1 int32
+constexpr int64_t key_scratch_words_for(int dtype, int64_t n) {
+    return key_scratch_words(n) + (dtype == 0 ? n * canon_strip_cols(n) : 0);
+}
 
 enum PhaseKind {
     kDiag = 0,
@@ -64,8 +76,9 @@ enum Semiring { kMinPlus = 0, kMaxMin = 1, kKey = 2 };
 // and the (optional) predecessor matrix; `b` is the k-block index, `nb` the
 // number of tile rows.  `flag` (kKey only, device int32): set to 1 when a
 // real key leaves its range.  `gate` (device int32 or NULL): when non-NULL
-// the launch does nothing unless *gate != 0 at the time it runs.  Returns
-// hipSuccess or the launch error.
+// the launch does nothing unless *gate != 0 at the time it runs; min-plus
+// only, and without predecessors only at tiles 64 and 32 (the 128-wide
+// copy path takes no gate).  Returns hipSuccess or the launch error.
 hipError_t launch_diag(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
                        int64_t ldp, int b, hipStream_t st, int32_t *flag = nullptr,
                        const int32_t *gate = nullptr);
@@ -94,8 +107,28 @@ hipError_t launch_key_prepare(int dtype, const void *d, int32_t *keys, int n, in
                               int64_t ldk, int32_t *scratch, hipStream_t st);
 hipError_t launch_key_finish(int dtype, void *d, int32_t *keys, int n, int64_t ld, int64_t ldk,
                              int32_t *scratch, hipStream_t st);
-// Number of gated 64-bit predecessor sweeps that ran on the current device
-// (synchronises the device).
+// The fp32 canonical path, for a keyed solve whose input was not keys (an
+// entry not an integer of the key range, or a real key out of range) and
+// whose diagonals stayed non-negative: the distances by the distances-only
+// sweep, then p_ij = the smallest q != j with (q == i ? 0 : d_iq) + w_qj ==
+// d_ij in fp32 arithmetic (-1 for i == j, for unreachable pairs and when no q
+// matches), the oracle's definition of the canonical last hop, over the
+// original weights.  The predecessor matrix holds the weights meanwhile.
+//   canon_gate:  scratch[3] = scratch[0] && !scratch[2] (the gate of the rest).
+//   canon_save:  P = the bits of d (the weights); counts one fallback.
+//   canon_strip: strip = columns [j0, j0 + w) of those weights (n x w, ld w).
+//   canon_pred:  columns [j0, j0 + w) of P from the final d and the strip.
+// Each launch but the first does nothing unless *gate != 0.
+hipError_t launch_canon_gate(int32_t *scratch, hipStream_t st);
+hipError_t launch_canon_save(const float *d, int32_t *p, int n, int64_t ld, int64_t ldp,
+                             const int32_t *gate, hipStream_t st);
+hipError_t launch_canon_strip(const int32_t *p, int n, int64_t ldp, int j0, int w, float *strip,
+                              const int32_t *gate, hipStream_t st);
+hipError_t launch_canon_pred(const float *d, int n, int64_t ld, const float *strip, int j0, int w,
+                             int32_t *p, int64_t ldp, const int32_t *gate, hipStream_t st);
+// Number of gated predecessor fallbacks (64-bit or compare-form sweeps, and
+// fp32 canonical paths) that ran on the current device (synchronises the
+// device).
 int64_t pred_fallbacks();
 // Vertices with d_ii < 0, ascending, into list (NULL: not written) and their
 // number into *count (device memory).

@@ -224,6 +224,108 @@ pred_fix_kernel(const T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t
 }
 
 // ---------------------------------------------------------------------------
+// The fp32 canonical path (fw_internal.h): the canonical last hops from the
+// final distances and the original weights, as the oracle defines them.
+// ---------------------------------------------------------------------------
+__global__ void canon_gate_kernel(int32_t *__restrict__ flag) {
+    if (threadIdx.x == 0) flag[3] = (flag[0] != 0 && flag[2] == 0) ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(256)
+canon_save_kernel(const float *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld,
+                  int64_t ldp, const int32_t *gate) {
+    if (gated_off(gate)) return;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+        atomicAdd(&g_pred_fallbacks, 1ull);
+    for (int i = blockIdx.y; i < n; i += gridDim.y)
+        for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256)
+            P[(int64_t)i * ldp + j] = __float_as_int(d[(int64_t)i * ld + j]);
+}
+
+__global__ void __launch_bounds__(256)
+canon_strip_kernel(const int32_t *__restrict__ P, int n, int64_t ldp, int j0, int w,
+                   float *__restrict__ strip, const int32_t *gate) {
+    if (gated_off(gate)) return;
+    for (int q = blockIdx.y; q < n; q += gridDim.y)
+        for (int c = blockIdx.x * 256 + threadIdx.x; c < w; c += gridDim.x * 256)
+            strip[(int64_t)q * w + c] = __int_as_float(P[(int64_t)q * ldp + j0 + c]);
+}
+
+// One 64 x 64 tile of P (rows i0.., strip columns c0..; global column j0 +
+// c) per workgroup, 4 x 4 cells per thread.  The candidates q run downward in
+// 32-deep slices staged in LDS, and a cell keeps the last q whose sum equals
+// its distance: the smallest.  A cell whose pair has no last hop (i == j,
+// or d_ij = +INF) compares against NaN, which equals nothing.  The slice of
+// d is staged with 0 at (i, i) (a path from i starts with the empty path)
+// and the strip with +INF at (j, j) (q = j is no last hop of j); rows and
+// columns beyond the matrix stage +INF, whose sums match no finite
+// distance.  No order of the sums matters: each is one fp32 add, compared
+// exactly.
+constexpr int kCanonTile = 64, kCanonDepth = 32;
+
+__global__ void __launch_bounds__(256)
+canon_pred_kernel(const float *__restrict__ d, int n, int64_t ld, const float *__restrict__ strip,
+                  int j0, int w, int32_t *__restrict__ P, int64_t ldp, const int32_t *gate) {
+    if (gated_off(gate)) return;
+    constexpr int S = kCanonTile, KD = kCanonDepth;
+    __shared__ __align__(16) float As[KD][S + 4];  // As[q][r] = d[i0 + r][q0 + q]
+    __shared__ __align__(16) float Bs[KD][S + 4];  // Bs[q][c] = w[q0 + q][c0 + c]
+    const int i0 = blockIdx.y * S, c0 = blockIdx.x * S;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const float kNaN = __builtin_nanf("");
+    float t[4][4];
+    int32_t best[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = i0 + ty * 4 + r, cc = c0 + tx * 4 + c, j = j0 + cc;
+            float v = kNaN;
+            if (i < n && cc < w && i != j) {
+                v = d[(int64_t)i * ld + j];
+                if (v == __builtin_inff()) v = kNaN;
+            }
+            t[r][c] = v;
+            best[r][c] = -1;
+        }
+    for (int q0 = (n - 1) / KD * KD; q0 >= 0; q0 -= KD) {
+        __syncthreads();  // the previous slice's reads are done
+        for (int e = threadIdx.x; e < KD * S; e += 256) {
+            const int q = e % KD, r = e / KD, gi = i0 + r, gq = q0 + q;
+            float v = __builtin_inff();
+            if (gi < n && gq < n) v = gi == gq ? 0.0f : d[(int64_t)gi * ld + gq];
+            As[q][r] = v;
+        }
+        for (int e = threadIdx.x; e < KD * S; e += 256) {
+            const int c = e % S, q = e / S, gq = q0 + q, cc = c0 + c;
+            float v = __builtin_inff();
+            if (gq < n && cc < w && gq != j0 + cc) v = strip[(int64_t)gq * w + cc];
+            Bs[q][c] = v;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int q = KD - 1; q >= 0; --q) {
+            const float4 a = *reinterpret_cast<const float4 *>(&As[q][ty * 4]);
+            const float4 b = *reinterpret_cast<const float4 *>(&Bs[q][tx * 4]);
+            const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+            const int32_t gq = q0 + q;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    best[r][c] = av[r] + bv[c] == t[r][c] ? gq : best[r][c];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = i0 + ty * 4 + r, cc = c0 + tx * 4 + c;
+            if (i < n && cc < w) P[(int64_t)i * ldp + j0 + cc] = best[r][c];
+        }
+}
+
+// ---------------------------------------------------------------------------
 // The keyed int32 predecessor solve (keys as in fw_internal.h).
 // ---------------------------------------------------------------------------
 // Zero the head of the scratch: the flags, and the row and column minima,
@@ -268,7 +370,8 @@ key_pack_kernel(const T *__restrict__ d, int32_t *__restrict__ keys, int n, int6
 }
 
 // A negative diagonal entry after the keyed sweep (a negative cycle: the
-// 64-bit sweep then gives its documented result) raises the flag.
+// pair-form sweep then gives its documented result) raises the flag, and
+// the negative-diagonal word beside it.
 __global__ void __launch_bounds__(256)
 key_diag_kernel(const int32_t *__restrict__ keys, int n, int64_t ldk, int32_t *__restrict__ flag) {
     bool bad = false;
@@ -276,7 +379,10 @@ key_diag_kernel(const int32_t *__restrict__ keys, int n, int64_t ldk, int32_t *_
         const int32_t key = keys[(int64_t)i * ldk + i];
         bad |= key < kKeyInfFloor && (key >> kKeyBits) < 0;
     }
-    if (bad) *flag = 1;
+    if (bad) {
+        flag[0] = 1;
+        flag[2] = 1;
+    }
 }
 
 __device__ __forceinline__ int32_t wave_min(int32_t v) {
@@ -489,8 +595,10 @@ template <typename T, class A, bool ALLOW_PRED>
 hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b,
                          int nb, int mode, bool close_next, hipStream_t st, int32_t *flag,
                          const int32_t *gate) {
-    // only the predecessor forms take a gate (the 64-bit sweep behind a keyed one)
-    if (gate && !p) return hipErrorInvalidValue;
+    // gates: the predecessor forms (the pair-form sweep behind a keyed one),
+    // and without predecessors the register-staged tiles (the distances of
+    // the fp32 canonical path)
+    if (gate && !p && tile > 64) return hipErrorInvalidValue;
     const int64_t m = nb - 1;
     const int64_t grid = mode == 0 ? 2 * m : m * m;
     if (grid <= 0) return close_next ? hipErrorInvalidValue : hipSuccess;
@@ -519,9 +627,9 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
     }
     if (tile == 64)
         return vec ? tile_t<T, true, false, A>(tile, d, p, n, ld, ldp, b, nb, mode,
-                                               (unsigned)grid, st, c, flag, nullptr)
+                                               (unsigned)grid, st, c, flag, gate)
                    : tile_t<T, false, false, A>(tile, d, p, n, ld, ldp, b, nb, mode,
-                                                (unsigned)grid, st, c, flag, nullptr);
+                                                (unsigned)grid, st, c, flag, gate);
 #if FW_PANEL_STRIPS
     if (mode == 0 && tile == 128) {
         if (4 * grid > 0x7fffffffLL) return hipErrorInvalidValue;
@@ -554,15 +662,16 @@ hipError_t tile_dispatch(int tile, T *d, int32_t *p, int n, int64_t ld, int64_t 
     }
     if (close_next) return hipErrorInvalidValue;  // every closing form is handled above
     return vec ? tile_t<T, true, false, A>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid, st,
-                                           0, flag, nullptr)
+                                           0, flag, gate)
                : tile_t<T, false, false, A>(tile, d, p, n, ld, ldp, b, nb, mode, (unsigned)grid,
-                                            st, 0, flag, nullptr);
+                                            st, 0, flag, gate);
 }
 
 template <typename T>
 hipError_t tile_any(int sr, int tile, T *d, int32_t *p, int n, int64_t ld, int64_t ldp, int b,
                     int nb, int mode, bool close_next, hipStream_t st, int32_t *flag,
                     const int32_t *gate) {
+    if (gate && sr != kMinPlus) return hipErrorInvalidValue;
     if (sr == kMaxMin)
         return tile_dispatch<T, ArMaxMin<T>, false>(tile, d, p, n, ld, ldp, b, nb, mode,
                                                      close_next, st, nullptr, gate);
@@ -582,7 +691,7 @@ hipError_t tile_any(int sr, int tile, T *d, int32_t *p, int n, int64_t ld, int64
 
 hipError_t launch_diag(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
                        int64_t ldp, int b, hipStream_t st, int32_t *flag, const int32_t *gate) {
-    if (gate && !p) return hipErrorInvalidValue;
+    if (gate && (sr != kMinPlus || (!p && tile > 64))) return hipErrorInvalidValue;
     if (sr == kMaxMin) {
         if (p) return hipErrorInvalidValue;
         if (dtype == 0)
@@ -600,11 +709,11 @@ hipError_t launch_diag(int dtype, int sr, int tile, void *d, int32_t *p, int n, 
         return p ? diag_t<float, true, Ar<float>>(tile, (float *)d, p, n, ld, ldp, b, st, nullptr,
                                                   gate)
                  : diag_t<float, false, Ar<float>>(tile, (float *)d, p, n, ld, ldp, b, st,
-                                                   nullptr, nullptr);
+                                                   nullptr, gate);
     return p ? diag_t<int32_t, true, Ar<int32_t>>(tile, (int32_t *)d, p, n, ld, ldp, b, st,
                                                   nullptr, gate)
              : diag_t<int32_t, false, Ar<int32_t>>(tile, (int32_t *)d, p, n, ld, ldp, b, st,
-                                                   nullptr, nullptr);
+                                                   nullptr, gate);
 }
 
 hipError_t launch_panels(int dtype, int sr, int tile, void *d, int32_t *p, int n, int64_t ld,
@@ -689,6 +798,35 @@ hipError_t launch_key_finish(int dtype, void *d, int32_t *keys, int n, int64_t l
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     key_inf_kernel<<<elementwise_grid(n), 256, 0, st>>>((int32_t *)d, n, ld, scratch);
+    return hipGetLastError();
+}
+
+hipError_t launch_canon_gate(int32_t *scratch, hipStream_t st) {
+    canon_gate_kernel<<<1, 64, 0, st>>>(scratch);
+    return hipGetLastError();
+}
+
+hipError_t launch_canon_save(const float *d, int32_t *p, int n, int64_t ld, int64_t ldp,
+                             const int32_t *gate, hipStream_t st) {
+    canon_save_kernel<<<elementwise_grid(n), 256, 0, st>>>(d, p, n, ld, ldp, gate);
+    return hipGetLastError();
+}
+
+hipError_t launch_canon_strip(const int32_t *p, int n, int64_t ldp, int j0, int w, float *strip,
+                              const int32_t *gate, hipStream_t st) {
+    if (n <= 0 || w <= 0 || j0 < 0 || j0 + w > n) return hipErrorInvalidValue;
+    const int gx = (w + 255) / 256, gy = n < 8192 / gx ? n : 8192 / gx;
+    canon_strip_kernel<<<dim3((unsigned)gx, (unsigned)gy), 256, 0, st>>>(p, n, ldp, j0, w, strip,
+                                                                         gate);
+    return hipGetLastError();
+}
+
+hipError_t launch_canon_pred(const float *d, int n, int64_t ld, const float *strip, int j0, int w,
+                             int32_t *p, int64_t ldp, const int32_t *gate, hipStream_t st) {
+    if (n <= 0 || w <= 0 || j0 < 0 || j0 + w > n) return hipErrorInvalidValue;
+    const dim3 g((unsigned)((w + kCanonTile - 1) / kCanonTile),
+                 (unsigned)((n + kCanonTile - 1) / kCanonTile));
+    canon_pred_kernel<<<g, 256, 0, st>>>(d, n, ld, strip, j0, w, p, ldp, gate);
     return hipGetLastError();
 }
 

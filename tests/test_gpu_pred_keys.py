@@ -1,10 +1,11 @@
 """Solves with predecessors: the 32-bit keyed sweep and its fallback.
 
 fw_apsp_pred first sweeps (distance, last hop) pairs packed into 32-bit
-integer keys and falls back to the pair form (64-bit keys for int32, compares
-for fp32; queued behind it, gated on a device flag) when an entry is not an
-integer with |w| < 2^14, a distance met during the sweep has |d| >= 2^14 or a
-diagonal entry ends negative.  Both must give the oracle's d and canonical P
+integer keys and falls back (queued behind it, gated on a device flag) when
+an entry is not an integer with |w| < 2^14, a distance met during the sweep
+has |d| >= 2^14 or a diagonal entry ends negative: int32 to the pair form
+with 64-bit keys; fp32 to the canonical path, or to the compare form after a
+negative diagonal.  Both must give the oracle's d and canonical P
 bit for bit; fw.pred_fallbacks() tells which one ran.
 
 * in-range graphs take the keyed path (no fallback) at every tile;
@@ -19,9 +20,11 @@ bit for bit; fw.pred_fallbacks() tells which one ran.
   canonical reading does not cover (absent and positive diagonal entries);
 * negative cycles fall back; captured solve plans replay both paths;
   a side stream gets the same bits;
-* fp32: integer weights keyed (also n=5000, tile 128), fractional and large
-  weights fall back, unreachable pairs stay +INF, keyed vs compare-form
-  differential, plan replays of both paths.
+* fp32: integer weights keyed (also n=5000, tile 128); fractional and large
+  weights take the canonical path (the distances, then every last hop from
+  its definition over the saved weights), a negative diagonal the compare
+  form; unreachable pairs stay +INF; keyed vs fallback differential, plan
+  replays of both paths.
 """
 import numpy as np
 import pytest
@@ -239,7 +242,7 @@ def test_f32_keyed_path_taken_and_exact(n, tile):
 @pytest.mark.parametrize("what", ["half", "large", "sparse"])
 def test_f32_fallbacks_and_unreachable(what):
     n = 600
-    if what == "half":     # fractional weights: the compare form (exact: multiples of 1/2)
+    if what == "half":     # fractional weights: the canonical path (exact: multiples of 1/2)
         w = gen.dense_graph(n, 0.2, 1, 100, seed=31, dtype=np.float32)
         w[np.isfinite(w)] += 0.5
         np.fill_diagonal(w, 0)
@@ -261,10 +264,31 @@ def test_f32_fallbacks_and_unreachable(what):
     assert np.array_equal(P, oracle.canonical_pred(ref, w))
 
 
+@pytest.mark.parametrize("n,p,tile", [(2, 1.0, None), (37, 0.3, None), (64, 0.3, None),
+                                      (1100, 0.05, 128), (1500, 0.001, None),
+                                      (2100, 0.03, None)])
+def test_f32_canonical_path(n, p, tile):
+    """Fractional weights leave the keyed sweep for the fp32 canonical path:
+    the distances, then each last hop from its definition, in strips of up to
+    1024 columns.  One and several strips, ragged tiles and strips, a
+    2-vertex graph, unreachable pairs (p=0.001), a 128-wide keyed sweep."""
+    w = gen.dense_graph(n, p, 1, 100, seed=900 + n, dtype=np.float32)
+    w[np.isfinite(w)] += 0.25
+    np.fill_diagonal(w, 0)
+    print(f"[pred keys] f32 canonical path n={n} p={p} tile={tile}", flush=True)
+    before = fw.pred_fallbacks()
+    d, P = _solve(w, tile)
+    assert fw.pred_fallbacks() == before + 1
+    ref = oracle.fw(w)
+    if p <= 0.001:
+        assert np.isinf(ref).any()
+    assert np.array_equal(d.view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(P, oracle.canonical_pred(ref, w))
+
+
 def test_f32_nan_entry_leaves_the_keyed_sweep():
     """A NaN is outside the contract, but the keyed sweep's input check must
-    still see it (a NaN is not an integer) and hand the solve to the
-    compare form."""
+    still see it (a NaN is not an integer) and hand the solve on."""
     n = 200
     w = gen.dense_graph(n, 0.2, 1, 100, seed=71, dtype=np.float32)
     w[3, 7] = np.nan
