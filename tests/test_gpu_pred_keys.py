@@ -216,8 +216,8 @@ def test_side_stream_same_bits():
 
 # ---------------------------------------------------------------------------
 # fp32: integer weights with |w| < 2^14 take the same keyed sweep (fp32
-# arithmetic on them is exact); anything else falls back to the fp32 compare
-# form.  Unreachable pairs stay +INF.
+# arithmetic on them is exact); anything else takes the fp32 canonical path,
+# or the compare form after a negative diagonal.  Unreachable pairs stay +INF.
 # ---------------------------------------------------------------------------
 def _f32(g_w):
     w = g_w.astype(np.float32)
@@ -284,6 +284,21 @@ def test_f32_canonical_path(n, p, tile):
         assert np.isinf(ref).any()
     assert np.array_equal(d.view(np.uint32), ref.view(np.uint32))
     assert np.array_equal(P, oracle.canonical_pred(ref, w))
+
+
+def test_f32_canonical_path_side_stream():
+    """The canonical path on a side stream: its scratch, gate and strips are
+    ordered on the caller's stream like the rest of the solve."""
+    n = 1300
+    w = gen.dense_graph(n, 0.05, 1, 100, seed=77, dtype=np.float32)
+    w[np.isfinite(w)] += 0.5
+    np.fill_diagonal(w, 0)
+    print("[pred keys] f32 canonical path, side stream", flush=True)
+    ref_d, ref_P = _solve(w)
+    s = torch.cuda.Stream()
+    d, P = _solve(w, stream=s)
+    assert np.array_equal(d.view(np.uint32), ref_d.view(np.uint32))
+    assert np.array_equal(P, ref_P)
 
 
 def test_f32_nan_entry_leaves_the_keyed_sweep():
