@@ -122,6 +122,12 @@ int fw_apsp_i32(int32_t *d, int64_t n, int64_t ld, void *stream);
  * form, whose pred leads a walk to the cycle.  Within the precondition the
  * results are the same in every case and the choice is invisible except in
  * time (fw_pred_fallbacks counts the second forms).
+ * fp32 with pred and n > 16383 (beyond the keys) takes the canonical path
+ * directly: the weights saved in `pred`, the distances-only sweep, then
+ * every last hop from the definition; after a negative diagonal instead the
+ * compare form from the saved weights (counted by fw_pred_fallbacks).  This
+ * takes 256 + 4 n min(n rounded up to 64, 1024) bytes of stream-ordered
+ * device memory; where it cannot be had, the compare form runs alone.
  * Errors: as fw_apsp, plus FW_ERR_INVALID for a bad dtype or, with pred
  * non-NULL, ld_pred < n or n*ld_pred overflowing int64.
  */

@@ -237,23 +237,16 @@ int enqueue_solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t 
     return FW_OK;
 }
 
-// The fp32 canonical path behind a keyed sweep (fw_internal.h), every launch
-// gated on scratch[3]: the weights saved in P, the distances by the
-// distances-only sweep at tile 64 (the register-staged tiles take a gate),
-// then P strip by strip from the distances and the saved weights.
-int enqueue_canon(float *d, int n, int64_t ld, int32_t *pred, int64_t ldp, hipStream_t st,
-                  bool capturing, int32_t *scratch) {
-    const int32_t *gate = scratch + 3;
+// The last hops of the fp32 canonical path (fw_internal.h), strip by strip
+// from the final distances in d and the weights saved in P, every launch
+// gated on `gate`.
+int enqueue_canon_hops(const float *d, int n, int64_t ld, int32_t *pred, int64_t ldp,
+                       float *strip, const int32_t *gate, hipStream_t st, bool capturing) {
     auto run = [&](auto &&launch) -> hipError_t {
         if (capturing) return launch();
         return timed(kPredFallback, 0.0, st, launch);
     };
-    hipError_t e = run([&] { return launch_canon_gate(scratch, st); });
-    if (e == hipSuccess) e = run([&] { return launch_canon_save(d, pred, n, ld, ldp, gate, st); });
-    if (e != hipSuccess) return status_of(e);
-    int s = enqueue_solve(d, FW_F32, n, ld, nullptr, 0, 64, st, capturing, kMinPlus, nullptr, gate);
-    if (s != FW_OK) return s;
-    float *strip = reinterpret_cast<float *>(scratch + key_scratch_words(n));
+    hipError_t e = hipSuccess;
     const int w = canon_strip_cols(n);
     for (int j0 = 0; j0 < n && e == hipSuccess; j0 += w) {
         const int wc = std::min(w, n - j0);
@@ -264,6 +257,78 @@ int enqueue_canon(float *d, int n, int64_t ld, int32_t *pred, int64_t ldp, hipSt
             });
     }
     return status_of(e);
+}
+
+// The fp32 canonical path behind a keyed sweep, every launch gated on
+// scratch[3]: the weights saved in P, the distances by the distances-only
+// sweep at tile 64 (the register-staged tiles take a gate), then P.
+int enqueue_canon(float *d, int n, int64_t ld, int32_t *pred, int64_t ldp, hipStream_t st,
+                  bool capturing, int32_t *scratch) {
+    const int32_t *gate = scratch + 3;
+    auto run = [&](auto &&launch) -> hipError_t {
+        if (capturing) return launch();
+        return timed(kPredFallback, 0.0, st, launch);
+    };
+    hipError_t e = run([&] { return launch_canon_gate(scratch, false, st); });
+    if (e == hipSuccess) e = run([&] { return launch_canon_save(d, pred, n, ld, ldp, gate, st); });
+    if (e != hipSuccess) return status_of(e);
+    int s = enqueue_solve(d, FW_F32, n, ld, nullptr, 0, 64, st, capturing, kMinPlus, nullptr, gate);
+    if (s != FW_OK) return s;
+    return enqueue_canon_hops(d, n, ld, pred, ldp,
+                              reinterpret_cast<float *>(scratch + key_scratch_words(n)), gate, st,
+                              capturing);
+}
+
+// fp32 with predecessors on graphs beyond the keys' vertices: the canonical
+// path with no keyed sweep before it.  The weights saved in P; the
+// distances-only sweep (tile `tile`, ungated); the negative-diagonal count of
+// the distances into scratch[2]; then, gated on no negative diagonal, P from
+// the distances -- or, gated on one, d restored from P and the compare form
+// (tile `pred_tile`), whose P leads a walk to the cycle.  Scratch as
+// canon_scratch_words: `scratch` (a solve plan's), else stream-ordered memory
+// of this call; FW_ERR_UNSUPPORTED, nothing enqueued, when none can be had.
+int enqueue_canon_direct(float *d, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
+                         int pred_tile, hipStream_t st, bool capturing, int32_t *scratch) {
+    bool own = false;
+    if (!scratch) {
+        if (capturing) return FW_ERR_UNSUPPORTED;
+        void *mem = nullptr;
+        if (hipMallocAsync(&mem, (size_t)canon_scratch_words(n) * 4, st) != hipSuccess) {
+            (void)hipGetLastError();
+            return FW_ERR_UNSUPPORTED;
+        }
+        scratch = (int32_t *)mem;
+        own = true;
+    }
+    auto run = [&](int kind, auto &&launch) -> hipError_t {
+        if (capturing) return launch();
+        return timed(kind, 0.0, st, launch);
+    };
+    int s = FW_OK;
+    hipError_t e = run(kPredFix, [&] { return launch_canon_save(d, pred, n, ld, ldp, nullptr, st); });
+    if (e != hipSuccess) s = status_of(e);
+    if (s == FW_OK) s = enqueue_solve(d, FW_F32, n, ld, nullptr, 0, tile, st, capturing);
+    if (s == FW_OK) {
+        e = run(kPredFix, [&] {
+            const hipError_t e1 = launch_negcycle(FW_F32, d, n, ld, nullptr, scratch + 2, st);
+            return e1 != hipSuccess ? e1 : launch_canon_gate(scratch, true, st);
+        });
+        if (e != hipSuccess) s = status_of(e);
+    }
+    if (s == FW_OK)
+        s = enqueue_canon_hops(d, n, ld, pred, ldp, reinterpret_cast<float *>(scratch + 64),
+                               scratch + 3, st, capturing);
+    if (s == FW_OK) {
+        e = run(kPredFallback, [&] {
+            return launch_canon_restore(d, pred, n, ld, ldp, scratch + 2, st);
+        });
+        if (e != hipSuccess) s = status_of(e);
+    }
+    if (s == FW_OK)
+        s = enqueue_solve(d, FW_F32, n, ld, pred, ldp, pred_tile, st, capturing, kMinPlus,
+                          nullptr, scratch + 2);
+    if (own) (void)hipFreeAsync(scratch, st);
+    return s;
 }
 
 // A solve with predecessors as a keyed sweep (fw_internal.h): the pairs
@@ -323,10 +388,15 @@ bool keyed_solve(const int32_t *pred, int n, int sr) {
     return pred && sr == kMinPlus && n > 1 && n <= kKeyMaxN;
 }
 
+bool canon_direct_solve(int dtype, const int32_t *pred, int n, int sr) {
+    return pred && dtype == FW_F32 && sr == kMinPlus && n > kKeyMaxN;
+}
+
 // Enqueue the whole solve for one graph.  Arguments already valid.  `tile`
 // is the tile of the solve (with predecessors: of the pair-form sweep);
-// `key_tile` that of a keyed sweep (0: `tile`); `key_scratch` a solve plan's
-// scratch for it.
+// `key_tile` that of a keyed sweep, or of the distances of the fp32
+// canonical path beyond the keys' vertices (0: `tile`); `key_scratch` a
+// solve plan's scratch for either.
 int solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int tile,
           hipStream_t st, bool capturing = false, int sr = kMinPlus,
           int32_t *key_scratch = nullptr, int key_tile = 0) {
@@ -346,6 +416,13 @@ int solve(void *d, int dtype, int n, int64_t ld, int32_t *pred, int64_t ldp, int
         if (!tile_supported(key_tile)) return FW_ERR_INVALID;
         const int s = enqueue_solve_keyed(d, dtype, n, ld, pred, ldp, tile, key_tile, st,
                                           capturing, key_scratch);
+        if (s != FW_ERR_UNSUPPORTED) return s;
+    }
+    if (canon_direct_solve(dtype, pred, n, sr)) {
+        if (key_tile == 0) key_tile = tile;
+        if (!tile_supported(key_tile)) return FW_ERR_INVALID;
+        const int s = enqueue_canon_direct(static_cast<float *>(d), n, ld, pred, ldp, key_tile,
+                                           tile, st, capturing, key_scratch);
         if (s != FW_ERR_UNSUPPORTED) return s;
     }
     return enqueue_solve(d, dtype, n, ld, pred, ldp, tile, st, capturing, sr);
@@ -695,9 +772,11 @@ int fw_solve_plan_create(void *d, int dtype, int64_t n, int64_t ld, int32_t *pre
         delete pl;
         return FW_ERR_HIP;
     }
-    if (keyed_solve(pred, (int)n, kMinPlus)) {
+    if (keyed_solve(pred, (int)n, kMinPlus) || canon_direct_solve(dtype, pred, (int)n, kMinPlus)) {
         void *mem = nullptr;
-        hipError_t e = hipMalloc(&mem, (size_t)key_scratch_words_for(dtype, n) * 4);
+        const int64_t words = keyed_solve(pred, (int)n, kMinPlus) ? key_scratch_words_for(dtype, n)
+                                                                  : canon_scratch_words(n);
+        hipError_t e = hipMalloc(&mem, (size_t)words * 4);
         if (e != hipSuccess) {
             delete pl;
             return status_of(e);

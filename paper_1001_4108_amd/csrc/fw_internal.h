@@ -48,6 +48,10 @@ constexpr int canon_strip_cols(int64_t n) {
 constexpr int64_t key_scratch_words_for(int dtype, int64_t n) {
     return key_scratch_words(n) + (dtype == 0 ? n * canon_strip_cols(n) : 0);
 }
+// Scratch of an fp32 canonical path with no keyed sweep before it (graphs
+// beyond the keys' vertices): the four flag words as above (64 words), then
+// the strip.
+constexpr int64_t canon_scratch_words(int64_t n) { return 64 + n * canon_strip_cols(n); }
 
 enum PhaseKind {
     kDiag = 0,
@@ -114,12 +118,18 @@ hipError_t launch_key_finish(int dtype, void *d, int32_t *keys, int n, int64_t l
 // d_ij in fp32 arithmetic (-1 for i == j, for unreachable pairs and when no q
 // matches), the oracle's definition of the canonical last hop, over the
 // original weights.  The predecessor matrix holds the weights meanwhile.
-//   canon_gate:  scratch[3] = scratch[0] && !scratch[2] (the gate of the rest).
-//   canon_save:  P = the bits of d (the weights); counts one fallback.
+//   canon_gate:  scratch[3] = (direct || scratch[0]) && !scratch[2] (the gate
+//                of the rest; direct: no keyed sweep before, scratch[2] the
+//                negative-diagonal count of the distances).
+//   canon_save:  P = the bits of d (the weights); gated, counts one fallback.
 //   canon_strip: strip = columns [j0, j0 + w) of those weights (n x w, ld w).
 //   canon_pred:  columns [j0, j0 + w) of P from the final d and the strip.
-// Each launch but the first does nothing unless *gate != 0.
-hipError_t launch_canon_gate(int32_t *scratch, hipStream_t st);
+//   canon_restore: d = the weights saved in P (before the compare form that
+//                a negative diagonal takes instead).
+// With a gate a launch does nothing unless *gate != 0.
+hipError_t launch_canon_gate(int32_t *scratch, bool direct, hipStream_t st);
+hipError_t launch_canon_restore(float *d, const int32_t *p, int n, int64_t ld, int64_t ldp,
+                                const int32_t *gate, hipStream_t st);
 hipError_t launch_canon_save(const float *d, int32_t *p, int n, int64_t ld, int64_t ldp,
                              const int32_t *gate, hipStream_t st);
 hipError_t launch_canon_strip(const int32_t *p, int n, int64_t ldp, int j0, int w, float *strip,

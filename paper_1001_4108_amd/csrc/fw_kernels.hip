@@ -227,19 +227,29 @@ pred_fix_kernel(const T *__restrict__ d, int32_t *__restrict__ P, int n, int64_t
 // The fp32 canonical path (fw_internal.h): the canonical last hops from the
 // final distances and the original weights, as the oracle defines them.
 // ---------------------------------------------------------------------------
-__global__ void canon_gate_kernel(int32_t *__restrict__ flag) {
-    if (threadIdx.x == 0) flag[3] = (flag[0] != 0 && flag[2] == 0) ? 1 : 0;
+__global__ void canon_gate_kernel(int32_t *__restrict__ flag, int direct) {
+    if (threadIdx.x == 0) flag[3] = ((direct || flag[0] != 0) && flag[2] == 0) ? 1 : 0;
 }
 
+// A gated save (behind a keyed sweep) counts one fallback.
 __global__ void __launch_bounds__(256)
 canon_save_kernel(const float *__restrict__ d, int32_t *__restrict__ P, int n, int64_t ld,
                   int64_t ldp, const int32_t *gate) {
     if (gated_off(gate)) return;
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+    if (gate && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
         atomicAdd(&g_pred_fallbacks, 1ull);
     for (int i = blockIdx.y; i < n; i += gridDim.y)
         for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256)
             P[(int64_t)i * ldp + j] = __float_as_int(d[(int64_t)i * ld + j]);
+}
+
+__global__ void __launch_bounds__(256)
+canon_restore_kernel(float *__restrict__ d, const int32_t *__restrict__ P, int n, int64_t ld,
+                     int64_t ldp, const int32_t *gate) {
+    if (gated_off(gate)) return;
+    for (int i = blockIdx.y; i < n; i += gridDim.y)
+        for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256)
+            d[(int64_t)i * ld + j] = __int_as_float(P[(int64_t)i * ldp + j]);
 }
 
 __global__ void __launch_bounds__(256)
@@ -804,8 +814,14 @@ hipError_t launch_key_finish(int dtype, void *d, int32_t *keys, int n, int64_t l
     return hipGetLastError();
 }
 
-hipError_t launch_canon_gate(int32_t *scratch, hipStream_t st) {
-    canon_gate_kernel<<<1, 64, 0, st>>>(scratch);
+hipError_t launch_canon_gate(int32_t *scratch, bool direct, hipStream_t st) {
+    canon_gate_kernel<<<1, 64, 0, st>>>(scratch, direct ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_canon_restore(float *d, const int32_t *p, int n, int64_t ld, int64_t ldp,
+                                const int32_t *gate, hipStream_t st) {
+    canon_restore_kernel<<<elementwise_grid(n), 256, 0, st>>>(d, p, n, ld, ldp, gate);
     return hipGetLastError();
 }
 

@@ -301,6 +301,53 @@ def test_f32_canonical_path_side_stream():
     assert np.array_equal(P, ref_P)
 
 
+def test_f32_canonical_path_beyond_the_keys():
+    """fp32 with predecessors on 16400 vertices (beyond the keys' 16383): no
+    keyed sweep, the canonical path directly -- the 128-wide distances sweep,
+    then 17 strips of last hops (the last one 16 columns wide).  Sampled rows
+    of d against Dijkstra and of P against the oracle's canonical
+    predecessors; no fallback is counted."""
+    n = 16400
+    w = gen.dense_graph(n, 0.002, 1, 100, seed=4242, dtype=np.float32)
+    srcs = np.array([0, 5, 8191, 16383, 16399])
+    print(f"[pred keys] f32 canonical path beyond the keys n={n}", flush=True)
+    d = torch.from_numpy(w).cuda()
+    P = torch.full((n, n), -77, dtype=torch.int32, device="cuda")
+    before = fw.pred_fallbacks()
+    fw.fw_apsp_pred(d, P)
+    torch.cuda.synchronize()
+    assert fw.pred_fallbacks() == before
+    idx = torch.from_numpy(srcs).cuda()
+    rows, prow = d[idx].cpu().numpy(), P[idx].cpu().numpy()
+    del d, P
+    ref = oracle.dijkstra_rows(w, srcs).astype(np.float32)
+    assert np.isfinite(ref).sum() > len(srcs) * n // 2
+    assert np.array_equal(rows.view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(prow, oracle.canonical_pred(ref, w, rows=srcs))
+
+
+def test_f32_negative_cycle_beyond_the_keys():
+    """Beyond the keys, a negative diagonal after the distances sweep sends
+    the solve to the compare form (from the weights saved in P; counted as a
+    fallback); the planted cycle is listed and recovered."""
+    n = 16390
+    w, cyc = gen.planted_negative_cycle(n, 0.001, 3, seed=97, dtype=np.float32)
+    print(f"[pred keys] f32 negative cycle beyond the keys n={n}", flush=True)
+    d = torch.from_numpy(w).cuda()
+    P = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    before = fw.pred_fallbacks()
+    fw.fw_apsp_pred(d, P)
+    torch.cuda.synchronize()
+    assert fw.pred_fallbacks() == before + 1
+    listed = fw.fw_negative_cycle_vertices(d)
+    assert listed == sorted(cyc.tolist())
+    v = listed[0]
+    Pv = P.cpu().numpy()
+    del d, P
+    found, _ = fw.fw_negative_cycle_find(w, v, Pv)
+    assert sorted(found) == sorted(cyc.tolist())
+
+
 def test_f32_nan_entry_leaves_the_keyed_sweep():
     """A NaN is outside the contract, but the keyed sweep's input check must
     still see it (a NaN is not an integer) and hand the solve on."""
