@@ -286,6 +286,59 @@ def test_f32_canonical_path(n, p, tile):
     assert np.array_equal(P, oracle.canonical_pred(ref, w))
 
 
+def test_f32_canonical_path_negative_weights():
+    """Negative fractional weights (a reweighted graph, every real edge
+    raised by 0.25: cycles stay positive) through the canonical path: the
+    distances and every last hop against the oracle."""
+    n = 700
+    g = gen.reweighted_graph(n, 0.1, 1, 200, -100, 100, seed=808)
+    w = _f32(g.w)
+    off = np.isfinite(w) & ~np.eye(n, dtype=bool)
+    w[off] += 0.25
+    assert (w[off] < 0).any()
+    print("[pred keys] f32 canonical path, negative weights", flush=True)
+    before = fw.pred_fallbacks()
+    d, P = _solve(w)
+    assert fw.pred_fallbacks() == before + 1
+    ref = oracle.fw(w)
+    assert (ref < 0).any()
+    assert np.array_equal(d.view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(P, oracle.canonical_pred(ref, w))
+
+
+def test_f32_canonical_path_beyond_the_keys_plan_replays():
+    """The canonical path beyond the keys captured in a solve plan (its
+    scratch the plan's): two graph replays, each after fresh input, give the
+    eager solve's bits."""
+    n = 16390
+    w = gen.dense_graph(n, 0.002, 1, 100, seed=515, dtype=np.float32)
+    w[np.isfinite(w)] += 0.5
+    np.fill_diagonal(w, 0)
+    print(f"[pred keys] f32 canonical path beyond the keys, plan replays n={n}", flush=True)
+    src = torch.from_numpy(w).cuda()
+    d = src.clone()
+    P = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    fw.fw_apsp_pred(d, P)
+    torch.cuda.synchronize()
+    ref_d, ref_P = d.clone(), P.clone()
+    plan = fw.SolvePlan(d, P)
+    try:
+        for rep in range(2):
+            d.copy_(src)
+            P.fill_(-77)
+            plan.launch("graph")
+            torch.cuda.synchronize()
+            assert torch.equal(d.view(torch.int32), ref_d.view(torch.int32)), rep
+            assert torch.equal(P, ref_P), rep
+    finally:
+        plan.destroy()
+    srcs = np.array([3, 9000])
+    ref = oracle.dijkstra_rows(w, srcs).astype(np.float32)
+    idx = torch.from_numpy(srcs).cuda()
+    assert np.array_equal(ref_d[idx].cpu().numpy().view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(ref_P[idx].cpu().numpy(), oracle.canonical_pred(ref, w, rows=srcs))
+
+
 def test_f32_canonical_path_side_stream():
     """The canonical path on a side stream: its scratch, gate and strips are
     ordered on the caller's stream like the rest of the solve."""
